@@ -1,0 +1,325 @@
+"""Seeded synthetic inputs for the map-making hot path.
+
+This module produces INPUTS only: scan pointing (theta, phi, psi), detector
+focal-plane offsets, random IQU sky maps, white or 1/f noise streams and the
+band-Toeplitz inverse-noise coefficients.  It contains none of the method's
+arithmetic (no pixelisation, no pointing matrix, no noise weighting, no
+solver), so both the HIP path and the FP64 CPU oracle can consume what it
+makes without sharing any of the computation being checked.
+
+The paper names no dataset or benchmark suite; these generators stand in for
+the unstated CMB time-ordered-data workloads of its statement of need
+(section "Statement of Need": experiments producing massive TOD streams).
+
+Random numbers come from one counter-based generator (the SplitMix64 output
+function of Steele, Lea and Flood, "Fast splittable pseudorandom number
+generators", OOPSLA 2014) keyed by (config seed, stream, sub-stream) and
+indexed by a sample counter.  It is written with 64-bit integer tensor ops,
+so it gives the same bits on the CPU and on a GPU, and detector k's data does
+not depend on how many detectors are generated: a detector subset is an exact
+prefix of the full set.
+
+Scan law: a spin axis precessing around a fixed anti-sun axis (opening 45 deg,
+period 90 min) and a boresight spinning around the spin axis (opening 50 deg,
+period 1 min), sampled at 50 Hz, with detectors offset from the boresight by
+up to +-1 deg in two orthogonal directions.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import Optional
+
+import numpy as np
+import torch
+
+_M64 = (1 << 64) - 1
+_GOLDEN = 0x9E3779B97F4A7C15
+_MIX1 = 0xBF58476D1CE4E5B9
+_MIX2 = 0x94D049BB133111EB
+
+
+def _s64(x: int) -> int:
+    """Reinterpret an unsigned 64-bit Python int as a signed int64."""
+    x &= _M64
+    return x - (1 << 64) if x >= (1 << 63) else x
+
+
+def _mix64_int(z: int) -> int:
+    z &= _M64
+    z = ((z ^ (z >> 30)) * _MIX1) & _M64
+    z = ((z ^ (z >> 27)) * _MIX2) & _M64
+    return z ^ (z >> 31)
+
+
+def _srl(z: torch.Tensor, s: int) -> torch.Tensor:
+    """Logical right shift of an int64 tensor (torch's >> is arithmetic)."""
+    return (z >> s) & ((1 << (64 - s)) - 1)
+
+
+def _mix64(z: torch.Tensor) -> torch.Tensor:
+    z = (z ^ _srl(z, 30)) * _s64(_MIX1)
+    z = (z ^ _srl(z, 27)) * _s64(_MIX2)
+    return z ^ _srl(z, 31)
+
+
+STREAM_SCAN = 0
+STREAM_MAP = 1
+SUB_PSI = 0
+SUB_OFFSET = 1
+SUB_NOISE = 2
+SUB_GAIN = 3
+
+
+def stream_key(seed: int, stream: int, sub: int = 0) -> int:
+    """64-bit key of one random stream (unsigned, as a Python int)."""
+    k = _mix64_int(seed * _GOLDEN + 0x632BE59BD9B4E019)
+    k = _mix64_int(k ^ ((stream + 1) * 0xD1B54A32D192ED03))
+    return _mix64_int(k ^ ((sub + 1) * 0x8CB92BA72F3D8DD7))
+
+
+def uniform(key: int, counter: torch.Tensor) -> torch.Tensor:
+    """U[0,1) doubles: output `counter` of the SplitMix64 sequence started at `key`."""
+    z = (counter.to(torch.int64) + 1) * _s64(_GOLDEN) + _s64(key)
+    z = _mix64(z)
+    return _srl(z, 11).to(torch.float64) * (2.0 ** -53)
+
+
+def normal(key: int, counter: torch.Tensor) -> torch.Tensor:
+    """N(0,1) doubles by Box-Muller from the uniform pair (2c, 2c+1)."""
+    c = counter.to(torch.int64)
+    u1 = uniform(key, 2 * c)
+    u2 = uniform(key, 2 * c + 1)
+    return torch.sqrt(-2.0 * torch.log1p(-u1)) * torch.cos(2.0 * math.pi * u2)
+
+
+@dataclass(frozen=True)
+class Workload:
+    """One synthetic map-making workload."""
+    name: str
+    seed: int
+    nside: int
+    n_det: int
+    n_samp: int
+    noise: str                    # "diag" (white) or "band" (1/f, band-Toeplitz inverse)
+    bandwidth: int = 1            # number of Toeplitz lags t[0..b-1]
+    hwp: bool = False
+    dtype: str = "f64"            # canonical pointing / TOD dtype: "f64" or "f32"
+    iters: int = 20
+    offsets_deg: float = 1.0      # detector offsets uniform in +-offsets_deg (0: boresight)
+    fs: float = 50.0              # sampling rate [Hz]
+    spin_period: float = 60.0     # [s]
+    prec_period: float = 5400.0   # [s]
+    spin_angle_deg: float = 50.0
+    prec_angle_deg: float = 45.0
+    f_hwp: float = 2.0            # [Hz]
+    f_knee: float = 0.1
+    alpha: float = -1.0
+    sigma: float = 1.0
+    psd_len: int = 1 << 20        # frequency grid length used to build the Toeplitz lags
+
+    @property
+    def npix(self) -> int:
+        return 12 * self.nside * self.nside
+
+    @property
+    def n_samples(self) -> int:
+        return self.n_det * self.n_samp
+
+    @property
+    def hwp_num(self) -> int:
+        return int(round(self.f_hwp)) if self.hwp else 0
+
+    @property
+    def hwp_den(self) -> int:
+        return int(round(self.fs)) if self.hwp else 1
+
+    def with_(self, **kw) -> "Workload":
+        return replace(self, **kw)
+
+
+# The five workloads the method is exercised on (1: CPU-size FP64; 2: FP64 at
+# scale with 1/f noise and a HWP; 3: FP32 variant of 2; 4: differentiation;
+# 5: the large single-GPU run).
+WORKLOADS = {
+    1: Workload("nside64_4x65536_diag_f64", 1001, 64, 4, 65536, "diag", 1, False, "f64", 20,
+                offsets_deg=0.0),
+    2: Workload("nside512_256x2^20_band4096_hwp_f64", 1002, 512, 256, 1 << 20, "band", 4096,
+                True, "f64", 50),
+    3: Workload("nside512_256x2^20_band4096_hwp_f32", 1003, 512, 256, 1 << 20, "band", 4096,
+                True, "f32", 50),
+    4: Workload("nside256_64x2^20_diag_f32_grad", 1004, 256, 64, 1 << 20, "diag", 1, False,
+                "f32", 0),
+    5: Workload("nside1024_1024x2^20_band8192_hwp_f32", 1005, 1024, 1024, 1 << 20, "band", 8192,
+                True, "f32", 100),
+}
+
+
+def _rot(axis: str, a: torch.Tensor) -> torch.Tensor:
+    """Right-handed rotation matrices about a coordinate axis, shape a.shape + (3, 3)."""
+    c, s = torch.cos(a), torch.sin(a)
+    o, z = torch.ones_like(a), torch.zeros_like(a)
+    if axis == "x":
+        rows = [[o, z, z], [z, c, -s], [z, s, c]]
+    elif axis == "y":
+        rows = [[c, z, s], [z, o, z], [-s, z, c]]
+    else:
+        rows = [[c, -s, z], [s, c, z], [z, z, o]]
+    return torch.stack([torch.stack(r, -1) for r in rows], -2)
+
+
+def detector_offsets(w: Workload, det: torch.Tensor) -> torch.Tensor:
+    """Focal-plane offsets (dx_k, dy_k) in radians, shape [len(det), 2]."""
+    out = torch.empty(len(det), 2, dtype=torch.float64)
+    lim = math.radians(w.offsets_deg)
+    for j, k in enumerate(det.tolist()):
+        key = stream_key(w.seed, 2 + k, SUB_OFFSET)
+        u = uniform(key, torch.arange(2))
+        out[j] = (2.0 * u - 1.0) * lim
+    return out
+
+
+def boresight_rotations(w: Workload, i0: int, n: int, device) -> torch.Tensor:
+    """Scan rotation R(t_i) for samples i0..i0+n-1, shape [n, 3, 3], float64."""
+    key = stream_key(w.seed, STREAM_SCAN, 0)
+    ph = uniform(key, torch.arange(2)) * (2.0 * math.pi)
+    t = torch.arange(i0, i0 + n, dtype=torch.float64, device=device) / w.fs
+    wp = 2.0 * math.pi / w.prec_period
+    ws = 2.0 * math.pi / w.spin_period
+    r_a = _rot("y", torch.tensor(math.pi / 2, dtype=torch.float64, device=device))
+    r_p = _rot("z", wp * t + float(ph[0]))
+    r_45 = _rot("y", torch.tensor(math.radians(w.prec_angle_deg), dtype=torch.float64,
+                                  device=device))
+    r_s = _rot("z", ws * t + float(ph[1]))
+    r_50 = _rot("y", torch.tensor(math.radians(w.spin_angle_deg), dtype=torch.float64,
+                                  device=device))
+    return r_a @ r_p @ r_45 @ r_s @ r_50
+
+
+@dataclass
+class Pointing:
+    """Detector pointing: theta, phi, psi planes [n_det][n_samp] (radians)."""
+    theta: torch.Tensor
+    phi: torch.Tensor
+    psi: torch.Tensor
+
+
+def pointing(w: Workload, det0: int = 0, n_det: Optional[int] = None, i0: int = 0,
+             n_samp: Optional[int] = None, device="cpu", dtype: Optional[str] = None,
+             det_chunk: int = 16) -> Pointing:
+    """Generate detector pointing for detectors [det0, det0+n_det) and samples [i0, i0+n_samp).
+
+    Directions are computed in float64 and rounded once to the requested dtype
+    (the workload's canonical dtype by default).
+    """
+    n_det = w.n_det - det0 if n_det is None else n_det
+    n_samp = w.n_samp - i0 if n_samp is None else n_samp
+    dt = {"f64": torch.float64, "f32": torch.float32}[dtype or w.dtype]
+    theta = torch.empty(n_det, n_samp, dtype=dt, device=device)
+    phi = torch.empty_like(theta)
+    psi = torch.empty_like(theta)
+    rot = boresight_rotations(w, i0, n_samp, device)
+    dets = torch.arange(det0, det0 + n_det)
+    offs = detector_offsets(w, dets)
+    zhat = torch.tensor([0.0, 0.0, 1.0], dtype=torch.float64)
+    counters = torch.arange(i0, i0 + n_samp, dtype=torch.int64, device=device)
+    two_pi = 2.0 * math.pi
+    for c0 in range(0, n_det, det_chunk):
+        c1 = min(n_det, c0 + det_chunk)
+        u = torch.stack([_rot("x", offs[j, 1]) @ _rot("y", offs[j, 0]) @ zhat
+                         for j in range(c0, c1)]).to(device)            # [d, 3]
+        v = torch.einsum("tij,dj->dti", rot, u)                          # [d, t, 3]
+        vz = v[..., 2].clamp(-1.0, 1.0)
+        theta[c0:c1] = torch.arccos(vz).to(dt)
+        ph = torch.atan2(v[..., 1], v[..., 0])
+        ph = torch.where(ph < 0, ph + two_pi, ph)
+        phi[c0:c1] = ph.to(dt)
+        for j in range(c0, c1):
+            key = stream_key(w.seed, 2 + det0 + j, SUB_PSI)
+            psi[j] = (uniform(key, counters) * two_pi).to(dt)
+        del v
+    return Pointing(theta, phi, psi)
+
+
+def sky_map(w: Workload, device="cpu") -> torch.Tensor:
+    """Random IQU map, i.i.d. N(0,1) per pixel and Stokes, shape [3, npix], float64."""
+    key = stream_key(w.seed, STREAM_MAP, 0)
+    return normal(key, torch.arange(3 * w.npix, device=device)).reshape(3, w.npix)
+
+
+def psd(w: Workload, f: np.ndarray) -> np.ndarray:
+    """Noise power spectrum sigma^2 (1 + (f/f_knee)^alpha)."""
+    with np.errstate(divide="ignore"):
+        return w.sigma ** 2 * (1.0 + (f / w.f_knee) ** w.alpha)
+
+
+def toeplitz_lags(w: Workload, b: Optional[int] = None) -> np.ndarray:
+    """Inverse-noise autocorrelation lags t[0..b-1] (float64) from the PSD.
+
+    The inverse PSD is sampled on the frequency grid j*fs/L (L = psd_len), its
+    zero-frequency value replaced by the first non-zero bin, and transformed
+    back to lags with an inverse real FFT; the first b lags are kept.
+    """
+    b = w.bandwidth if b is None else b
+    L = w.psd_len
+    f = np.arange(L // 2 + 1) * (w.fs / L)
+    p = psd(w, f)
+    p[0] = p[1]
+    t = np.fft.irfft(1.0 / p, n=L)
+    return np.ascontiguousarray(t[:b])
+
+
+def white_lags(w: Workload) -> np.ndarray:
+    return np.array([1.0 / w.sigma ** 2])
+
+
+def noise(w: Workload, det0: int = 0, n_det: Optional[int] = None, i0: int = 0,
+          n_samp: Optional[int] = None, device="cpu") -> torch.Tensor:
+    """Noise streams [n_det][n_samp] float64: white sigma, or 1/f shaped in Fourier space."""
+    n_det = w.n_det - det0 if n_det is None else n_det
+    n_samp = w.n_samp - i0 if n_samp is None else n_samp
+    out = torch.empty(n_det, n_samp, dtype=torch.float64, device=device)
+    cnt = torch.arange(i0, i0 + n_samp, dtype=torch.int64, device=device)
+    shape = None
+    if w.noise == "band":
+        f = np.arange(n_samp // 2 + 1) * (w.fs / n_samp)
+        p = psd(w, f)
+        p[0] = p[1] if n_samp > 2 else p[0]
+        shape = torch.from_numpy(np.sqrt(p) / w.sigma).to(device)
+    for j in range(n_det):
+        key = stream_key(w.seed, 2 + det0 + j, SUB_NOISE)
+        x = normal(key, cnt) * w.sigma
+        if shape is not None:
+            x = torch.fft.irfft(torch.fft.rfft(x) * shape, n=n_samp)
+        out[j] = x
+    return out
+
+
+def gains(w: Workload, det0: int = 0, n_det: Optional[int] = None, scale: float = 0.01):
+    """Per-detector gains 1 + scale * N(0,1), float64 [n_det]."""
+    n_det = w.n_det - det0 if n_det is None else n_det
+    out = torch.empty(n_det, dtype=torch.float64)
+    for j in range(n_det):
+        key = stream_key(w.seed, 2 + det0 + j, SUB_GAIN)
+        out[j] = 1.0 + scale * normal(key, torch.arange(1))[0]
+    return out
+
+
+def angle_offsets(w: Workload, det0: int = 0, n_det: Optional[int] = None,
+                  sigma_deg: float = 0.5):
+    """Per-detector polarisation-angle offsets N(0, sigma_deg^2) in radians, float64 [n_det]."""
+    n_det = w.n_det - det0 if n_det is None else n_det
+    out = torch.empty(n_det, dtype=torch.float64)
+    for j in range(n_det):
+        key = stream_key(w.seed, 2 + det0 + j, SUB_GAIN)
+        out[j] = math.radians(sigma_deg) * normal(key, torch.arange(1, 2))[0]
+    return out
+
+
+def uniform_sphere(seed: int, n: int, device="cpu"):
+    """n points uniform on the sphere: (theta, phi) float64."""
+    key = stream_key(seed, 7, 0)
+    c = torch.arange(n, device=device)
+    z = 1.0 - 2.0 * uniform(key, 2 * c)
+    ph = 2.0 * math.pi * uniform(key, 2 * c + 1)
+    return torch.arccos(z.clamp(-1, 1)), ph
