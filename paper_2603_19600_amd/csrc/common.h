@@ -1,0 +1,213 @@
+// Internal declarations shared by the library's translation units: device-side
+// pointing math, kernel argument bundles and host-side error plumbing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+
+#include "furax.h"
+
+namespace fx {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kMaxNside = 8192;
+
+// ---------------------------------------------------------------------------
+// Host-side status plumbing.
+// ---------------------------------------------------------------------------
+furax_status set_error(furax_status st, const std::string &msg);
+furax_status hip_error(hipError_t e, const char *what);
+
+#define FX_HIP(call)                                                   \
+  do {                                                                 \
+    hipError_t fx_e_ = (call);                                         \
+    if (fx_e_ != hipSuccess) return ::fx::hip_error(fx_e_, #call);     \
+  } while (0)
+
+#define FX_TRY(call)                                                   \
+  do {                                                                 \
+    furax_status fx_s_ = (call);                                       \
+    if (fx_s_ != FURAX_OK) return fx_s_;                               \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Pointing operator arguments as passed to kernels (by value).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct PtArgs {
+  const T *theta, *phi, *psi;
+  const double *gain;   // may be null
+  const double *dpsi;   // may be null
+  int64_t n_det, n_samp;
+  int32_t nside;
+  int32_t hwp;
+  int64_t hwp_num_mod, hwp_den;   // hwp_num reduced mod hwp_den
+  double hwp_phase0;
+  const uint8_t *valid; // [npix] or null: samples in pixels with valid == 0 are flagged
+};
+
+// HEALPix ring-scheme ang2pix in FP64 (ring-scheme formulas of Gorski et al.
+// 2005).  Every operation is rounded on its own (no contraction) so that the
+// result equals a plain IEEE evaluation of the same expression sequence; the
+// only libm call is cos().  Returns -1 for non-finite input or theta outside
+// [0, pi].
+__device__ __forceinline__ int32_t ang2pix_ring(int32_t n, double theta, double phi) {
+#pragma clang fp contract(off)
+  if (!(theta >= 0.0 && theta <= kPi)) return -1;      // also rejects NaN
+  if (!(phi - phi == 0.0)) return -1;                   // rejects NaN and +-inf
+  const double N = (double)n;
+  const double two_pi = 2.0 * kPi;
+  const double half_pi = 0.5 * kPi;
+  const double z = cos(theta);
+  const double za = fabs(z);
+  double phr = fmod(phi, two_pi);
+  if (phr < 0.0) phr = phr + two_pi;
+  const double tt = phr / half_pi;                      // in [0, 4]
+  int32_t pix;
+  if (za <= 2.0 / 3.0) {
+    const double t1 = N * (0.5 + tt);
+    const double t2 = (0.75 * N) * z;
+    const int32_t jp = (int32_t)floor(t1 - t2);
+    const int32_t jm = (int32_t)floor(t1 + t2);
+    const int32_t ir = n + 1 + jp - jm;                 // 1 .. 2n+1
+    const int32_t kshift = 1 - (ir & 1);
+    int32_t ip = (jp + jm - n + kshift + 1) / 2;        // non-negative
+    ip = ip % (4 * n);
+    pix = 2 * n * (n - 1) + (ir - 1) * (4 * n) + ip;
+  } else {
+    const double tp = tt - floor(tt);
+    const double w = N * sqrt(3.0 * (1.0 - za));
+    const int32_t jp = (int32_t)floor(tp * w);
+    const int32_t jm = (int32_t)floor((1.0 - tp) * w);
+    const int32_t ir = jp + jm + 1;                     // 1 .. n
+    int32_t ip = (int32_t)floor(tt * (double)ir);
+    ip = ip % (4 * ir);
+    pix = (z > 0.0) ? 2 * ir * (ir - 1) + ip : 12 * n * n - 2 * ir * (ir + 1) + ip;
+  }
+  return ((uint32_t)pix < (uint32_t)(12 * n * n)) ? pix : -1;
+}
+
+// HWP angle alpha_i = 2 pi ((num * i) mod den) / den + phase0, from integers.
+__device__ __forceinline__ double hwp_alpha(int64_t i, int64_t num_mod, int64_t den,
+                                            double phase0) {
+#pragma clang fp contract(off)
+  const int64_t m = (num_mod * (i % den)) % den;
+  const double frac = (double)m / (double)den;
+  return (2.0 * kPi) * frac + phase0;
+}
+
+// Merged polarisation angle times two: 2 (psi + dpsi_k + 2 alpha_i), FP64.
+template <typename T>
+__device__ __forceinline__ double two_psi_eff(const PtArgs<T> &a, int64_t k, int64_t i,
+                                              double psi) {
+#pragma clang fp contract(off)
+  double pe = psi;
+  if (a.dpsi) pe = pe + a.dpsi[k];
+  if (a.hwp) pe = pe + 2.0 * hwp_alpha(i, a.hwp_num_mod, a.hwp_den, a.hwp_phase0);
+  return 2.0 * pe;
+}
+
+// Polariser weights cos / sin of an angle given in FP64.  The FP64 variant
+// evaluates them in FP64; the FP32 variant first reduces the angle to
+// [-pi, pi] in FP64, then evaluates in FP32.
+__device__ __forceinline__ void weights(double ang, double &c, double &s) {
+  sincos(ang, &s, &c);
+}
+__device__ __forceinline__ void weights(double ang, float &c, float &s) {
+  const double r = ang - (2.0 * kPi) * rint(ang * (1.0 / (2.0 * kPi)));
+  sincosf((float)r, &s, &c);
+}
+
+// Geometry of one sample: pixel (or -1) and polariser weights.
+template <typename T>
+struct Geom {
+  int32_t pix;
+  T c, s;
+};
+
+template <typename T>
+__device__ __forceinline__ Geom<T> sample_geom(const PtArgs<T> &a, int64_t k, int64_t i) {
+  const int64_t off = k * a.n_samp + i;
+  Geom<T> g;
+  g.pix = ang2pix_ring(a.nside, (double)a.theta[off], (double)a.phi[off]);
+  if (g.pix >= 0 && a.valid && !a.valid[g.pix]) g.pix = -1;
+  weights(two_psi_eff(a, k, i, (double)a.psi[off]), g.c, g.s);
+  return g;
+}
+
+template <typename T>
+__device__ __forceinline__ T gain_of(const PtArgs<T> &a, int64_t k) {
+  return a.gain ? (T)a.gain[k] : (T)1;
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers.
+// ---------------------------------------------------------------------------
+// Per-sample kernels: one workgroup covers kChunk consecutive samples of one
+// detector (kBlock threads x kItems samples, strided so loads coalesce).
+constexpr int kBlock = 256;
+constexpr int kItems = 4;
+constexpr int64_t kChunk = (int64_t)kBlock * kItems;
+
+__host__ __device__ inline int64_t chunks_per_det(int64_t n_samp) { return (n_samp + kChunk - 1) / kChunk; }
+
+// ---------------------------------------------------------------------------
+// Host-side validation and conversion of the public structs.
+// ---------------------------------------------------------------------------
+furax_status check_pointing(const furax_pointing *P);
+furax_status check_noise(const furax_noise *N, int64_t n_det, int64_t n_samp, int32_t dt);
+int64_t npix_of(int64_t nside);
+
+template <typename T>
+PtArgs<T> pt_args(const furax_pointing *P, const uint8_t *valid) {
+  PtArgs<T> a;
+  a.theta = static_cast<const T *>(P->theta);
+  a.phi = static_cast<const T *>(P->phi);
+  a.psi = static_cast<const T *>(P->psi);
+  a.gain = P->gain;
+  a.dpsi = P->dpsi;
+  a.n_det = P->n_det;
+  a.n_samp = P->n_samp;
+  a.nside = (int32_t)P->nside;
+  a.hwp = P->hwp;
+  a.hwp_den = P->hwp ? P->hwp_den : 1;
+  a.hwp_num_mod = P->hwp ? (P->hwp_num % a.hwp_den) : 0;
+  a.hwp_phase0 = P->hwp ? P->hwp_phase0 : 0.0;
+  a.valid = valid;
+  return a;
+}
+
+// Device scratch that a call allocates stream-ordered and frees on exit.
+struct DevBuf {
+  void *ptr = nullptr;
+  hipStream_t stream = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() {
+    if (ptr) (void)hipFreeAsync(ptr, stream);
+  }
+  furax_status alloc(size_t bytes, hipStream_t s);
+};
+
+// Kernel-launch wrappers implemented in the individual translation units.
+template <typename T>
+furax_status launch_pointing_apply(const PtArgs<T> &a, const void *map, bool map_f64, T *tod,
+                                   hipStream_t s);
+template <typename T>
+furax_status launch_pointing_transpose(const PtArgs<T> &a, const T *tod, double *map,
+                                       bool tod_scaled_by_w, const double *w_det,
+                                       hipStream_t s);
+template <typename T>
+furax_status launch_noise(const furax_noise *N, const T *in, T *out, void *work,
+                          size_t work_bytes, hipStream_t s);
+template <typename T>
+size_t noise_workspace_bytes(const furax_noise *N);
+template <typename T>
+furax_status launch_fused_diag(const PtArgs<T> &a, const T *map_lo, const double *p,
+                               const double *w_det, double *q, hipStream_t s);
+
+furax_status zero_async(void *ptr, size_t bytes, hipStream_t s);
+
+}  // namespace fx

@@ -1,0 +1,568 @@
+// Normal operator A = P^T N^-1 P and the block-Jacobi PCG map-maker.
+//
+// The solver is the iterative inverse of Table 1 (A.I(solver, preconditioner))
+// applied to the estimator of Eq. (2) with T = 0, preconditioned by the
+// block-Jacobi preconditioner of "Map-making classes".  All scalars of the
+// recurrence (<p,q>, alpha, <r,z>, beta, |r|) live in device memory and are
+// produced by deterministic two-pass FP64 reductions, so an iteration never
+// waits on the host; a device-side stop flag freezes the iterate on
+// convergence or breakdown.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "reduce.h"
+
+namespace fx {
+
+template <typename T>
+furax_status noise_prepare(const furax_noise *N, void *spec, hipStream_t s);
+template <typename T>
+furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *spec,
+                       hipStream_t s);
+template <typename T>
+furax_status launch_bj_build(const PtArgs<T> &a, const double *w_det, double *M6, int32_t *hits,
+                             hipStream_t s);
+furax_status launch_bj_invert(int64_t npix, const double *M6, const int32_t *hits,
+                              double rcond_min, int32_t min_hits, const uint8_t *force_valid,
+                              double *Minv6, uint8_t *valid, double *rcond, hipStream_t s);
+
+
+struct PcgScalars {
+  double rz, pq, alpha, beta, rr, bnorm, rel, rtol;
+  int32_t stop;      // 0 running, 1 rtol reached, 2 breakdown
+  int32_t iters;
+};
+
+__device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v - v == 0.0; }
+
+// partial[j*kRedBlocks + block] = sum over this block's range of a_j . b_j
+__global__ void __launch_bounds__(kBlock) k_dot2_partial(const double *__restrict__ a0,
+                                                         const double *__restrict__ b0,
+                                                         const double *__restrict__ a1,
+                                                         const double *__restrict__ b1,
+                                                         int64_t n, double *__restrict__ partial) {
+  double v[2] = {0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    v[0] += a0[i] * b0[i];
+    if (a1) v[1] += a1[i] * b1[i];
+  }
+  block_sum<2>(v, partial + blockIdx.x, kRedBlocks);
+}
+
+// After the initial residual: partial[0] = <r,z>, partial[1] = <b,b>.
+__global__ void __launch_bounds__(kBlock) k_init_final(const double *__restrict__ partial,
+                                                       double rtol, PcgScalars *sc, double *hist) {
+  double v[2];
+  final_sum<2>(partial, v);
+  if (threadIdx.x != 0) return;
+  sc->rz = v[0];
+  sc->rtol = rtol;
+  sc->bnorm = sqrt(v[1]);
+  sc->iters = 0;
+  sc->stop = 0;
+  // b = 0 is solved by x = 0; a non-finite or non-positive <r,z> is a breakdown
+  sc->rel = v[1] == 0.0 ? 0.0 : 1.0;
+  if (hist) hist[0] = sc->rel;
+  if (v[1] == 0.0) sc->stop = 1;
+  else if (!finite_pos(v[0]) || !finite_pos(v[1])) sc->stop = 2;
+}
+
+__global__ void __launch_bounds__(kBlock) k_pq_final(const double *__restrict__ partial,
+                                                     PcgScalars *sc) {
+  double v[1];
+  final_sum<1>(partial, v);
+  if (threadIdx.x != 0 || sc->stop) return;
+  sc->pq = v[0];
+  if (!finite_pos(v[0])) sc->stop = 2;
+  else sc->alpha = sc->rz / v[0];
+}
+
+// x += alpha p; r -= alpha q; z = Minv r; partials of <r,z> and <r,r>.
+__global__ void __launch_bounds__(kBlock) k_update1(int64_t npix, double *__restrict__ x,
+                                                    double *__restrict__ r,
+                                                    const double *__restrict__ p,
+                                                    const double *__restrict__ q,
+                                                    const double *__restrict__ Mi,
+                                                    double *__restrict__ z,
+                                                    const PcgScalars *__restrict__ sc,
+                                                    double *__restrict__ partial) {
+  if (sc->stop) return;
+  const double alpha = sc->alpha;
+  double v[2] = {0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npix; i += stride) {
+    double rr[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t j = c * npix + i;
+      x[j] = x[j] + alpha * p[j];
+      rr[c] = r[j] - alpha * q[j];
+      r[j] = rr[c];
+    }
+    const double a = Mi[i], b = Mi[npix + i], cc = Mi[2 * npix + i];
+    const double d = Mi[3 * npix + i], e = Mi[4 * npix + i], f = Mi[5 * npix + i];
+    const double z0 = a * rr[0] + b * rr[1] + cc * rr[2];
+    const double z1 = b * rr[0] + d * rr[1] + e * rr[2];
+    const double z2 = cc * rr[0] + e * rr[1] + f * rr[2];
+    z[i] = z0;
+    z[npix + i] = z1;
+    z[2 * npix + i] = z2;
+    v[0] += rr[0] * z0 + rr[1] * z1 + rr[2] * z2;
+    v[1] += rr[0] * rr[0] + rr[1] * rr[1] + rr[2] * rr[2];
+  }
+  block_sum<2>(v, partial + blockIdx.x, kRedBlocks);
+}
+
+__global__ void __launch_bounds__(kBlock) k_rz_final(const double *__restrict__ partial,
+                                                     PcgScalars *sc, double *hist, int32_t nhist) {
+  double v[2];
+  final_sum<2>(partial, v);
+  if (threadIdx.x != 0 || sc->stop) return;
+  const int32_t it = sc->iters + 1;
+  sc->iters = it;
+  sc->rr = v[1];
+  const double rel = sqrt(v[1]) / sc->bnorm;
+  sc->rel = rel;
+  if (hist && it < nhist) hist[it] = rel;
+  if (rel <= sc->rtol) {
+    sc->stop = 1;
+  } else if (!finite_pos(v[0])) {
+    sc->stop = 2;
+  } else {
+    sc->beta = v[0] / sc->rz;
+    sc->rz = v[0];
+  }
+}
+
+// p = z + beta p (and its FP32 copy for the FP32 path).
+__global__ void __launch_bounds__(kBlock) k_update2(int64_t n, double *__restrict__ p,
+                                                    const double *__restrict__ z,
+                                                    float *__restrict__ p32,
+                                                    const PcgScalars *__restrict__ sc) {
+  if (sc->stop) return;
+  const double beta = sc->beta;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const double v = z[i] + beta * p[i];
+    p[i] = v;
+    if (p32) p32[i] = (float)v;
+  }
+}
+
+// z = Minv r (initial), r = b, p = z, x = 0; partials of <r,z>, <b,b>.
+__global__ void __launch_bounds__(kBlock) k_init_vectors(int64_t npix, const double *__restrict__ b,
+                                                         double *__restrict__ x,
+                                                         double *__restrict__ r,
+                                                         double *__restrict__ z,
+                                                         double *__restrict__ p,
+                                                         float *__restrict__ p32,
+                                                         const double *__restrict__ Mi,
+                                                         double *__restrict__ partial) {
+  double v[2] = {0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npix; i += stride) {
+    double rr[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      rr[c] = b[c * npix + i];
+      r[c * npix + i] = rr[c];
+      x[c * npix + i] = 0.0;
+    }
+    const double a = Mi[i], bb = Mi[npix + i], cc = Mi[2 * npix + i];
+    const double d = Mi[3 * npix + i], e = Mi[4 * npix + i], f = Mi[5 * npix + i];
+    const double zz[3] = {a * rr[0] + bb * rr[1] + cc * rr[2], bb * rr[0] + d * rr[1] + e * rr[2],
+                          cc * rr[0] + e * rr[1] + f * rr[2]};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      z[c * npix + i] = zz[c];
+      p[c * npix + i] = zz[c];
+      if (p32) p32[c * npix + i] = (float)zz[c];
+      v[0] += rr[c] * zz[c];
+      v[1] += rr[c] * rr[c];
+    }
+  }
+  block_sum<2>(v, partial + blockIdx.x, kRedBlocks);
+}
+
+__global__ void __launch_bounds__(kBlock) k_to_f32(int64_t n, const double *__restrict__ a,
+                                                   float *__restrict__ b) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+    b[i] = (float)a[i];
+}
+
+__global__ void k_diag_weights(int64_t n_det, const double *__restrict__ inv_var,
+                               const double *__restrict__ lags, int64_t lag_stride,
+                               double *__restrict__ w) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_det) return;
+  w[k] = inv_var ? inv_var[k] : lags[k * lag_stride];
+}
+
+static int64_t map_blocks(int64_t n) {
+  return std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, kRedBlocks));
+}
+
+// ---------------------------------------------------------------------------
+// Normal operator.
+// ---------------------------------------------------------------------------
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct NormalLayout {
+  size_t spec = 0, y = 0, z = 0, p32 = 0, wdet = 0, total = 0;
+};
+
+template <typename T>
+static NormalLayout normal_layout(const furax_pointing *P, const furax_noise *N) {
+  NormalLayout L;
+  size_t off = 0;
+  const size_t tod = (size_t)P->n_det * P->n_samp * sizeof(T);
+  L.wdet = off; off += align256(sizeof(double) * P->n_det);
+  if (N->kind == 1) {
+    L.spec = off; off += align256(noise_workspace_bytes<T>(N));
+    L.y = off; off += align256(tod);
+    L.z = off; off += align256(tod);
+  }
+  if (sizeof(T) == 4) {
+    L.p32 = off; off += align256(sizeof(float) * 3 * npix_of(P->nside));
+  }
+  L.total = off;
+  return L;
+}
+
+// Everything the normal operator needs besides p and q, prepared once.
+template <typename T>
+struct NormalPlan {
+  const furax_pointing *P;
+  const furax_noise *N;
+  PtArgs<T> a;
+  char *work;
+  NormalLayout L;
+  int64_t npix;
+};
+
+template <typename T>
+static furax_status normal_prepare(NormalPlan<T> &pl, hipStream_t s) {
+  const furax_noise *N = pl.N;
+  double *w = reinterpret_cast<double *>(pl.work + pl.L.wdet);
+  hipLaunchKernelGGL(k_diag_weights, dim3((unsigned)((pl.P->n_det + 255) / 256)), dim3(256), 0, s,
+                     pl.P->n_det, N->kind == 0 ? N->inv_var : nullptr,
+                     N->kind == 1 ? N->toeplitz : nullptr, N->toeplitz_stride, w);
+  FX_HIP(hipGetLastError());
+  if (N->kind == 1) FX_TRY(noise_prepare<T>(N, pl.work + pl.L.spec, s));
+  return FURAX_OK;
+}
+
+// q = P^T N^-1 P p.  If p32 is given it is the FP32 copy of p (FP32 path).
+template <typename T>
+static furax_status normal_run(const NormalPlan<T> &pl, const double *p, const float *p32,
+                               double *q, hipStream_t s) {
+  const double *w = reinterpret_cast<const double *>(pl.work + pl.L.wdet);
+  FX_TRY(zero_async(q, sizeof(double) * 3 * pl.npix, s));
+  const T *map_lo = nullptr;
+  if constexpr (sizeof(T) == 4) map_lo = p32;
+  if (pl.N->kind == 0) return launch_fused_diag<T>(pl.a, map_lo, p, w, q, s);
+  T *y = reinterpret_cast<T *>(pl.work + pl.L.y);
+  T *z = reinterpret_cast<T *>(pl.work + pl.L.z);
+  if (map_lo) FX_TRY(launch_pointing_apply<T>(pl.a, map_lo, false, y, s));
+  else FX_TRY(launch_pointing_apply<T>(pl.a, p, true, y, s));
+  FX_TRY(noise_run<T>(pl.N, y, z, pl.work + pl.L.spec, s));
+  return launch_pointing_transpose<T>(pl.a, z, q, true, nullptr, s);
+}
+
+int64_t normal_workspace_bytes(const furax_pointing *P, const furax_noise *N, int32_t prec) {
+  return prec == FURAX_F32 ? (int64_t)normal_layout<float>(P, N).total
+                           : (int64_t)normal_layout<double>(P, N).total;
+}
+
+template <typename T>
+furax_status normal_apply_impl(const furax_pointing *P, const furax_noise *N, const double *p,
+                               double *q, const uint8_t *valid, void *work, hipStream_t s) {
+  NormalPlan<T> pl;
+  pl.P = P;
+  pl.N = N;
+  pl.a = pt_args<T>(P, valid);
+  pl.L = normal_layout<T>(P, N);
+  pl.npix = npix_of(P->nside);
+  DevBuf own;
+  if (!work) {
+    FX_TRY(own.alloc(pl.L.total, s));
+    work = own.ptr;
+  }
+  pl.work = static_cast<char *>(work);
+  FX_TRY(normal_prepare<T>(pl, s));
+  float *p32 = nullptr;
+  if constexpr (sizeof(T) == 4) {
+    p32 = reinterpret_cast<float *>(pl.work + pl.L.p32);
+    const int64_t n = 3 * pl.npix;
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)map_blocks(n)), dim3(kBlock), 0, s, n, p, p32);
+    FX_HIP(hipGetLastError());
+  }
+  return normal_run<T>(pl, p, p32, q, s);
+}
+template furax_status normal_apply_impl<float>(const furax_pointing *, const furax_noise *,
+                                               const double *, double *, const uint8_t *, void *,
+                                               hipStream_t);
+template furax_status normal_apply_impl<double>(const furax_pointing *, const furax_noise *,
+                                                const double *, double *, const uint8_t *, void *,
+                                                hipStream_t);
+
+template <typename T>
+furax_status bj_build_impl(const furax_pointing *P, const furax_noise *N, double *M6,
+                           int32_t *hits, hipStream_t s) {
+  const int64_t npix = npix_of(P->nside);
+  DevBuf wbuf;
+  FX_TRY(wbuf.alloc(sizeof(double) * P->n_det, s));
+  double *w = static_cast<double *>(wbuf.ptr);
+  hipLaunchKernelGGL(k_diag_weights, dim3((unsigned)((P->n_det + 255) / 256)), dim3(256), 0, s,
+                     P->n_det, N->kind == 0 ? N->inv_var : nullptr,
+                     N->kind == 1 ? N->toeplitz : nullptr, N->toeplitz_stride, w);
+  FX_HIP(hipGetLastError());
+  FX_TRY(zero_async(M6, sizeof(double) * 6 * npix, s));
+  FX_TRY(zero_async(hits, sizeof(int32_t) * npix, s));
+  return launch_bj_build<T>(pt_args<T>(P, nullptr), w, M6, hits, s);
+}
+template furax_status bj_build_impl<float>(const furax_pointing *, const furax_noise *, double *,
+                                           int32_t *, hipStream_t);
+template furax_status bj_build_impl<double>(const furax_pointing *, const furax_noise *, double *,
+                                            int32_t *, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// PCG session.
+// ---------------------------------------------------------------------------
+}  // namespace fx
+
+struct furax_pcg_state {
+  furax_pointing P;
+  furax_noise N;
+  furax_pcg_opts opt;
+  hipStream_t s = nullptr;
+  int64_t npix = 0;
+  int32_t precision = FURAX_F64;
+  char *mem = nullptr;       // one stream-ordered allocation for everything
+  size_t mem_bytes = 0;
+  double *x, *r, *z, *p, *q, *Minv, *partial, *hist;
+  float *p32;
+  uint8_t *valid;
+  fx::PcgScalars *sc;
+  fx::NormalPlan<float> pl32;
+  fx::NormalPlan<double> pl64;
+  int32_t nhist = 0;
+  int32_t iters_launched = 0;
+};
+
+namespace fx {
+
+template <typename T>
+static furax_status pcg_setup(furax_pcg_state *h, const void *tod) {
+  hipStream_t s = h->s;
+  const int64_t npix = h->npix;
+  NormalPlan<T> &pl = [&]() -> NormalPlan<T> & {
+    if constexpr (sizeof(T) == 4) return h->pl32;
+    else return h->pl64;
+  }();
+  pl.P = &h->P;
+  pl.N = &h->N;
+  pl.npix = npix;
+  pl.L = normal_layout<T>(&h->P, &h->N);
+
+  // Memory map of the session.
+  const size_t vec = align256(sizeof(double) * 3 * npix);
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t o = off; off += align256(b); return o; };
+  const size_t o_x = take(vec), o_r = take(vec), o_z = take(vec), o_p = take(vec), o_q = take(vec);
+  const size_t o_minv = take(sizeof(double) * 6 * npix);
+  const size_t o_valid = take(npix);
+  const size_t o_p32 = take(sizeof(T) == 4 ? sizeof(float) * 3 * npix : 0);
+  const size_t o_part = take(sizeof(double) * 2 * kRedBlocks);
+  const size_t o_sc = take(sizeof(PcgScalars));
+  h->nhist = h->opt.max_iter + 1;
+  const size_t o_hist = take(sizeof(double) * h->nhist);
+  const size_t o_work = take(pl.L.total);
+  h->mem_bytes = off;
+  if (hipMallocAsync((void **)&h->mem, off, s) != hipSuccess)
+    return set_error(FURAX_ENOMEM, "PCG workspace allocation failed");
+  char *m = h->mem;
+  h->x = (double *)(m + o_x);
+  h->r = (double *)(m + o_r);
+  h->z = (double *)(m + o_z);
+  h->p = (double *)(m + o_p);
+  h->q = (double *)(m + o_q);
+  h->Minv = (double *)(m + o_minv);
+  h->valid = (uint8_t *)(m + o_valid);
+  h->p32 = sizeof(T) == 4 ? (float *)(m + o_p32) : nullptr;
+  h->partial = (double *)(m + o_part);
+  h->sc = (PcgScalars *)(m + o_sc);
+  h->hist = (double *)(m + o_hist);
+  pl.work = m + o_work;
+  // Before the first iteration the unaccumulated blocks M6 (6 planes) live in
+  // the adjacent p and q vectors (2 * vec >= 6 npix doubles) and the hit
+  // counts in x; both are consumed by the inversion before those vectors are
+  // initialised.
+  double *M6 = h->p;
+  int32_t *hits = reinterpret_cast<int32_t *>(h->x);
+
+  // Preconditioner: M6 (in p,q), hits (in x), then Minv and valid.
+  pl.a = pt_args<T>(&h->P, nullptr);
+  FX_TRY(normal_prepare<T>(pl, s));
+  const double *w = reinterpret_cast<const double *>(pl.work + pl.L.wdet);
+  FX_TRY(zero_async(M6, sizeof(double) * 6 * npix, s));
+  FX_TRY(zero_async(hits, sizeof(int32_t) * npix, s));
+  FX_TRY(launch_bj_build<T>(pl.a, w, M6, hits, s));
+  FX_TRY(launch_bj_invert(npix, M6, hits, h->opt.rcond_min, h->opt.min_hits, h->opt.valid_in,
+                          h->Minv, h->valid, nullptr, s));
+
+  // Right-hand side b = P^T N^-1 d with samples in invalid pixels flagged; b -> z buffer.
+  pl.a = pt_args<T>(&h->P, h->valid);
+  double *b = h->z;
+  FX_TRY(zero_async(b, sizeof(double) * 3 * npix, s));
+  const T *d = static_cast<const T *>(tod);
+  if (h->N.kind == 0) {
+    FX_TRY(launch_pointing_transpose<T>(pl.a, d, b, false, w, s));
+  } else {
+    T *zt = reinterpret_cast<T *>(pl.work + pl.L.z);
+    FX_TRY(noise_run<T>(&h->N, d, zt, pl.work + pl.L.spec, s));
+    FX_TRY(launch_pointing_transpose<T>(pl.a, zt, b, false, nullptr, s));
+  }
+  // r = b (copied into r), x = 0, z = Minv r, p = z.  b lives in z; k_init_vectors
+  // reads b[i] before writing z[i] for the same i, element by element.
+  hipLaunchKernelGGL(k_init_vectors, dim3((unsigned)kRedBlocks), dim3(kBlock), 0, s, npix, b, h->x,
+                     h->r, h->z, h->p, h->p32, h->Minv, h->partial);
+  FX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_init_final, dim3(1), dim3(kBlock), 0, s, h->partial, h->opt.rtol, h->sc,
+                     h->hist);
+  FX_HIP(hipGetLastError());
+  return FURAX_OK;
+}
+
+template <typename T>
+static furax_status pcg_step(furax_pcg_state *h) {
+  hipStream_t s = h->s;
+  const int64_t n3 = 3 * h->npix;
+  NormalPlan<T> &pl = [&]() -> NormalPlan<T> & {
+    if constexpr (sizeof(T) == 4) return h->pl32;
+    else return h->pl64;
+  }();
+  FX_TRY(normal_run<T>(pl, h->p, h->p32, h->q, s));
+  hipLaunchKernelGGL(k_dot2_partial, dim3((unsigned)kRedBlocks), dim3(kBlock), 0, s, h->p, h->q,
+                     (const double *)nullptr, (const double *)nullptr, n3, h->partial);
+  hipLaunchKernelGGL(k_pq_final, dim3(1), dim3(kBlock), 0, s, h->partial, h->sc);
+  hipLaunchKernelGGL(k_update1, dim3((unsigned)kRedBlocks), dim3(kBlock), 0, s, h->npix, h->x,
+                     h->r, h->p, h->q, h->Minv, h->z, h->sc, h->partial);
+  hipLaunchKernelGGL(k_rz_final, dim3(1), dim3(kBlock), 0, s, h->partial, h->sc, h->hist,
+                     h->nhist);
+  hipLaunchKernelGGL(k_update2, dim3((unsigned)map_blocks(n3)), dim3(kBlock), 0, s, n3, h->p, h->z,
+                     h->p32, h->sc);
+  FX_HIP(hipGetLastError());
+  return FURAX_OK;
+}
+
+furax_status pcg_create(const furax_pointing *P, const furax_noise *N, int32_t tod_dt,
+                        const void *tod, const furax_pcg_opts *opt, hipStream_t s,
+                        furax_pcg *out) {
+  furax_pcg_state *h = new (std::nothrow) furax_pcg_state();
+  if (!h) return set_error(FURAX_ENOMEM, "host allocation failed");
+  h->P = *P;
+  h->N = *N;
+  h->opt = *opt;
+  h->s = s;
+  h->npix = npix_of(P->nside);
+  h->precision = opt->precision;
+  furax_status st = opt->precision == FURAX_F32 ? pcg_setup<float>(h, tod) : pcg_setup<double>(h, tod);
+  if (st != FURAX_OK) {
+    if (h->mem) (void)hipFreeAsync(h->mem, s);
+    delete h;
+    return st;
+  }
+  *out = h;
+  return FURAX_OK;
+}
+
+furax_status pcg_iterate(furax_pcg h, int32_t n_iter) {
+  for (int32_t i = 0; i < n_iter; ++i) {
+    if (h->iters_launched >= h->opt.max_iter) break;
+    if (!h->opt.no_early_exit) {
+      int32_t stop = 0;
+      FX_HIP(hipMemcpyAsync(&stop, &h->sc->stop, sizeof(int32_t), hipMemcpyDeviceToHost, h->s));
+      FX_HIP(hipStreamSynchronize(h->s));
+      if (stop) break;
+    }
+    FX_TRY(h->precision == FURAX_F32 ? pcg_step<float>(h) : pcg_step<double>(h));
+    ++h->iters_launched;
+  }
+  return FURAX_OK;
+}
+
+__global__ void k_copy_out(int64_t npix, const double *__restrict__ x,
+                           const uint8_t *__restrict__ valid, double *__restrict__ out,
+                           uint8_t *__restrict__ vout) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npix; i += stride) {
+    const bool ok = valid[i] != 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c * npix + i] = ok ? x[c * npix + i] : 0.0;
+    if (vout) vout[i] = valid[i];
+  }
+}
+
+__global__ void k_count_valid(int64_t npix, const uint8_t *__restrict__ valid, double *partial) {
+  double v[1] = {0.0};
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npix; i += stride)
+    v[0] += valid[i] ? 1.0 : 0.0;
+  block_sum<1>(v, partial + blockIdx.x, kRedBlocks);
+}
+
+__global__ void k_count_final(const double *partial, PcgScalars *sc, double *out) {
+  double v[1];
+  final_sum<1>(partial, v);
+  if (threadIdx.x == 0) out[0] = v[0];
+}
+
+furax_status pcg_finish(furax_pcg h, double *map_out, uint8_t *valid_out, furax_pcg_info *info) {
+  hipStream_t s = h->s;
+  if (map_out) {
+    hipLaunchKernelGGL(k_copy_out, dim3((unsigned)map_blocks(h->npix)), dim3(kBlock), 0, s,
+                       h->npix, h->x, h->valid, map_out, valid_out);
+    FX_HIP(hipGetLastError());
+  }
+  // n_valid via a deterministic count into the q buffer's first element
+  hipLaunchKernelGGL(k_count_valid, dim3((unsigned)kRedBlocks), dim3(kBlock), 0, s, h->npix,
+                     h->valid, h->partial);
+  hipLaunchKernelGGL(k_count_final, dim3(1), dim3(kBlock), 0, s, h->partial, h->sc, h->q);
+  FX_HIP(hipGetLastError());
+  PcgScalars sc;
+  double nvalid = 0.0;
+  FX_HIP(hipMemcpyAsync(&sc, h->sc, sizeof(sc), hipMemcpyDeviceToHost, s));
+  FX_HIP(hipMemcpyAsync(&nvalid, h->q, sizeof(double), hipMemcpyDeviceToHost, s));
+  std::vector<double> hist;
+  if (info && info->resid_history && !h->opt.no_early_exit) {
+    hist.resize(h->nhist);
+    FX_HIP(hipMemcpyAsync(hist.data(), h->hist, sizeof(double) * h->nhist, hipMemcpyDeviceToHost, s));
+  }
+  FX_HIP(hipStreamSynchronize(s));
+  if (info) {
+    info->iters = sc.iters;
+    info->stop_reason = sc.stop;
+    info->rel_resid = sc.rel;
+    info->n_valid = (int64_t)nvalid;
+    if (info->resid_history && !hist.empty())
+      std::memcpy(info->resid_history, hist.data(), sizeof(double) * (sc.iters + 1));
+  }
+  if (sc.stop == 2) return set_error(FURAX_EBREAKDOWN, "PCG breakdown (<p,Ap> or <r,z> not positive and finite)");
+  if (sc.stop == 0 && h->opt.rtol > 0.0) return set_error(FURAX_ENOTCONV, "PCG reached max_iter before rtol");
+  return FURAX_OK;
+}
+
+furax_status pcg_destroy(furax_pcg h) {
+  if (!h) return FURAX_OK;
+  if (h->mem) FX_HIP(hipFreeAsync(h->mem, h->s));
+  FX_HIP(hipStreamSynchronize(h->s));
+  delete h;
+  return FURAX_OK;
+}
+
+}  // namespace fx

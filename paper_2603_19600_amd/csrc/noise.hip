@@ -1,0 +1,392 @@
+// Inverse-noise weighting N^-1, block-diagonal over detectors.
+//
+//  * diagonal (HomothetyOperator / DiagonalOperator of Table 2): z = w_k y;
+//  * symmetric band-Toeplitz (SymmetricBandToeplitzOperator, Table 2, applied
+//    by the overlap-save method named in the paragraph after the table):
+//        z[i] = sum_{|tau| <= b-1, 0 <= i+tau < n} t[|tau|] y[i+tau].
+//
+// Overlap-save on gfx950: one workgroup owns one block of L = 2M consecutive
+// input samples of one detector (zero outside the detector's stream) and
+// produces the V = L - 2(b-1) outputs whose stencil lies inside the block.
+// The real block is packed as M complex values (even samples -> real part,
+// odd -> imaginary), transformed by a Stockham radix-4 FFT of length M held in
+// LDS (128 KB for M = 16384 FP32 or M = 8192 FP64), split into the length-L
+// real spectrum, multiplied by the kernel's spectrum -- which is real because
+// the kernel is symmetric -- re-packed and transformed back.  The split,
+// multiply and re-pack are one pass over (k, M-k) pairs.
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "common.h"
+
+namespace fx {
+
+template <typename T>
+struct C2 {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ C2<T> cadd(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ C2<T> csub(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ C2<T> cmulc(C2<T> a, C2<T> b) {  // a * conj(b)
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T>
+__device__ __forceinline__ C2<T> cscale(C2<T> a, T s) { return {a.x * s, a.y * s}; }
+
+// ---------------------------------------------------------------------------
+// Stockham autosort FFT of length M in LDS (decimation in time; radix 2 once
+// when log2 M is odd, then radix 4).  Each pass loads every butterfly's inputs
+// into registers, synchronises, and writes the outputs back to the same LDS
+// array, so one M-element buffer suffices.  tw[j] = exp(-2 pi i j / L) with
+// L = 2M, so the length-M twiddle W_M^j is tw[2j].  INV selects the inverse
+// (unnormalised) transform.
+// ---------------------------------------------------------------------------
+template <typename T, int M, int NT, bool INV>
+__device__ __forceinline__ void fft_lds(C2<T> *s, const C2<T> *__restrict__ tw) {
+  const int tid = threadIdx.x;
+  int Ns = 1;
+  if constexpr ((__builtin_ctz(M) & 1) != 0) {
+    constexpr int NB = M / 2;
+    constexpr int PER = (NB + NT - 1) / NT;
+    C2<T> v[PER][2];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      if (j < NB) {
+        v[q][0] = s[j];
+        v[q][1] = s[j + NB];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      if (j < NB) {
+        const C2<T> a0 = v[q][0], a1 = v[q][1];
+        s[2 * j] = cadd(a0, a1);
+        s[2 * j + 1] = csub(a0, a1);
+      }
+    }
+    __syncthreads();
+    Ns = 2;
+  }
+  constexpr int NB = M / 4;
+  constexpr int PER = (NB + NT - 1) / NT;
+  for (; Ns < M; Ns *= 4) {
+    C2<T> v[PER][4];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      if (j < NB) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[q][r] = s[j + r * NB];
+      }
+    }
+    __syncthreads();
+    const int tstep = 2 * (M / (4 * Ns));   // W_M^(k r M/(4 Ns)) = tw[2 k r M/(4 Ns)]
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      if (j < NB) {
+        const int k = j & (Ns - 1);
+        C2<T> a0 = v[q][0], a1 = v[q][1], a2 = v[q][2], a3 = v[q][3];
+        if (Ns > 1) {
+          const C2<T> w1 = tw[k * tstep], w2 = tw[2 * k * tstep], w3 = tw[3 * k * tstep];
+          if (INV) {
+            a1 = cmulc(a1, w1);
+            a2 = cmulc(a2, w2);
+            a3 = cmulc(a3, w3);
+          } else {
+            a1 = cmul(a1, w1);
+            a2 = cmul(a2, w2);
+            a3 = cmul(a3, w3);
+          }
+        }
+        const C2<T> t0 = cadd(a0, a2), t1 = csub(a0, a2);
+        const C2<T> t2 = cadd(a1, a3), t3 = csub(a1, a3);
+        // forward: y1 = t1 - i t3, y3 = t1 + i t3; inverse swaps them.
+        const C2<T> it3 = {-t3.y, t3.x};
+        const int d = (j - k) * 4 + k;
+        s[d] = cadd(t0, t2);
+        s[d + 2 * Ns] = csub(t0, t2);
+        s[d + Ns] = INV ? cadd(t1, it3) : csub(t1, it3);
+        s[d + 3 * Ns] = INV ? csub(t1, it3) : cadd(t1, it3);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Block index -> (detector, time block) with consecutive time blocks of one
+// detector kept on the same XCD (workgroups are dealt round-robin over the 8
+// XCDs), so the halo a block shares with its neighbours is read through the
+// same L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
+  const int64_t per = nblocks / 8;
+  if (per == 0 || bid >= per * 8) return bid;
+  return (bid % 8) * per + bid / 8;
+}
+
+template <typename T, int M, int NT>
+__global__ void __launch_bounds__(NT) k_overlap_save(const T *__restrict__ in, T *__restrict__ out,
+                                                     int64_t n_det, int64_t n, int32_t b,
+                                                     int64_t nblk, const T *__restrict__ spec,
+                                                     int64_t spec_stride,
+                                                     const C2<T> *__restrict__ tw) {
+  __shared__ C2<T> s[M];
+  constexpr int L = 2 * M;
+  const int V = L - 2 * (b - 1);
+  const int64_t bid = xcd_remap(blockIdx.x, (int64_t)gridDim.x);
+  const int64_t det = bid / nblk;
+  const int64_t blk = bid % nblk;
+  const int64_t s0 = blk * V - (b - 1);
+  const T *x = in + det * n;
+  const int tid = threadIdx.x;
+
+  for (int m = tid; m < M; m += NT) {
+    const int64_t g = s0 + 2 * m;
+    C2<T> v;
+    v.x = (g >= 0 && g < n) ? x[g] : (T)0;
+    v.y = (g + 1 >= 0 && g + 1 < n) ? x[g + 1] : (T)0;
+    s[m] = v;
+  }
+  __syncthreads();
+  fft_lds<T, M, NT, false>(s, tw);
+
+  const T *H = spec + det * spec_stride;   // H[0..M], already divided by M
+  for (int k = tid; k <= M / 2; k += NT) {
+    const int k2 = (M - k) & (M - 1);
+    const C2<T> z1 = s[k], z2 = s[k2];
+    C2<T> r1, r2;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int kk = h ? k2 : k;
+      const C2<T> za = h ? z2 : z1;
+      const C2<T> zb = h ? z1 : z2;               // Z[M - kk]
+      const C2<T> zc = {zb.x, -zb.y};             // conj(Z[M - kk])
+      const C2<T> E = cscale(cadd(za, zc), (T)0.5);
+      const C2<T> Dh = cscale(csub(za, zc), (T)0.5);
+      const C2<T> O = {Dh.y, -Dh.x};              // (Z[k] - conj Z[M-k]) / (2i)
+      const T Hk = H[kk], Hm = H[M - kk];
+      const T hp = (Hk + Hm) * (T)0.5, hm = (Hk - Hm) * (T)0.5;
+      const C2<T> W = tw[kk];                     // exp(-2 pi i kk / L)
+      const C2<T> A = cadd(cscale(E, hp), cscale(cmul(W, O), hm));
+      const C2<T> B = cadd(cscale(cmulc(E, W), hm), cscale(O, hp));
+      const C2<T> r = {A.x - B.y, A.y + B.x};     // A + i B
+      if (h) r2 = r; else r1 = r;
+    }
+    s[k] = r1;
+    if (k2 != k) s[k2] = r2;
+  }
+  __syncthreads();
+  fft_lds<T, M, NT, true>(s, tw);
+
+  T *z = out + det * n;
+  const int lo = b - 1, hi = b - 1 + V;
+  for (int m = tid; m < M; m += NT) {
+    const int e = 2 * m;
+    const C2<T> v = s[m];
+    if (e >= lo && e < hi && s0 + e < n) z[s0 + e] = v.x;
+    if (e + 1 >= lo && e + 1 < hi && s0 + e + 1 < n) z[s0 + e + 1] = v.y;
+  }
+}
+
+// Spectrum of the symmetric circular kernel of length L = 2M, divided by M:
+// H[k] = (t0 + 2 sum_{tau=1}^{b-1} t[tau] cos(2 pi k tau / L)) / M, k = 0..M.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_spectrum(const double *__restrict__ lags, int32_t b,
+                                                     int64_t lag_stride, int32_t M,
+                                                     const C2<double> *__restrict__ tw64,
+                                                     T *__restrict__ spec) {
+  const int64_t kern = blockIdx.y;
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k > M) return;
+  const double *t = lags + kern * lag_stride;
+  const int Lmask = 2 * M - 1;
+  double acc = 0.0;
+  for (int tau = b - 1; tau >= 1; --tau) acc += t[tau] * tw64[((int64_t)k * tau) & Lmask].x;
+  spec[kern * (int64_t)(M + 1) + k] = (T)((t[0] + 2.0 * acc) / (double)M);
+}
+
+__global__ void __launch_bounds__(kBlock) k_twiddles(int32_t L, C2<double> *tw64, C2<float> *tw32) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= L) return;
+  double s, c;
+  sincospi(2.0 * (double)j / (double)L, &s, &c);
+  tw64[j] = {c, -s};
+  if (tw32) tw32[j] = {(float)c, (float)-s};
+}
+
+template <typename T, int M, int NT>
+__global__ void __launch_bounds__(kBlock) k_diag(const T *__restrict__ in, T *__restrict__ out,
+                                                 int64_t n_det, int64_t n,
+                                                 const double *__restrict__ w) {
+  const int64_t total = n_det * n;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += stride)
+    out[i] = (T)w[i / n] * in[i];
+}
+
+// ---------------------------------------------------------------------------
+// Per-device twiddle tables (content-independent; kept until
+// furax_release_caches()).
+// ---------------------------------------------------------------------------
+struct TwTables {
+  C2<double> *tw64 = nullptr;
+  C2<float> *tw32 = nullptr;
+};
+static std::mutex g_tw_mu;
+static std::map<std::pair<int, int>, TwTables> g_tw;   // (device, L) -> tables
+
+static furax_status get_twiddles(int L, hipStream_t s, TwTables &out) {
+  int dev = 0;
+  FX_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_tw_mu);
+  auto it = g_tw.find({dev, L});
+  if (it != g_tw.end()) {
+    out = it->second;
+    return FURAX_OK;
+  }
+  TwTables t;
+  FX_HIP(hipMalloc(&t.tw64, sizeof(C2<double>) * L));
+  if (hipMalloc(&t.tw32, sizeof(C2<float>) * L) != hipSuccess) {
+    (void)hipFree(t.tw64);
+    return set_error(FURAX_ENOMEM, "twiddle table allocation failed");
+  }
+  hipLaunchKernelGGL(k_twiddles, dim3((L + kBlock - 1) / kBlock), dim3(kBlock), 0, s, L, t.tw64,
+                     t.tw32);
+  FX_HIP(hipGetLastError());
+  g_tw[{dev, L}] = t;
+  out = t;
+  return FURAX_OK;
+}
+
+void release_twiddles() {
+  std::lock_guard<std::mutex> lk(g_tw_mu);
+  for (auto &kv : g_tw) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(kv.first.first);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(kv.second.tw64);
+    (void)hipFree(kv.second.tw32);
+    (void)hipSetDevice(cur);
+  }
+  g_tw.clear();
+}
+
+// FFT half-length M used for a band of b lags in precision T.
+template <typename T>
+int os_half_length(int64_t b) {
+  const int64_t mmax = sizeof(T) == 4 ? 16384 : 8192;
+  int64_t m = 512;
+  while (m < 4 * (b - 1) && m < mmax) m *= 2;
+  return (int)m;
+}
+
+template <typename T>
+int64_t os_max_band() { return sizeof(T) == 4 ? 8192 : 4096; }
+template int64_t os_max_band<float>();
+template int64_t os_max_band<double>();
+
+// Spectrum buffer size for a noise model in precision T.
+template <typename T>
+size_t noise_workspace_bytes(const furax_noise *N) {
+  if (N->kind != 1) return 0;
+  const int M = os_half_length<T>(N->bandwidth);
+  const int64_t nk = N->toeplitz_stride ? N->n_det : 1;
+  return (size_t)nk * (M + 1) * sizeof(T);
+}
+template size_t noise_workspace_bytes<float>(const furax_noise *);
+template size_t noise_workspace_bytes<double>(const furax_noise *);
+
+// Compute the kernel spectrum into `spec` (noise_workspace_bytes<T> bytes).
+template <typename T>
+furax_status noise_prepare(const furax_noise *N, void *spec, hipStream_t s) {
+  if (N->kind != 1) return FURAX_OK;
+  const int M = os_half_length<T>(N->bandwidth);
+  TwTables tw;
+  FX_TRY(get_twiddles(2 * M, s, tw));
+  const int64_t nk = N->toeplitz_stride ? N->n_det : 1;
+  dim3 grid((M + 1 + kBlock - 1) / kBlock, (unsigned)nk);
+  hipLaunchKernelGGL(k_spectrum<T>, grid, dim3(kBlock), 0, s, N->toeplitz, (int32_t)N->bandwidth,
+                     N->toeplitz_stride, M, tw.tw64, static_cast<T *>(spec));
+  FX_HIP(hipGetLastError());
+  return FURAX_OK;
+}
+template furax_status noise_prepare<float>(const furax_noise *, void *, hipStream_t);
+template furax_status noise_prepare<double>(const furax_noise *, void *, hipStream_t);
+
+template <typename T, int M, int NT>
+static furax_status launch_os(const furax_noise *N, const T *in, T *out, const T *spec,
+                              const C2<T> *tw, hipStream_t s) {
+  const int b = (int)N->bandwidth;
+  const int64_t V = 2 * M - 2 * (int64_t)(b - 1);
+  const int64_t nblk = (N->n_samp + V - 1) / V;
+  const int64_t blocks = N->n_det * nblk;
+  const int64_t spec_stride = N->toeplitz_stride ? (M + 1) : 0;
+  hipLaunchKernelGGL((k_overlap_save<T, M, NT>), dim3((unsigned)blocks), dim3(NT), 0, s, in, out,
+                     N->n_det, N->n_samp, b, nblk, spec, spec_stride, tw);
+  FX_HIP(hipGetLastError());
+  return FURAX_OK;
+}
+
+// Apply N^-1 given a prepared spectrum (kind 1) or the diagonal weights (kind 0).
+template <typename T>
+furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *spec,
+                       hipStream_t s) {
+  if (N->n_samp == 0) return FURAX_OK;
+  if (N->kind == 0) {
+    const int64_t total = N->n_det * N->n_samp;
+    const int64_t blocks = std::min<int64_t>((total + kBlock - 1) / kBlock, 65536);
+    hipLaunchKernelGGL((k_diag<T, 0, 0>), dim3((unsigned)blocks), dim3(kBlock), 0, s, in, out,
+                       N->n_det, N->n_samp, N->inv_var);
+    FX_HIP(hipGetLastError());
+    return FURAX_OK;
+  }
+  const int M = os_half_length<T>(N->bandwidth);
+  TwTables tw;
+  FX_TRY(get_twiddles(2 * M, s, tw));
+  const T *sp = static_cast<const T *>(spec);
+  const C2<T> *t = reinterpret_cast<const C2<T> *>(sizeof(T) == 4 ? (const void *)tw.tw32
+                                                                  : (const void *)tw.tw64);
+  switch (M) {
+    case 512: return launch_os<T, 512, 128>(N, in, out, sp, t, s);
+    case 1024: return launch_os<T, 1024, 256>(N, in, out, sp, t, s);
+    case 2048: return launch_os<T, 2048, 512>(N, in, out, sp, t, s);
+    case 4096: return launch_os<T, 4096, 1024>(N, in, out, sp, t, s);
+    case 8192: return launch_os<T, 8192, 1024>(N, in, out, sp, t, s);
+    case 16384:
+      if constexpr (sizeof(T) == 4) return launch_os<T, 16384, 1024>(N, in, out, sp, t, s);
+      break;
+  }
+  return set_error(FURAX_EUNSUPPORTED, "no overlap-save instance for this band");
+}
+template furax_status noise_run<float>(const furax_noise *, const float *, float *, const void *,
+                                       hipStream_t);
+template furax_status noise_run<double>(const furax_noise *, const double *, double *,
+                                        const void *, hipStream_t);
+
+template <typename T>
+furax_status launch_noise(const furax_noise *N, const T *in, T *out, void *work,
+                          size_t work_bytes, hipStream_t s) {
+  if (N->kind == 1 && work_bytes < noise_workspace_bytes<T>(N))
+    return set_error(FURAX_EINVAL, "noise workspace too small");
+  FX_TRY(noise_prepare<T>(N, work, s));
+  return noise_run<T>(N, in, out, work, s);
+}
+template furax_status launch_noise<float>(const furax_noise *, const float *, float *, void *,
+                                          size_t, hipStream_t);
+template furax_status launch_noise<double>(const furax_noise *, const double *, double *, void *,
+                                           size_t, hipStream_t);
+
+}  // namespace fx
