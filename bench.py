@@ -1,0 +1,262 @@
+"""Benchmark: TOD samples/s per PCG iteration of P^T N^-1 P on one MI355X.
+
+A step is one block-Jacobi PCG iteration of the map-maker: q = P^T N^-1 P p
+(pointing expanded on the fly, overlap-save band-Toeplitz N^-1, scatter-add
+P^T) plus the FP64 vector updates and dot products.  Inputs are synthetic,
+seeded and resident in HBM before the timed region.
+
+Default workload: HEALPix nside 512, 256 detectors x 2^20 samples, FP64
+pointing/TOD, 1/f noise weighted by a band-Toeplitz of 4096 lags, ideal HWP at
+2 Hz.  The FP32 variant of the same workload (FP32 pointing, TOD and FFT,
+FP64 accumulation, dots and preconditioner) is measured beside it.
+
+Prints one JSON line (rank 0).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "TOD samples/s per PCG iter of P^T N^-1 P (FP32 vs FP64) + % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_inputs(w, dev):
+    import torch
+
+    from paper_2603_19600_amd import furax as fx
+    from paper_2603_19600_amd import synth
+
+    t0 = time.time()
+    pt = synth.pointing(w, device=dev, det_chunk=8)
+    hwp = (w.hwp_num, w.hwp_den, 0.0) if w.hwp else None
+    P = fx.Pointing(w.nside, pt.theta, pt.phi, pt.psi, hwp=hwp)
+    if w.noise == "band":
+        lags = torch.from_numpy(synth.toeplitz_lags(w)).to(dev)
+        N = fx.Noise("band", w.n_det, w.n_samp, lags=lags)
+    else:
+        N = fx.Noise("diag", w.n_det, w.n_samp,
+                     inv_var=torch.full((w.n_det,), 1.0 / w.sigma ** 2, dtype=torch.float64,
+                                        device=dev))
+    m_true = synth.sky_map(w, device=dev)
+    d = fx.pointing_apply(P, m_true)                       # signal (HIP path; bench only)
+    d += synth.noise(w, device=dev).to(d.dtype)
+    torch.cuda.synchronize()
+    log(f"{w.name}: inputs generated in {time.time() - t0:.1f} s")
+    return P, N, d
+
+
+def time_kernels(fx, P, N, d, reps=5):
+    """Average duration (ms) of each kernel of q = P^T N^-1 P p, with HIP events on
+    the stream the library launches on (torch's current stream)."""
+    import torch
+
+    dev = d.device
+    p = torch.randn(3, P.npix, dtype=torch.float64, device=dev)
+    y = torch.empty_like(d)
+    z = torch.empty_like(d)
+    q = torch.zeros(3, P.npix, dtype=torch.float64, device=dev)
+    out = {}
+
+    def run(name, fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / reps
+
+    run("pointing_apply", lambda: fx.pointing_apply(P, p, out=y))
+    run("noise_apply", lambda: fx.noise_apply(N, y, out=z))
+    run("pointing_transpose", lambda: fx.pointing_transpose(P, z, out=q, accumulate=True))
+    return out
+
+
+def kernel_bytes(P, N, esize):
+    """Algorithmic HBM bytes per launch of each kernel (what the kernel must move)."""
+    S = P.n_det * P.n_samp
+    map_b = 3 * P.npix * 8
+    return {
+        # theta, phi, psi in; TOD out; the FP64 map read once
+        "pointing_apply": S * (3 * esize + esize) + map_b,
+        # TOD in, TOD out
+        "noise_apply": S * 2 * esize,
+        # theta, phi, psi and TOD in; the FP64 accumulator read and written once
+        "pointing_transpose": S * (3 * esize + esize) + 2 * map_b,
+    }
+
+
+def run_pcg(fx, P, N, d, steps, warmup):
+    import torch
+
+    sess = fx.PCGSession(P, N, d, max_iter=steps + warmup, rtol=0.0, no_early_exit=True)
+    sess.iterate(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    sess.iterate(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    x, valid, info, st = sess.finish()
+    sess.close()
+    ms = e0.elapsed_time(e1) / steps
+    return ms, wall, info, x
+
+
+def measure(w, dev, steps, warmup, with_kernels=True):
+    import torch
+
+    from paper_2603_19600_amd import furax as fx
+
+    P, N, d = make_inputs(w, dev)
+    ms, wall, info, x = run_pcg(fx, P, N, d, steps, warmup)
+    S = w.n_det * w.n_samp
+    res = {"ms_per_step": ms, "value": S / (ms * 1e-3), "wall_s": wall, "iters": info.iters,
+           "rel_resid": info.rel_resid, "n_valid": info.n_valid}
+    log(f"{w.name}: {ms:.3f} ms/iter, {res['value']:.4g} samples/s, rel resid {info.rel_resid:.3e}")
+    if with_kernels:
+        esize = 8 if w.dtype == "f64" else 4
+        kt = time_kernels(fx, P, N, d)
+        kb = kernel_bytes(P, N, esize)
+        res["kernels"] = {k: {"ms": kt[k], "alg_bytes": kb[k],
+                              "GB_s": kb[k] / (kt[k] * 1e-3) / 1e9} for k in kt}
+        log("kernels: " + ", ".join(f"{k} {v['ms']:.3f} ms {v['GB_s']:.0f} GB/s"
+                                    for k, v in res["kernels"].items()))
+    del P, N, d, x
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(w, n_det, seconds_hint=20.0):
+    """The FP64 NumPy oracle's P^T N^-1 P on a detector prefix of the same workload."""
+    import numpy as np
+
+    from oracle import mapmaker as omm
+    from paper_2603_19600_amd import synth
+
+    pt = synth.pointing(w, n_det=n_det)
+    lags = synth.toeplitz_lags(w) if w.noise == "band" else None
+    hwp = (w.hwp_num, w.hwp_den, 0.0) if w.hwp else None
+    prob = omm.Problem(w.nside, pt.theta.double().numpy(), pt.phi.double().numpy(),
+                       pt.psi.double().numpy(), w.noise,
+                       inv_var=None if lags is not None else np.ones(n_det), lags=lags, hwp=hwp)
+    x = synth.sky_map(w).numpy()
+    t0 = time.perf_counter()
+    pix, c, s = prob.geometry()           # pointing is expanded at every application
+    omm.normal_apply(prob, pix, c, s, x)
+    dt = time.perf_counter() - t0
+    S = n_det * w.n_samp
+    return {"value": S / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"one application of P^T N^-1 P (FP64 NumPy oracle, pointing expanded, "
+                      f"FFT band-Toeplitz) on a {n_det}-detector x {w.n_samp}-sample prefix of "
+                      f"the workload, {dt:.1f} s",
+            "seconds": dt}
+
+
+def host_info():
+    info = {"nproc": os.cpu_count(), "machine": platform.machine()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name"):
+                info["cpu"] = ln.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    for k in ("OMP_NUM_THREADS", "MKL_NUM_THREADS", "OPENBLAS_NUM_THREADS"):
+        if k in os.environ:
+            info[k] = os.environ[k]
+    return info
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2, help="workload number (2, 3 or 5)")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 variant")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernels", action="store_true")
+    ap.add_argument("--cpu-dets", type=int, default=24)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the map-making path is built and measured on a single "
+              "MI355X (multi-GPU sharding by detector is a design note, not part of this build).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2603_19600_amd import synth
+
+    dev = torch.device("cuda:0")
+    w = synth.WORKLOADS[args.config]
+    primary = measure(w, dev, args.steps, args.warmup, not args.no_kernels)
+    fp32 = None
+    if not args.no_fp32 and w.dtype == "f64":
+        w32 = synth.WORKLOADS[3] if args.config == 2 else w.with_(dtype="f32")
+        fp32 = measure(w32, dev, args.steps, args.warmup, not args.no_kernels)
+
+    roofline = None
+    if "kernels" in primary:
+        name, k = max(primary["kernels"].items(), key=lambda kv: kv[1]["ms"])
+        roofline = {"bound": "hbm", "kernel": name, "achieved": k["GB_s"], "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": k["GB_s"] / HBM_PEAK_GBS, "traffic": None,
+                    "alg_bytes_per_launch": k["alg_bytes"], "ms_per_launch": k["ms"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.cpu_dets)
+        log(f"cpu baseline: {cpu['value']:.4g} samples/s ({cpu['seconds']:.1f} s)")
+
+    S = w.n_det * w.n_samp
+    line = {
+        "metric": METRIC,
+        "value": primary["value"],
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": primary["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": w.dtype,
+        "data": "synthetic (seeded spin+precession scan, random IQU sky, 1/f noise)",
+        "config": {"workload": w.name, "nside": w.nside, "n_det": w.n_det, "n_samp": w.n_samp,
+                   "samples": S, "noise": w.noise, "bandwidth": w.bandwidth, "hwp": w.hwp,
+                   "pcg_precision": w.dtype, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": primary.get("kernels"),
+        "fp32": None if fp32 is None else {
+            "workload": synth.WORKLOADS[3].name if args.config == 2 else w.name + "_f32",
+            "value": fp32["value"], "ms_per_step": fp32["ms_per_step"],
+            "kernels": fp32.get("kernels"), "speedup_vs_fp64": fp32["value"] / primary["value"]},
+        "host": host_info(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
