@@ -158,9 +158,9 @@ furax_status furax_pointing_apply(const furax_pointing *P, int32_t map_dt, const
   if (P->n_samp > 0 && (!map || !tod)) return set_error(FURAX_EINVAL, "NULL map or tod");
   if (P->dtype == FURAX_F32)
     return launch_pointing_apply<float>(pt_args<float>(P, nullptr), map, map_dt == FURAX_F64,
-                                        (float *)tod, stream);
-  return launch_pointing_apply<double>(pt_args<double>(P, nullptr), map, true, (double *)tod,
-                                       stream);
+                                        planar_layout(npix_of(P->nside)), (float *)tod, stream);
+  return launch_pointing_apply<double>(pt_args<double>(P, nullptr), map, true,
+                                       planar_layout(npix_of(P->nside)), (double *)tod, stream);
 }
 
 furax_status furax_pointing_transpose(const furax_pointing *P, int32_t tod_dt, const void *tod,
@@ -170,10 +170,12 @@ furax_status furax_pointing_transpose(const furax_pointing *P, int32_t tod_dt, c
   if (!map || (P->n_samp > 0 && !tod)) return set_error(FURAX_EINVAL, "NULL map or tod");
   if (!accumulate) FX_TRY(zero_async(map, sizeof(double) * 3 * npix_of(P->nside), stream));
   if (P->dtype == FURAX_F32)
-    return launch_pointing_transpose<float>(pt_args<float>(P, nullptr), (const float *)tod, map,
-                                            false, nullptr, stream);
-  return launch_pointing_transpose<double>(pt_args<double>(P, nullptr), (const double *)tod, map,
-                                           false, nullptr, stream);
+    return launch_scatter<float>(pt_args<float>(P, nullptr), (const float *)tod, nullptr, nullptr,
+                                 false, planar_layout(npix_of(P->nside)), map,
+                                 planar_layout(npix_of(P->nside)), stream);
+  return launch_scatter<double>(pt_args<double>(P, nullptr), (const double *)tod, nullptr, nullptr,
+                                false, planar_layout(npix_of(P->nside)), map,
+                                planar_layout(npix_of(P->nside)), stream);
 }
 
 furax_status furax_noise_apply(const furax_noise *N, int32_t dt, const void *tod_in,

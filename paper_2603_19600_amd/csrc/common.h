@@ -191,22 +191,47 @@ struct DevBuf {
   furax_status alloc(size_t bytes, hipStream_t s);
 };
 
+// Addressing of a Stokes map: element (c, pix) lives at base[c * cs + pix * ps].
+// Planar [3][npix] maps (the public layout) have cs = npix, ps = 1; the
+// solver's internal vectors are interleaved [npix][4] (cs = 1, ps = 4) so that
+// the three Stokes values of a pixel share one cache line.
+struct MapLayout {
+  int64_t cs;
+  int32_t ps;
+};
+inline MapLayout planar_layout(int64_t npix) { return {npix, 1}; }
+constexpr MapLayout kInterleaved = {1, 4};
+
+// Sample tiles: a workgroup owns `dets` detectors x `ts` consecutive samples
+// (ts a power of two), so that the waves of one CU sweep the same patch of
+// sky at the same time and share its map cache lines.
+struct Tiling {
+  int32_t dets, log2ts;
+  int64_t n_tb, n_dg;    // time blocks per detector, detector groups
+  __host__ __device__ int64_t blocks() const { return n_tb * n_dg; }
+};
+Tiling make_tiling(int64_t n_det, int64_t n_samp, int32_t nside, int64_t target_samples,
+                   int32_t min_log2ts);
+
 // Kernel-launch wrappers implemented in the individual translation units.
 template <typename T>
-furax_status launch_pointing_apply(const PtArgs<T> &a, const void *map, bool map_f64, T *tod,
-                                   hipStream_t s);
+furax_status launch_pointing_apply(const PtArgs<T> &a, const void *map, bool map_f64,
+                                   MapLayout ml, T *tod, hipStream_t s);
+// q(c, pix) += sum over samples of v (1, cos, sin) with
+//   v = g_k w_k tod[k,i]               when tod != null (w_det may be null: w = 1), or
+//   v = g_k w_k g_k (P p)[k,i]          when tod == null (fused diagonal normal operator;
+//                                        p read from pmap with layout pl).
+// Accumulation is privatised per tile in an LDS hash table of FP64 sums and
+// flushed with one FP64 global atomic per touched pixel and Stokes component.
 template <typename T>
-furax_status launch_pointing_transpose(const PtArgs<T> &a, const T *tod, double *map,
-                                       bool tod_scaled_by_w, const double *w_det,
-                                       hipStream_t s);
+furax_status launch_scatter(const PtArgs<T> &a, const T *tod, const double *w_det,
+                            const void *pmap, bool pmap_f64, MapLayout pl, double *q,
+                            MapLayout ql, hipStream_t s);
 template <typename T>
 furax_status launch_noise(const furax_noise *N, const T *in, T *out, void *work,
                           size_t work_bytes, hipStream_t s);
 template <typename T>
 size_t noise_workspace_bytes(const furax_noise *N);
-template <typename T>
-furax_status launch_fused_diag(const PtArgs<T> &a, const T *map_lo, const double *p,
-                               const double *w_det, double *q, hipStream_t s);
 
 furax_status zero_async(void *ptr, size_t bytes, hipStream_t s);
 

@@ -37,19 +37,15 @@ struct PcgScalars {
 
 __device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v - v == 0.0; }
 
-// partial[j*kRedBlocks + block] = sum over this block's range of a_j . b_j
-__global__ void __launch_bounds__(kBlock) k_dot2_partial(const double *__restrict__ a0,
-                                                         const double *__restrict__ b0,
-                                                         const double *__restrict__ a1,
-                                                         const double *__restrict__ b1,
-                                                         int64_t n, double *__restrict__ partial) {
-  double v[2] = {0.0, 0.0};
+// partial[block] = this block's share of <p, q>, p planar [3][npix], q interleaved [npix][4].
+__global__ void __launch_bounds__(kBlock) k_dot_pq(int64_t npix, const double *__restrict__ p,
+                                                   const double *__restrict__ q,
+                                                   double *__restrict__ partial) {
+  double v[1] = {0.0};
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-    v[0] += a0[i] * b0[i];
-    if (a1) v[1] += a1[i] * b1[i];
-  }
-  block_sum<2>(v, partial + blockIdx.x, kRedBlocks);
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npix; i += stride)
+    v[0] += p[i] * q[4 * i] + p[npix + i] * q[4 * i + 1] + p[2 * npix + i] * q[4 * i + 2];
+  block_sum<1>(v, partial + blockIdx.x, kRedBlocks);
 }
 
 // After the initial residual: partial[0] = <r,z>, partial[1] = <b,b>.
@@ -80,7 +76,7 @@ __global__ void __launch_bounds__(kBlock) k_pq_final(const double *__restrict__ 
   else sc->alpha = sc->rz / v[0];
 }
 
-// x += alpha p; r -= alpha q; z = Minv r; partials of <r,z> and <r,r>.
+// x += alpha p; r -= alpha q (q interleaved); z = Minv r; partials of <r,z> and <r,r>.
 __global__ void __launch_bounds__(kBlock) k_update1(int64_t npix, double *__restrict__ x,
                                                     double *__restrict__ r,
                                                     const double *__restrict__ p,
@@ -99,7 +95,7 @@ __global__ void __launch_bounds__(kBlock) k_update1(int64_t npix, double *__rest
     for (int c = 0; c < 3; ++c) {
       const int64_t j = c * npix + i;
       x[j] = x[j] + alpha * p[j];
-      rr[c] = r[j] - alpha * q[j];
+      rr[c] = r[j] - alpha * q[4 * i + c];
       r[j] = rr[c];
     }
     const double a = Mi[i], b = Mi[npix + i], cc = Mi[2 * npix + i];
@@ -137,28 +133,33 @@ __global__ void __launch_bounds__(kBlock) k_rz_final(const double *__restrict__ 
   }
 }
 
-// p = z + beta p (and its FP32 copy for the FP32 path).
-__global__ void __launch_bounds__(kBlock) k_update2(int64_t n, double *__restrict__ p,
+// p = z + beta p, and its interleaved gather copy pg in the path's precision.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_update2(int64_t npix, double *__restrict__ p,
                                                     const double *__restrict__ z,
-                                                    float *__restrict__ p32,
+                                                    T *__restrict__ pg,
                                                     const PcgScalars *__restrict__ sc) {
   if (sc->stop) return;
   const double beta = sc->beta;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-    const double v = z[i] + beta * p[i];
-    p[i] = v;
-    if (p32) p32[i] = (float)v;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npix; i += stride) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double v = z[c * npix + i] + beta * p[c * npix + i];
+      p[c * npix + i] = v;
+      pg[4 * i + c] = (T)v;
+    }
   }
 }
 
 // z = Minv r (initial), r = b, p = z, x = 0; partials of <r,z>, <b,b>.
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_init_vectors(int64_t npix, const double *__restrict__ b,
                                                          double *__restrict__ x,
                                                          double *__restrict__ r,
                                                          double *__restrict__ z,
                                                          double *__restrict__ p,
-                                                         float *__restrict__ p32,
+                                                         T *__restrict__ pg,
                                                          const double *__restrict__ Mi,
                                                          double *__restrict__ partial) {
   double v[2] = {0.0, 0.0};
@@ -179,19 +180,13 @@ __global__ void __launch_bounds__(kBlock) k_init_vectors(int64_t npix, const dou
     for (int c = 0; c < 3; ++c) {
       z[c * npix + i] = zz[c];
       p[c * npix + i] = zz[c];
-      if (p32) p32[c * npix + i] = (float)zz[c];
+      pg[4 * i + c] = (T)zz[c];
       v[0] += rr[c] * zz[c];
       v[1] += rr[c] * rr[c];
     }
+    pg[4 * i + 3] = (T)0;
   }
   block_sum<2>(v, partial + blockIdx.x, kRedBlocks);
-}
-
-__global__ void __launch_bounds__(kBlock) k_to_f32(int64_t n, const double *__restrict__ a,
-                                                   float *__restrict__ b) {
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
-    b[i] = (float)a[i];
 }
 
 __global__ void k_diag_weights(int64_t n_det, const double *__restrict__ inv_var,
@@ -212,23 +207,26 @@ static int64_t map_blocks(int64_t n) {
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct NormalLayout {
-  size_t spec = 0, y = 0, z = 0, p32 = 0, wdet = 0, total = 0;
+  size_t spec = 0, y = 0, z = 0, pg = 0, qi = 0, wdet = 0, total = 0;
 };
 
+// Workspace of the normal operator: per-detector diagonal weights, the band
+// kernel's spectrum and two TOD buffers (band noise), and the interleaved
+// gather copy of p and the interleaved FP64 accumulator of q.
 template <typename T>
 static NormalLayout normal_layout(const furax_pointing *P, const furax_noise *N) {
   NormalLayout L;
   size_t off = 0;
   const size_t tod = (size_t)P->n_det * P->n_samp * sizeof(T);
+  const int64_t npix = npix_of(P->nside);
   L.wdet = off; off += align256(sizeof(double) * P->n_det);
   if (N->kind == 1) {
     L.spec = off; off += align256(noise_workspace_bytes<T>(N));
     L.y = off; off += align256(tod);
     L.z = off; off += align256(tod);
   }
-  if (sizeof(T) == 4) {
-    L.p32 = off; off += align256(sizeof(float) * 3 * npix_of(P->nside));
-  }
+  L.pg = off; off += align256(sizeof(T) * 4 * npix);
+  L.qi = off; off += align256(sizeof(double) * 4 * npix);
   L.total = off;
   return L;
 }
@@ -256,21 +254,41 @@ static furax_status normal_prepare(NormalPlan<T> &pl, hipStream_t s) {
   return FURAX_OK;
 }
 
-// q = P^T N^-1 P p.  If p32 is given it is the FP32 copy of p (FP32 path).
+// q = P^T N^-1 P p with p given as its interleaved gather copy pg (precision T)
+// and q an interleaved [npix][4] FP64 accumulator (overwritten).
 template <typename T>
-static furax_status normal_run(const NormalPlan<T> &pl, const double *p, const float *p32,
-                               double *q, hipStream_t s) {
+static furax_status normal_run(const NormalPlan<T> &pl, const T *pg, double *q, hipStream_t s) {
   const double *w = reinterpret_cast<const double *>(pl.work + pl.L.wdet);
-  FX_TRY(zero_async(q, sizeof(double) * 3 * pl.npix, s));
-  const T *map_lo = nullptr;
-  if constexpr (sizeof(T) == 4) map_lo = p32;
-  if (pl.N->kind == 0) return launch_fused_diag<T>(pl.a, map_lo, p, w, q, s);
+  FX_TRY(zero_async(q, sizeof(double) * 4 * pl.npix, s));
+  constexpr bool f64 = sizeof(T) == 8;
+  if (pl.N->kind == 0)
+    return launch_scatter<T>(pl.a, nullptr, w, pg, f64, kInterleaved, q, kInterleaved, s);
   T *y = reinterpret_cast<T *>(pl.work + pl.L.y);
   T *z = reinterpret_cast<T *>(pl.work + pl.L.z);
-  if (map_lo) FX_TRY(launch_pointing_apply<T>(pl.a, map_lo, false, y, s));
-  else FX_TRY(launch_pointing_apply<T>(pl.a, p, true, y, s));
+  FX_TRY(launch_pointing_apply<T>(pl.a, pg, f64, kInterleaved, y, s));
   FX_TRY(noise_run<T>(pl.N, y, z, pl.work + pl.L.spec, s));
-  return launch_pointing_transpose<T>(pl.a, z, q, true, nullptr, s);
+  return launch_scatter<T>(pl.a, z, nullptr, nullptr, f64, kInterleaved, q, kInterleaved, s);
+}
+
+// planar FP64 [3][npix] -> interleaved [npix][4] of T (4th lane 0)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_to_interleaved(int64_t npix, const double *__restrict__ p,
+                                                           T *__restrict__ g) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npix; i += stride) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[4 * i + c] = (T)p[c * npix + i];
+    g[4 * i + 3] = (T)0;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_from_interleaved(int64_t npix, const double *__restrict__ qi,
+                                                             double *__restrict__ q) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npix; i += stride) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q[c * npix + i] = qi[4 * i + c];
+  }
 }
 
 int64_t normal_workspace_bytes(const furax_pointing *P, const furax_noise *N, int32_t prec) {
@@ -294,14 +312,15 @@ furax_status normal_apply_impl(const furax_pointing *P, const furax_noise *N, co
   }
   pl.work = static_cast<char *>(work);
   FX_TRY(normal_prepare<T>(pl, s));
-  float *p32 = nullptr;
-  if constexpr (sizeof(T) == 4) {
-    p32 = reinterpret_cast<float *>(pl.work + pl.L.p32);
-    const int64_t n = 3 * pl.npix;
-    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)map_blocks(n)), dim3(kBlock), 0, s, n, p, p32);
-    FX_HIP(hipGetLastError());
-  }
-  return normal_run<T>(pl, p, p32, q, s);
+  T *pg = reinterpret_cast<T *>(pl.work + pl.L.pg);
+  double *qi = reinterpret_cast<double *>(pl.work + pl.L.qi);
+  const unsigned nb = (unsigned)map_blocks(pl.npix);
+  hipLaunchKernelGGL(k_to_interleaved<T>, dim3(nb), dim3(kBlock), 0, s, pl.npix, p, pg);
+  FX_HIP(hipGetLastError());
+  FX_TRY(normal_run<T>(pl, pg, qi, s));
+  hipLaunchKernelGGL(k_from_interleaved, dim3(nb), dim3(kBlock), 0, s, pl.npix, qi, q);
+  FX_HIP(hipGetLastError());
+  return FURAX_OK;
 }
 template furax_status normal_apply_impl<float>(const furax_pointing *, const furax_noise *,
                                                const double *, double *, const uint8_t *, void *,
@@ -344,8 +363,8 @@ struct furax_pcg_state {
   int32_t precision = FURAX_F64;
   char *mem = nullptr;       // one stream-ordered allocation for everything
   size_t mem_bytes = 0;
-  double *x, *r, *z, *p, *q, *Minv, *partial, *hist;
-  float *p32;
+  double *x, *r, *z, *p, *q, *Minv, *partial, *hist;   // q: interleaved [npix][4]
+  void *pg;                                               // interleaved gather copy of p
   uint8_t *valid;
   fx::PcgScalars *sc;
   fx::NormalPlan<float> pl32;
@@ -373,10 +392,11 @@ static furax_status pcg_setup(furax_pcg_state *h, const void *tod) {
   const size_t vec = align256(sizeof(double) * 3 * npix);
   size_t off = 0;
   auto take = [&](size_t b) { size_t o = off; off += align256(b); return o; };
-  const size_t o_x = take(vec), o_r = take(vec), o_z = take(vec), o_p = take(vec), o_q = take(vec);
+  const size_t o_x = take(vec), o_r = take(vec), o_z = take(vec), o_p = take(vec);
+  const size_t o_q = take(sizeof(double) * 4 * npix);
   const size_t o_minv = take(sizeof(double) * 6 * npix);
   const size_t o_valid = take(npix);
-  const size_t o_p32 = take(sizeof(T) == 4 ? sizeof(float) * 3 * npix : 0);
+  const size_t o_pg = take(sizeof(T) * 4 * npix);
   const size_t o_part = take(sizeof(double) * 2 * kRedBlocks);
   const size_t o_sc = take(sizeof(PcgScalars));
   h->nhist = h->opt.max_iter + 1;
@@ -393,13 +413,13 @@ static furax_status pcg_setup(furax_pcg_state *h, const void *tod) {
   h->q = (double *)(m + o_q);
   h->Minv = (double *)(m + o_minv);
   h->valid = (uint8_t *)(m + o_valid);
-  h->p32 = sizeof(T) == 4 ? (float *)(m + o_p32) : nullptr;
+  h->pg = m + o_pg;
   h->partial = (double *)(m + o_part);
   h->sc = (PcgScalars *)(m + o_sc);
   h->hist = (double *)(m + o_hist);
   pl.work = m + o_work;
   // Before the first iteration the unaccumulated blocks M6 (6 planes) live in
-  // the adjacent p and q vectors (2 * vec >= 6 npix doubles) and the hit
+  // the adjacent p and q vectors (3 + 4 npix doubles >= 6 npix) and the hit
   // counts in x; both are consumed by the inversion before those vectors are
   // initialised.
   double *M6 = h->p;
@@ -421,16 +441,18 @@ static furax_status pcg_setup(furax_pcg_state *h, const void *tod) {
   FX_TRY(zero_async(b, sizeof(double) * 3 * npix, s));
   const T *d = static_cast<const T *>(tod);
   if (h->N.kind == 0) {
-    FX_TRY(launch_pointing_transpose<T>(pl.a, d, b, false, w, s));
+    FX_TRY(launch_scatter<T>(pl.a, d, w, nullptr, false, planar_layout(npix), b,
+                              planar_layout(npix), s));
   } else {
     T *zt = reinterpret_cast<T *>(pl.work + pl.L.z);
     FX_TRY(noise_run<T>(&h->N, d, zt, pl.work + pl.L.spec, s));
-    FX_TRY(launch_pointing_transpose<T>(pl.a, zt, b, false, nullptr, s));
+    FX_TRY(launch_scatter<T>(pl.a, zt, nullptr, nullptr, false, planar_layout(npix), b,
+                              planar_layout(npix), s));
   }
   // r = b (copied into r), x = 0, z = Minv r, p = z.  b lives in z; k_init_vectors
   // reads b[i] before writing z[i] for the same i, element by element.
-  hipLaunchKernelGGL(k_init_vectors, dim3((unsigned)kRedBlocks), dim3(kBlock), 0, s, npix, b, h->x,
-                     h->r, h->z, h->p, h->p32, h->Minv, h->partial);
+  hipLaunchKernelGGL(k_init_vectors<T>, dim3((unsigned)kRedBlocks), dim3(kBlock), 0, s, npix, b,
+                     h->x, h->r, h->z, h->p, static_cast<T *>(h->pg), h->Minv, h->partial);
   FX_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_init_final, dim3(1), dim3(kBlock), 0, s, h->partial, h->opt.rtol, h->sc,
                      h->hist);
@@ -441,21 +463,20 @@ static furax_status pcg_setup(furax_pcg_state *h, const void *tod) {
 template <typename T>
 static furax_status pcg_step(furax_pcg_state *h) {
   hipStream_t s = h->s;
-  const int64_t n3 = 3 * h->npix;
   NormalPlan<T> &pl = [&]() -> NormalPlan<T> & {
     if constexpr (sizeof(T) == 4) return h->pl32;
     else return h->pl64;
   }();
-  FX_TRY(normal_run<T>(pl, h->p, h->p32, h->q, s));
-  hipLaunchKernelGGL(k_dot2_partial, dim3((unsigned)kRedBlocks), dim3(kBlock), 0, s, h->p, h->q,
-                     (const double *)nullptr, (const double *)nullptr, n3, h->partial);
+  FX_TRY(normal_run<T>(pl, static_cast<const T *>(h->pg), h->q, s));
+  hipLaunchKernelGGL(k_dot_pq, dim3((unsigned)kRedBlocks), dim3(kBlock), 0, s, h->npix, h->p, h->q,
+                     h->partial);
   hipLaunchKernelGGL(k_pq_final, dim3(1), dim3(kBlock), 0, s, h->partial, h->sc);
   hipLaunchKernelGGL(k_update1, dim3((unsigned)kRedBlocks), dim3(kBlock), 0, s, h->npix, h->x,
                      h->r, h->p, h->q, h->Minv, h->z, h->sc, h->partial);
   hipLaunchKernelGGL(k_rz_final, dim3(1), dim3(kBlock), 0, s, h->partial, h->sc, h->hist,
                      h->nhist);
-  hipLaunchKernelGGL(k_update2, dim3((unsigned)map_blocks(n3)), dim3(kBlock), 0, s, n3, h->p, h->z,
-                     h->p32, h->sc);
+  hipLaunchKernelGGL(k_update2<T>, dim3((unsigned)map_blocks(h->npix)), dim3(kBlock), 0, s,
+                     h->npix, h->p, h->z, static_cast<T *>(h->pg), h->sc);
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }

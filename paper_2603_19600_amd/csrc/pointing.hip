@@ -62,143 +62,209 @@ furax_status zero_async(void *ptr, size_t bytes, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// Sample tiles.
+// ---------------------------------------------------------------------------
+Tiling make_tiling(int64_t n_det, int64_t n_samp, int32_t nside, int64_t target_samples,
+                   int32_t min_log2ts) {
+  Tiling t;
+  // At most 256 detectors per tile: with a +-1 deg focal plane they cover a
+  // patch a few tens of pixels wide, so a 64-sample stretch of all of them
+  // revisits each pixel ~10 times at nside 512.
+  t.dets = (int32_t)std::min<int64_t>(n_det, 256);
+  int32_t l2 = nside >= 1024 ? 5 : 6;
+  while (((int64_t)t.dets << l2) < target_samples && l2 < 10) ++l2;
+  l2 = std::max(l2, min_log2ts);
+  // never longer than the stream rounded up to a power of two
+  int32_t cap = 0;
+  while (((int64_t)1 << cap) < n_samp) ++cap;
+  t.log2ts = std::min(l2, cap);
+  t.n_tb = (n_samp + ((int64_t)1 << t.log2ts) - 1) >> t.log2ts;
+  t.n_dg = (n_det + t.dets - 1) / t.dets;
+  return t;
+}
+
+// Block index -> logical tile, keeping consecutive time blocks of one detector
+// group on the same XCD (workgroups are dealt round-robin over the 8 XCDs), so
+// the map lines a tile touches are likely already in that XCD's L2.
+__device__ __forceinline__ int64_t tile_of_block(int64_t bid, int64_t nblocks) {
+  const int64_t per = nblocks / 8;
+  if (per == 0 || bid >= per * 8) return bid;
+  return (bid % 8) * per + bid / 8;
+}
+
+template <typename MT>
+__device__ __forceinline__ void load_iqu(const MT *__restrict__ m, MapLayout l, int32_t pix,
+                                         MT &I, MT &Q, MT &U) {
+  const int64_t o = (int64_t)pix * l.ps;
+  I = m[o];
+  Q = m[o + l.cs];
+  U = m[o + 2 * l.cs];
+}
+
+// ---------------------------------------------------------------------------
 // P: tod[k,i] = g_k (I[p] + c Q[p] + s U[p]).
 // ---------------------------------------------------------------------------
+constexpr int kApplyThreads = 256;
+
 template <typename T, typename MT>
-__global__ void __launch_bounds__(kBlock) k_apply(PtArgs<T> a, const MT *__restrict__ map,
-                                                  int64_t npix, T *__restrict__ tod) {
-  const int64_t nch = chunks_per_det(a.n_samp);
-  const int64_t k = blockIdx.x / nch;
-  const int64_t base = (blockIdx.x % nch) * kChunk + threadIdx.x;
-  const T g = gain_of(a, k);
-#pragma unroll
-  for (int it = 0; it < kItems; ++it) {
-    const int64_t i = base + (int64_t)it * kBlock;
-    if (i >= a.n_samp) break;
+__global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *__restrict__ map,
+                                                         MapLayout ml, Tiling tl,
+                                                         T *__restrict__ tod) {
+  const int64_t tile = tile_of_block(blockIdx.x, tl.blocks());
+  const int64_t d0 = (tile / tl.n_tb) * tl.dets;
+  const int64_t t0 = (tile % tl.n_tb) << tl.log2ts;
+  const int32_t tsm = (1 << tl.log2ts) - 1;
+  const int32_t nsamp = tl.dets << tl.log2ts;
+  for (int32_t s = threadIdx.x; s < nsamp; s += kApplyThreads) {
+    const int64_t k = d0 + (s >> tl.log2ts);
+    const int64_t i = t0 + (s & tsm);
+    if (k >= a.n_det || i >= a.n_samp) continue;
     const Geom<T> gm = sample_geom(a, k, i);
     T y = 0;
     if (gm.pix >= 0) {
-      y = (T)map[gm.pix] + gm.c * (T)map[npix + gm.pix] + gm.s * (T)map[2 * npix + gm.pix];
-      y = g * y;
+      MT I, Q, U;
+      load_iqu(map, ml, gm.pix, I, Q, U);
+      y = (T)I + gm.c * (T)Q + gm.s * (T)U;
+      y = gain_of(a, k) * y;
     }
     tod[k * a.n_samp + i] = y;
   }
 }
 
 template <typename T>
-furax_status launch_pointing_apply(const PtArgs<T> &a, const void *map, bool map_f64, T *tod,
-                                   hipStream_t s) {
+furax_status launch_pointing_apply(const PtArgs<T> &a, const void *map, bool map_f64,
+                                   MapLayout ml, T *tod, hipStream_t s) {
   if (a.n_samp == 0) return FURAX_OK;
-  const int64_t npix = 12ll * a.nside * a.nside;
-  const int64_t blocks = a.n_det * chunks_per_det(a.n_samp);
+  const Tiling tl = make_tiling(a.n_det, a.n_samp, a.nside, 4096, 6);
   if (map_f64)
-    hipLaunchKernelGGL((k_apply<T, double>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a,
-                       static_cast<const double *>(map), npix, tod);
+    hipLaunchKernelGGL((k_apply<T, double>), dim3((unsigned)tl.blocks()), dim3(kApplyThreads), 0,
+                       s, a, static_cast<const double *>(map), ml, tl, tod);
   else
-    hipLaunchKernelGGL((k_apply<T, float>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a,
-                       static_cast<const float *>(map), npix, tod);
+    hipLaunchKernelGGL((k_apply<T, float>), dim3((unsigned)tl.blocks()), dim3(kApplyThreads), 0,
+                       s, a, static_cast<const float *>(map), ml, tl, tod);
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }
 template furax_status launch_pointing_apply<float>(const PtArgs<float> &, const void *, bool,
-                                                   float *, hipStream_t);
+                                                   MapLayout, float *, hipStream_t);
 template furax_status launch_pointing_apply<double>(const PtArgs<double> &, const void *, bool,
-                                                    double *, hipStream_t);
+                                                    MapLayout, double *, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// P^T: map[:, p] += g_k w_k d[k,i] (1, c, s), products in T, sums in FP64.
+// P^T scatter-add with LDS privatisation.
+//
+// Each workgroup owns one tile of samples and an open-addressing hash table
+// in LDS (kHashSlots pixel keys and three FP64 sums per slot).  A sample
+// claims its pixel's slot with a compare-and-swap on the key (linear
+// probing), then adds its three contributions with LDS FP64 atomics.  After
+// the tile, every occupied slot is flushed to the global map with FP64
+// atomics, so global atomic traffic falls from 3 per sample to 3 per distinct
+// pixel per tile.  A sample that finds no slot within kMaxProbe probes goes
+// straight to global memory, so the result never depends on the table size.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_transpose_atomic(PtArgs<T> a, const T *__restrict__ tod,
-                                                             int64_t npix, const double *w_det,
-                                                             double *__restrict__ map) {
-  const int64_t nch = chunks_per_det(a.n_samp);
-  const int64_t k = blockIdx.x / nch;
-  const int64_t base = (blockIdx.x % nch) * kChunk + threadIdx.x;
-  T g = gain_of(a, k);
-  if (w_det) g = g * (T)w_det[k];
-#pragma unroll
-  for (int it = 0; it < kItems; ++it) {
-    const int64_t i = base + (int64_t)it * kBlock;
-    if (i >= a.n_samp) break;
+constexpr int kHashSlots = 4096;        // 4096 x (4 + 24) B = 112 KB of LDS
+constexpr int kScatterThreads = 1024;
+constexpr int kMaxProbe = 64;
+constexpr int32_t kEmpty = -1;
+
+template <typename T, typename MT, bool FUSED>
+__global__ void __launch_bounds__(kScatterThreads)
+k_scatter(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_det,
+          const MT *__restrict__ pmap, MapLayout pl, Tiling tl, double *__restrict__ q,
+          MapLayout ql) {
+  __shared__ int32_t keys[kHashSlots];
+  __shared__ double acc[3][kHashSlots];
+  for (int h = threadIdx.x; h < kHashSlots; h += kScatterThreads) {
+    keys[h] = kEmpty;
+    acc[0][h] = 0.0;
+    acc[1][h] = 0.0;
+    acc[2][h] = 0.0;
+  }
+  __syncthreads();
+
+  const int64_t tile = tile_of_block(blockIdx.x, tl.blocks());
+  const int64_t d0 = (tile / tl.n_tb) * tl.dets;
+  const int64_t t0 = (tile % tl.n_tb) << tl.log2ts;
+  const int32_t tsm = (1 << tl.log2ts) - 1;
+  const int32_t nsamp = tl.dets << tl.log2ts;
+  volatile int32_t *vkeys = keys;
+  for (int32_t s = threadIdx.x; s < nsamp; s += kScatterThreads) {
+    const int64_t k = d0 + (s >> tl.log2ts);
+    const int64_t i = t0 + (s & tsm);
+    if (k >= a.n_det || i >= a.n_samp) continue;
     const Geom<T> gm = sample_geom(a, k, i);
     if (gm.pix < 0) continue;
-    const T v = g * tod[k * a.n_samp + i];
-    atomicAdd(&map[gm.pix], (double)v);
-    atomicAdd(&map[npix + gm.pix], (double)(v * gm.c));
-    atomicAdd(&map[2 * npix + gm.pix], (double)(v * gm.s));
+    const T g = gain_of(a, k);
+    T v;
+    if constexpr (FUSED) {
+      MT I, Q, U;
+      load_iqu(pmap, pl, gm.pix, I, Q, U);
+      const T y = g * ((T)I + gm.c * (T)Q + gm.s * (T)U);
+      v = g * ((T)w_det[k] * y);
+    } else {
+      v = g * tod[k * a.n_samp + i];
+      if (w_det) v = v * (T)w_det[k];
+    }
+    const double v0 = (double)v, v1 = (double)(v * gm.c), v2 = (double)(v * gm.s);
+    uint32_t h = ((uint32_t)gm.pix * 2654435761u) >> (32 - 12);   // 12 = log2(kHashSlots)
+    bool placed = false;
+    for (int probe = 0; probe < kMaxProbe; ++probe) {
+      int32_t cur = vkeys[h];
+      if (cur == kEmpty) cur = atomicCAS(&keys[h], kEmpty, gm.pix);
+      if (cur == kEmpty || cur == gm.pix) {
+        placed = true;
+        break;
+      }
+      h = (h + 1) & (kHashSlots - 1);
+    }
+    if (placed) {
+      atomicAdd(&acc[0][h], v0);
+      atomicAdd(&acc[1][h], v1);
+      atomicAdd(&acc[2][h], v2);
+    } else {
+      const int64_t o = (int64_t)gm.pix * ql.ps;
+      atomicAdd(&q[o], v0);
+      atomicAdd(&q[o + ql.cs], v1);
+      atomicAdd(&q[o + 2 * ql.cs], v2);
+    }
+  }
+  __syncthreads();
+  for (int h = threadIdx.x; h < kHashSlots; h += kScatterThreads) {
+    const int32_t key = keys[h];
+    if (key == kEmpty) continue;
+    const int64_t o = (int64_t)key * ql.ps;
+    atomicAdd(&q[o], acc[0][h]);
+    atomicAdd(&q[o + ql.cs], acc[1][h]);
+    atomicAdd(&q[o + 2 * ql.cs], acc[2][h]);
   }
 }
 
 template <typename T>
-furax_status launch_pointing_transpose(const PtArgs<T> &a, const T *tod, double *map,
-                                       bool /*tod_scaled_by_w*/, const double *w_det,
-                                       hipStream_t s) {
+furax_status launch_scatter(const PtArgs<T> &a, const T *tod, const double *w_det,
+                            const void *pmap, bool pmap_f64, MapLayout pl, double *q,
+                            MapLayout ql, hipStream_t s) {
   if (a.n_samp == 0) return FURAX_OK;
-  const int64_t npix = 12ll * a.nside * a.nside;
-  const int64_t blocks = a.n_det * chunks_per_det(a.n_samp);
-  hipLaunchKernelGGL(k_transpose_atomic<T>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a, tod,
-                     npix, w_det, map);
-  FX_HIP(hipGetLastError());
-  return FURAX_OK;
-}
-template furax_status launch_pointing_transpose<float>(const PtArgs<float> &, const float *,
-                                                       double *, bool, const double *,
-                                                       hipStream_t);
-template furax_status launch_pointing_transpose<double>(const PtArgs<double> &, const double *,
-                                                        double *, bool, const double *,
-                                                        hipStream_t);
-
-// ---------------------------------------------------------------------------
-// Fused q = P^T diag(w) P p for diagonal noise: one pass over the pointing.
-// map_lo is an FP32 copy of p for the FP32 path (null: read p in FP64).
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_fused_diag(PtArgs<T> a, const T *__restrict__ map_lo,
-                                                       const double *__restrict__ p, int64_t npix,
-                                                       const double *__restrict__ w_det,
-                                                       double *__restrict__ q) {
-  const int64_t nch = chunks_per_det(a.n_samp);
-  const int64_t k = blockIdx.x / nch;
-  const int64_t base = (blockIdx.x % nch) * kChunk + threadIdx.x;
-  const T g = gain_of(a, k);
-  const T w = (T)w_det[k];
-#pragma unroll
-  for (int it = 0; it < kItems; ++it) {
-    const int64_t i = base + (int64_t)it * kBlock;
-    if (i >= a.n_samp) break;
-    const Geom<T> gm = sample_geom(a, k, i);
-    if (gm.pix < 0) continue;
-    T y;
-    if (map_lo)
-      y = map_lo[gm.pix] + gm.c * map_lo[npix + gm.pix] + gm.s * map_lo[2 * npix + gm.pix];
-    else
-      y = (T)p[gm.pix] + gm.c * (T)p[npix + gm.pix] + gm.s * (T)p[2 * npix + gm.pix];
-    y = g * y;
-    const T v = g * (w * y);
-    atomicAdd(&q[gm.pix], (double)v);
-    atomicAdd(&q[npix + gm.pix], (double)(v * gm.c));
-    atomicAdd(&q[2 * npix + gm.pix], (double)(v * gm.s));
+  const Tiling tl = make_tiling(a.n_det, a.n_samp, a.nside, 8192, 6);
+  const dim3 grid((unsigned)tl.blocks()), blk(kScatterThreads);
+  if (tod) {
+    hipLaunchKernelGGL((k_scatter<T, double, false>), grid, blk, 0, s, a, tod, w_det,
+                       (const double *)nullptr, pl, tl, q, ql);
+  } else if (pmap_f64) {
+    hipLaunchKernelGGL((k_scatter<T, double, true>), grid, blk, 0, s, a, tod, w_det,
+                       static_cast<const double *>(pmap), pl, tl, q, ql);
+  } else {
+    hipLaunchKernelGGL((k_scatter<T, float, true>), grid, blk, 0, s, a, tod, w_det,
+                       static_cast<const float *>(pmap), pl, tl, q, ql);
   }
-}
-
-template <typename T>
-furax_status launch_fused_diag(const PtArgs<T> &a, const T *map_lo, const double *p,
-                               const double *w_det, double *q, hipStream_t s) {
-  if (a.n_samp == 0) return FURAX_OK;
-  const int64_t npix = 12ll * a.nside * a.nside;
-  const int64_t blocks = a.n_det * chunks_per_det(a.n_samp);
-  hipLaunchKernelGGL(k_fused_diag<T>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a, map_lo, p,
-                     npix, w_det, q);
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }
-template furax_status launch_fused_diag<float>(const PtArgs<float> &, const float *,
-                                               const double *, const double *, double *,
-                                               hipStream_t);
-template furax_status launch_fused_diag<double>(const PtArgs<double> &, const double *,
-                                                const double *, const double *, double *,
-                                                hipStream_t);
+template furax_status launch_scatter<float>(const PtArgs<float> &, const float *, const double *,
+                                            const void *, bool, MapLayout, double *, MapLayout,
+                                            hipStream_t);
+template furax_status launch_scatter<double>(const PtArgs<double> &, const double *,
+                                             const double *, const void *, bool, MapLayout,
+                                             double *, MapLayout, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Block-Jacobi accumulation: M_p += g^2 w_k (1,c,s)^T (1,c,s), hits_p += 1.
