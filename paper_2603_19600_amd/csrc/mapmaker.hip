@@ -207,12 +207,13 @@ static int64_t map_blocks(int64_t n) {
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct NormalLayout {
-  size_t spec = 0, y = 0, z = 0, pg = 0, qi = 0, wdet = 0, total = 0;
+  size_t spec = 0, y = 0, z = 0, pg = 0, qi = 0, wdet = 0, gpix = 0, gc = 0, gs = 0, total = 0;
 };
 
 // Workspace of the normal operator: per-detector diagonal weights, the band
 // kernel's spectrum and two TOD buffers (band noise), and the interleaved
-// gather copy of p and the interleaved FP64 accumulator of q.
+// gather copy of p and the interleaved FP64 accumulator of q; with band noise
+// also the transient per-sample geometry shared by P and P^T.
 template <typename T>
 static NormalLayout normal_layout(const furax_pointing *P, const furax_noise *N) {
   NormalLayout L;
@@ -224,6 +225,10 @@ static NormalLayout normal_layout(const furax_pointing *P, const furax_noise *N)
     L.spec = off; off += align256(noise_workspace_bytes<T>(N));
     L.y = off; off += align256(tod);
     L.z = off; off += align256(tod);
+    const size_t S = (size_t)P->n_det * P->n_samp;
+    L.gpix = off; off += align256(sizeof(int32_t) * S);
+    L.gc = off; off += align256(sizeof(T) * S);
+    L.gs = off; off += align256(sizeof(T) * S);
   }
   L.pg = off; off += align256(sizeof(T) * 4 * npix);
   L.qi = off; off += align256(sizeof(double) * 4 * npix);
@@ -265,9 +270,12 @@ static furax_status normal_run(const NormalPlan<T> &pl, const T *pg, double *q, 
     return launch_scatter<T>(pl.a, nullptr, w, pg, f64, kInterleaved, q, kInterleaved, s);
   T *y = reinterpret_cast<T *>(pl.work + pl.L.y);
   T *z = reinterpret_cast<T *>(pl.work + pl.L.z);
-  FX_TRY(launch_pointing_apply<T>(pl.a, pg, f64, kInterleaved, y, s));
+  const GeomCache<T> gc = {reinterpret_cast<int32_t *>(pl.work + pl.L.gpix),
+                           reinterpret_cast<T *>(pl.work + pl.L.gc),
+                           reinterpret_cast<T *>(pl.work + pl.L.gs)};
+  FX_TRY(launch_pointing_apply<T>(pl.a, pg, f64, kInterleaved, y, s, gc));
   FX_TRY(noise_run<T>(pl.N, y, z, pl.work + pl.L.spec, s));
-  return launch_scatter<T>(pl.a, z, nullptr, nullptr, f64, kInterleaved, q, kInterleaved, s);
+  return launch_scatter<T>(pl.a, z, nullptr, nullptr, f64, kInterleaved, q, kInterleaved, s, gc);
 }
 
 // planar FP64 [3][npix] -> interleaved [npix][4] of T (4th lane 0)

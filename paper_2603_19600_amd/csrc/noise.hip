@@ -43,86 +43,141 @@ template <typename T>
 __device__ __forceinline__ C2<T> cscale(C2<T> a, T s) { return {a.x * s, a.y * s}; }
 
 // ---------------------------------------------------------------------------
-// Stockham autosort FFT of length M in LDS (decimation in time; radix 2 once
-// when log2 M is odd, then radix 4).  Each pass loads every butterfly's inputs
-// into registers, synchronises, and writes the outputs back to the same LDS
-// array, so one M-element buffer suffices.  tw[j] = exp(-2 pi i j / L) with
-// L = 2M, so the length-M twiddle W_M^j is tw[2j].  INV selects the inverse
-// (unnormalised) transform.
+// Stockham autosort FFT of length M = 2^m in LDS, radix 16 in registers.
+//
+// Each pass loads every butterfly's R inputs (stride M/R) into registers,
+// synchronises, multiplies by the twiddles W_M^(r k M/(R Ns)), performs the
+// R-point DFT in registers and writes the R outputs at stride Ns, so one LDS
+// buffer suffices.  M = 16^a * f with f in {1, 2, 4, 8}: a radix-16 passes
+// then one or two radix-4 / radix-2 passes (16384 = 16^3 * 4 takes 4 passes
+// instead of 7 radix-4 ones).  The LDS index is padded by one element every
+// 16 (pad16) so that the stride-16 accesses of the first pass do not pile onto
+// a few banks.  tw[j] = exp(-2 pi i j / L), L = 2M, so W_M^x = tw[2x].  INV
+// selects the (unnormalised) inverse transform.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int pad16(int e) { return e + (e >> 4); }
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(C2<T> &a0, C2<T> &a1, C2<T> &a2, C2<T> &a3) {
+  const C2<T> t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  const C2<T> t2 = cadd(a1, a3), t3 = csub(a1, a3);
+  const C2<T> it3 = {-t3.y, t3.x};   // i t3
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = INV ? cadd(t1, it3) : csub(t1, it3);
+  a3 = INV ? csub(t1, it3) : cadd(t1, it3);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ C2<T> rot16(C2<T> a, int j) {
+  // a * W16^j (conjugated for the inverse), j in {1, 2, 3, 4, 6, 9}
+  constexpr T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173;
+  constexpr T h = (T)0.70710678118654752440;
+  const T sg = INV ? (T)1 : (T)-1;   // sign of the imaginary part of W16
+  C2<T> w;
+  switch (j) {
+    case 1: w = {c1, sg * s1}; break;
+    case 2: w = {h, sg * h}; break;
+    case 3: w = {s1, sg * c1}; break;
+    case 4: return INV ? C2<T>{-a.y, a.x} : C2<T>{a.y, -a.x};
+    case 6: w = {-h, sg * h}; break;
+    default: w = {-c1, -sg * s1}; break;   // j = 9
+  }
+  return cmul(a, w);
+}
+
+// In-place 16-point DFT: on return v[4 k1 + k2] holds X[k1 + 4 k2].
+template <typename T, bool INV>
+__device__ __forceinline__ void dft16(C2<T> (&v)[16]) {
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4<T, INV>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+  v[4 + 1] = rot16<T, INV>(v[4 + 1], 1);
+  v[4 + 2] = rot16<T, INV>(v[4 + 2], 2);
+  v[4 + 3] = rot16<T, INV>(v[4 + 3], 3);
+  v[8 + 1] = rot16<T, INV>(v[8 + 1], 2);
+  v[8 + 2] = rot16<T, INV>(v[8 + 2], 4);
+  v[8 + 3] = rot16<T, INV>(v[8 + 3], 6);
+  v[12 + 1] = rot16<T, INV>(v[12 + 1], 3);
+  v[12 + 2] = rot16<T, INV>(v[12 + 2], 6);
+  v[12 + 3] = rot16<T, INV>(v[12 + 3], 9);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) dft4<T, INV>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ C2<T> twiddle(C2<T> a, C2<T> w) {
+  return INV ? cmulc(a, w) : cmul(a, w);
+}
+
+template <typename T, int M, int NT, int R, bool INV>
+__device__ __forceinline__ void stockham_pass(C2<T> *s, const C2<T> *__restrict__ tw, int Ns) {
+  constexpr int NB = M / R;
+  constexpr int PER = (NB + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  C2<T> v[PER][R];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = tid + q * NT;
+    if (j < NB) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = s[pad16(j + r * NB)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = tid + q * NT;
+    if (j >= NB) continue;
+    const int k = j & (Ns - 1);
+    if (Ns > 1) {
+      const int b = 2 * k * (M / (R * Ns));
+      if constexpr (R == 16) {
+        const C2<T> w1 = tw[b], w2 = tw[2 * b], w4 = tw[4 * b], w8 = tw[8 * b];
+        const C2<T> w3 = cmul(w1, w2), w5 = cmul(w1, w4), w6 = cmul(w2, w4), w7 = cmul(w3, w4);
+        const C2<T> w[16] = {w1, w1, w2, w3, w4, w5, w6, w7, w8, cmul(w1, w8), cmul(w2, w8),
+                             cmul(w3, w8), cmul(w4, w8), cmul(w5, w8), cmul(w6, w8), cmul(w7, w8)};
+#pragma unroll
+        for (int r = 1; r < 16; ++r) v[q][r] = twiddle<T, INV>(v[q][r], w[r]);
+      } else {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = twiddle<T, INV>(v[q][r], tw[r * b]);
+      }
+    }
+    const int d = (j - k) * R + k;
+    if constexpr (R == 16) {
+      dft16<T, INV>(v[q]);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s[pad16(d + r * Ns)] = v[q][4 * (r & 3) + (r >> 2)];
+    } else if constexpr (R == 4) {
+      dft4<T, INV>(v[q][0], v[q][1], v[q][2], v[q][3]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s[pad16(d + r * Ns)] = v[q][r];
+    } else {
+      s[pad16(d)] = cadd(v[q][0], v[q][1]);
+      s[pad16(d + Ns)] = csub(v[q][0], v[q][1]);
+    }
+  }
+  __syncthreads();
+}
+
 template <typename T, int M, int NT, bool INV>
 __device__ __forceinline__ void fft_lds(C2<T> *s, const C2<T> *__restrict__ tw) {
-  const int tid = threadIdx.x;
+  constexpr int log2m = __builtin_ctz(M);
+  constexpr int n16 = log2m / 4;
+  constexpr int rem = M >> (4 * n16);
   int Ns = 1;
-  if constexpr ((__builtin_ctz(M) & 1) != 0) {
-    constexpr int NB = M / 2;
-    constexpr int PER = (NB + NT - 1) / NT;
-    C2<T> v[PER][2];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int j = tid + q * NT;
-      if (j < NB) {
-        v[q][0] = s[j];
-        v[q][1] = s[j + NB];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int j = tid + q * NT;
-      if (j < NB) {
-        const C2<T> a0 = v[q][0], a1 = v[q][1];
-        s[2 * j] = cadd(a0, a1);
-        s[2 * j + 1] = csub(a0, a1);
-      }
-    }
-    __syncthreads();
-    Ns = 2;
+  for (int p = 0; p < n16; ++p) {
+    stockham_pass<T, M, NT, 16, INV>(s, tw, Ns);
+    Ns *= 16;
   }
-  constexpr int NB = M / 4;
-  constexpr int PER = (NB + NT - 1) / NT;
-  for (; Ns < M; Ns *= 4) {
-    C2<T> v[PER][4];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int j = tid + q * NT;
-      if (j < NB) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) v[q][r] = s[j + r * NB];
-      }
-    }
-    __syncthreads();
-    const int tstep = 2 * (M / (4 * Ns));   // W_M^(k r M/(4 Ns)) = tw[2 k r M/(4 Ns)]
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int j = tid + q * NT;
-      if (j < NB) {
-        const int k = j & (Ns - 1);
-        C2<T> a0 = v[q][0], a1 = v[q][1], a2 = v[q][2], a3 = v[q][3];
-        if (Ns > 1) {
-          const C2<T> w1 = tw[k * tstep], w2 = tw[2 * k * tstep], w3 = tw[3 * k * tstep];
-          if (INV) {
-            a1 = cmulc(a1, w1);
-            a2 = cmulc(a2, w2);
-            a3 = cmulc(a3, w3);
-          } else {
-            a1 = cmul(a1, w1);
-            a2 = cmul(a2, w2);
-            a3 = cmul(a3, w3);
-          }
-        }
-        const C2<T> t0 = cadd(a0, a2), t1 = csub(a0, a2);
-        const C2<T> t2 = cadd(a1, a3), t3 = csub(a1, a3);
-        // forward: y1 = t1 - i t3, y3 = t1 + i t3; inverse swaps them.
-        const C2<T> it3 = {-t3.y, t3.x};
-        const int d = (j - k) * 4 + k;
-        s[d] = cadd(t0, t2);
-        s[d + 2 * Ns] = csub(t0, t2);
-        s[d + Ns] = INV ? cadd(t1, it3) : csub(t1, it3);
-        s[d + 3 * Ns] = INV ? csub(t1, it3) : cadd(t1, it3);
-      }
-    }
-    __syncthreads();
+  if constexpr (rem == 8) {
+    stockham_pass<T, M, NT, 4, INV>(s, tw, Ns);
+    stockham_pass<T, M, NT, 2, INV>(s, tw, Ns * 4);
+  } else if constexpr (rem == 4) {
+    stockham_pass<T, M, NT, 4, INV>(s, tw, Ns);
+  } else if constexpr (rem == 2) {
+    stockham_pass<T, M, NT, 2, INV>(s, tw, Ns);
   }
 }
 
@@ -142,7 +197,7 @@ __global__ void __launch_bounds__(NT) k_overlap_save(const T *__restrict__ in, T
                                                      int64_t nblk, const T *__restrict__ spec,
                                                      int64_t spec_stride,
                                                      const C2<T> *__restrict__ tw) {
-  __shared__ C2<T> s[M];
+  __shared__ C2<T> s[M + M / 16];
   constexpr int L = 2 * M;
   const int V = L - 2 * (b - 1);
   const int64_t bid = xcd_remap(blockIdx.x, (int64_t)gridDim.x);
@@ -157,7 +212,7 @@ __global__ void __launch_bounds__(NT) k_overlap_save(const T *__restrict__ in, T
     C2<T> v;
     v.x = (g >= 0 && g < n) ? x[g] : (T)0;
     v.y = (g + 1 >= 0 && g + 1 < n) ? x[g + 1] : (T)0;
-    s[m] = v;
+    s[pad16(m)] = v;
   }
   __syncthreads();
   fft_lds<T, M, NT, false>(s, tw);
@@ -165,7 +220,7 @@ __global__ void __launch_bounds__(NT) k_overlap_save(const T *__restrict__ in, T
   const T *H = spec + det * spec_stride;   // H[0..M], already divided by M
   for (int k = tid; k <= M / 2; k += NT) {
     const int k2 = (M - k) & (M - 1);
-    const C2<T> z1 = s[k], z2 = s[k2];
+    const C2<T> z1 = s[pad16(k)], z2 = s[pad16(k2)];
     C2<T> r1, r2;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -184,8 +239,8 @@ __global__ void __launch_bounds__(NT) k_overlap_save(const T *__restrict__ in, T
       const C2<T> r = {A.x - B.y, A.y + B.x};     // A + i B
       if (h) r2 = r; else r1 = r;
     }
-    s[k] = r1;
-    if (k2 != k) s[k2] = r2;
+    s[pad16(k)] = r1;
+    if (k2 != k) s[pad16(k2)] = r2;
   }
   __syncthreads();
   fft_lds<T, M, NT, true>(s, tw);
@@ -194,7 +249,7 @@ __global__ void __launch_bounds__(NT) k_overlap_save(const T *__restrict__ in, T
   const int lo = b - 1, hi = b - 1 + V;
   for (int m = tid; m < M; m += NT) {
     const int e = 2 * m;
-    const C2<T> v = s[m];
+    const C2<T> v = s[pad16(m)];
     if (e >= lo && e < hi && s0 + e < n) z[s0 + e] = v.x;
     if (e + 1 >= lo && e + 1 < hi && s0 + e + 1 < n) z[s0 + e + 1] = v.y;
   }
@@ -202,19 +257,29 @@ __global__ void __launch_bounds__(NT) k_overlap_save(const T *__restrict__ in, T
 
 // Spectrum of the symmetric circular kernel of length L = 2M, divided by M:
 // H[k] = (t0 + 2 sum_{tau=1}^{b-1} t[tau] cos(2 pi k tau / L)) / M, k = 0..M.
-template <typename T>
+// One wave per frequency k: the lanes split the lags, cos(2 pi k tau / L) is
+// read from the FP64 table at the exact integer phase (k tau) mod L, and the
+// lanes' partial sums are combined in a fixed order.
 __global__ void __launch_bounds__(kBlock) k_spectrum(const double *__restrict__ lags, int32_t b,
                                                      int64_t lag_stride, int32_t M,
                                                      const C2<double> *__restrict__ tw64,
-                                                     T *__restrict__ spec) {
+                                                     double *__restrict__ spec64,
+                                                     float *__restrict__ spec32) {
   const int64_t kern = blockIdx.y;
-  const int k = blockIdx.x * kBlock + threadIdx.x;
+  const int k = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (k > M) return;
   const double *t = lags + kern * lag_stride;
-  const int Lmask = 2 * M - 1;
+  const int64_t Lmask = 2 * M - 1;
   double acc = 0.0;
-  for (int tau = b - 1; tau >= 1; --tau) acc += t[tau] * tw64[((int64_t)k * tau) & Lmask].x;
-  spec[kern * (int64_t)(M + 1) + k] = (T)((t[0] + 2.0 * acc) / (double)M);
+  for (int tau = 1 + lane; tau < b; tau += 64) acc += t[tau] * tw64[((int64_t)k * tau) & Lmask].x;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) {
+    const double h = (t[0] + 2.0 * acc) / (double)M;
+    if (spec64) spec64[kern * (int64_t)(M + 1) + k] = h;
+    if (spec32) spec32[kern * (int64_t)(M + 1) + k] = (float)h;
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_twiddles(int32_t L, C2<double> *tw64, C2<float> *tw32) {
@@ -317,9 +382,12 @@ furax_status noise_prepare(const furax_noise *N, void *spec, hipStream_t s) {
   TwTables tw;
   FX_TRY(get_twiddles(2 * M, s, tw));
   const int64_t nk = N->toeplitz_stride ? N->n_det : 1;
-  dim3 grid((M + 1 + kBlock - 1) / kBlock, (unsigned)nk);
-  hipLaunchKernelGGL(k_spectrum<T>, grid, dim3(kBlock), 0, s, N->toeplitz, (int32_t)N->bandwidth,
-                     N->toeplitz_stride, M, tw.tw64, static_cast<T *>(spec));
+  constexpr int per_block = kBlock / 64;
+  dim3 grid((M + 1 + per_block - 1) / per_block, (unsigned)nk);
+  hipLaunchKernelGGL(k_spectrum, grid, dim3(kBlock), 0, s, N->toeplitz, (int32_t)N->bandwidth,
+                     N->toeplitz_stride, M, tw.tw64,
+                     sizeof(T) == 8 ? static_cast<double *>(spec) : nullptr,
+                     sizeof(T) == 4 ? static_cast<float *>(spec) : nullptr);
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }
@@ -360,11 +428,11 @@ furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *sp
   const C2<T> *t = reinterpret_cast<const C2<T> *>(sizeof(T) == 4 ? (const void *)tw.tw32
                                                                   : (const void *)tw.tw64);
   switch (M) {
-    case 512: return launch_os<T, 512, 128>(N, in, out, sp, t, s);
-    case 1024: return launch_os<T, 1024, 256>(N, in, out, sp, t, s);
-    case 2048: return launch_os<T, 2048, 512>(N, in, out, sp, t, s);
-    case 4096: return launch_os<T, 4096, 1024>(N, in, out, sp, t, s);
-    case 8192: return launch_os<T, 8192, 1024>(N, in, out, sp, t, s);
+    case 512: return launch_os<T, 512, 64>(N, in, out, sp, t, s);
+    case 1024: return launch_os<T, 1024, 64>(N, in, out, sp, t, s);
+    case 2048: return launch_os<T, 2048, 128>(N, in, out, sp, t, s);
+    case 4096: return launch_os<T, 4096, 256>(N, in, out, sp, t, s);
+    case 8192: return launch_os<T, 8192, 512>(N, in, out, sp, t, s);
     case 16384:
       if constexpr (sizeof(T) == 4) return launch_os<T, 16384, 1024>(N, in, out, sp, t, s);
       break;

@@ -92,6 +92,15 @@ __device__ __forceinline__ int64_t tile_of_block(int64_t bid, int64_t nblocks) {
   return (bid % 8) * per + bid / 8;
 }
 
+// 2 alpha_i for the tile's samples t0 .. t0 + 2^log2ts - 1, into LDS.
+template <typename T>
+__device__ __forceinline__ void fill_two_alpha(const PtArgs<T> &a, int64_t t0, int32_t log2ts,
+                                               double *ta, int nthreads) {
+  if (!a.hwp) return;
+  for (int t = threadIdx.x; t < (1 << log2ts); t += nthreads)
+    ta[t] = 2.0 * hwp_alpha(t0 + t, a.hwp_num_mod, a.hwp_den, a.hwp_phase0);
+}
+
 template <typename MT>
 __device__ __forceinline__ void load_iqu(const MT *__restrict__ m, MapLayout l, int32_t pix,
                                          MT &I, MT &Q, MT &U) {
@@ -105,21 +114,26 @@ __device__ __forceinline__ void load_iqu(const MT *__restrict__ m, MapLayout l, 
 // P: tod[k,i] = g_k (I[p] + c Q[p] + s U[p]).
 // ---------------------------------------------------------------------------
 constexpr int kApplyThreads = 256;
+constexpr int kMaxTileSamples = 1024;   // longest tile (2^10 samples per detector)
 
 template <typename T, typename MT>
 __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *__restrict__ map,
                                                          MapLayout ml, Tiling tl,
-                                                         T *__restrict__ tod) {
+                                                         T *__restrict__ tod, GeomCache<T> gc) {
+  __shared__ double ta[kMaxTileSamples];
   const int64_t tile = tile_of_block(blockIdx.x, tl.blocks());
   const int64_t d0 = (tile / tl.n_tb) * tl.dets;
   const int64_t t0 = (tile % tl.n_tb) << tl.log2ts;
   const int32_t tsm = (1 << tl.log2ts) - 1;
   const int32_t nsamp = tl.dets << tl.log2ts;
+  fill_two_alpha(a, t0, tl.log2ts, ta, kApplyThreads);
+  __syncthreads();
   for (int32_t s = threadIdx.x; s < nsamp; s += kApplyThreads) {
     const int64_t k = d0 + (s >> tl.log2ts);
     const int64_t i = t0 + (s & tsm);
     if (k >= a.n_det || i >= a.n_samp) continue;
-    const Geom<T> gm = sample_geom(a, k, i);
+    const int64_t off = k * a.n_samp + i;
+    const Geom<T> gm = sample_geom_ta(a, k, off, ta[s & tsm]);
     T y = 0;
     if (gm.pix >= 0) {
       MT I, Q, U;
@@ -127,28 +141,35 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *
       y = (T)I + gm.c * (T)Q + gm.s * (T)U;
       y = gain_of(a, k) * y;
     }
-    tod[k * a.n_samp + i] = y;
+    tod[off] = y;
+    if (gc.pix) {
+      gc.pix[off] = gm.pix;
+      gc.c[off] = gm.c;
+      gc.s[off] = gm.s;
+    }
   }
 }
 
 template <typename T>
 furax_status launch_pointing_apply(const PtArgs<T> &a, const void *map, bool map_f64,
-                                   MapLayout ml, T *tod, hipStream_t s) {
+                                   MapLayout ml, T *tod, hipStream_t s, GeomCache<T> gc) {
   if (a.n_samp == 0) return FURAX_OK;
   const Tiling tl = make_tiling(a.n_det, a.n_samp, a.nside, 4096, 6);
   if (map_f64)
     hipLaunchKernelGGL((k_apply<T, double>), dim3((unsigned)tl.blocks()), dim3(kApplyThreads), 0,
-                       s, a, static_cast<const double *>(map), ml, tl, tod);
+                       s, a, static_cast<const double *>(map), ml, tl, tod, gc);
   else
     hipLaunchKernelGGL((k_apply<T, float>), dim3((unsigned)tl.blocks()), dim3(kApplyThreads), 0,
-                       s, a, static_cast<const float *>(map), ml, tl, tod);
+                       s, a, static_cast<const float *>(map), ml, tl, tod, gc);
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }
 template furax_status launch_pointing_apply<float>(const PtArgs<float> &, const void *, bool,
-                                                   MapLayout, float *, hipStream_t);
+                                                   MapLayout, float *, hipStream_t,
+                                                   GeomCache<float>);
 template furax_status launch_pointing_apply<double>(const PtArgs<double> &, const void *, bool,
-                                                    MapLayout, double *, hipStream_t);
+                                                    MapLayout, double *, hipStream_t,
+                                                    GeomCache<double>);
 
 // ---------------------------------------------------------------------------
 // P^T scatter-add with LDS privatisation.
@@ -167,13 +188,16 @@ constexpr int kScatterThreads = 1024;
 constexpr int kMaxProbe = 64;
 constexpr int32_t kEmpty = -1;
 
-template <typename T, typename MT, bool FUSED>
+// MODE 0: v from tod, geometry recomputed; 1: fused diagonal normal operator;
+// 2: v from tod, geometry read from the cache written by the gather.
+template <typename T, typename MT, int MODE>
 __global__ void __launch_bounds__(kScatterThreads)
 k_scatter(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_det,
           const MT *__restrict__ pmap, MapLayout pl, Tiling tl, double *__restrict__ q,
-          MapLayout ql) {
+          MapLayout ql, GeomCache<T> gc) {
   __shared__ int32_t keys[kHashSlots];
   __shared__ double acc[3][kHashSlots];
+  __shared__ double ta[kMaxTileSamples];
   for (int h = threadIdx.x; h < kHashSlots; h += kScatterThreads) {
     keys[h] = kEmpty;
     acc[0][h] = 0.0;
@@ -187,22 +211,33 @@ k_scatter(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_d
   const int64_t t0 = (tile % tl.n_tb) << tl.log2ts;
   const int32_t tsm = (1 << tl.log2ts) - 1;
   const int32_t nsamp = tl.dets << tl.log2ts;
+  if constexpr (MODE != 2) fill_two_alpha(a, t0, tl.log2ts, ta, kScatterThreads);
+  __syncthreads();
   volatile int32_t *vkeys = keys;
   for (int32_t s = threadIdx.x; s < nsamp; s += kScatterThreads) {
     const int64_t k = d0 + (s >> tl.log2ts);
     const int64_t i = t0 + (s & tsm);
     if (k >= a.n_det || i >= a.n_samp) continue;
-    const Geom<T> gm = sample_geom(a, k, i);
-    if (gm.pix < 0) continue;
+    const int64_t off = k * a.n_samp + i;
+    Geom<T> gm;
+    if constexpr (MODE == 2) {
+      gm.pix = gc.pix[off];
+      if (gm.pix < 0) continue;
+      gm.c = gc.c[off];
+      gm.s = gc.s[off];
+    } else {
+      gm = sample_geom_ta(a, k, off, ta[s & tsm]);
+      if (gm.pix < 0) continue;
+    }
     const T g = gain_of(a, k);
     T v;
-    if constexpr (FUSED) {
+    if constexpr (MODE == 1) {
       MT I, Q, U;
       load_iqu(pmap, pl, gm.pix, I, Q, U);
       const T y = g * ((T)I + gm.c * (T)Q + gm.s * (T)U);
       v = g * ((T)w_det[k] * y);
     } else {
-      v = g * tod[k * a.n_samp + i];
+      v = g * tod[off];
       if (w_det) v = v * (T)w_det[k];
     }
     const double v0 = (double)v, v1 = (double)(v * gm.c), v2 = (double)(v * gm.s);
@@ -242,29 +277,33 @@ k_scatter(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_d
 template <typename T>
 furax_status launch_scatter(const PtArgs<T> &a, const T *tod, const double *w_det,
                             const void *pmap, bool pmap_f64, MapLayout pl, double *q,
-                            MapLayout ql, hipStream_t s) {
+                            MapLayout ql, hipStream_t s, GeomCache<T> gc) {
   if (a.n_samp == 0) return FURAX_OK;
   const Tiling tl = make_tiling(a.n_det, a.n_samp, a.nside, 8192, 6);
   const dim3 grid((unsigned)tl.blocks()), blk(kScatterThreads);
-  if (tod) {
-    hipLaunchKernelGGL((k_scatter<T, double, false>), grid, blk, 0, s, a, tod, w_det,
-                       (const double *)nullptr, pl, tl, q, ql);
+  if (tod && gc.pix) {
+    hipLaunchKernelGGL((k_scatter<T, double, 2>), grid, blk, 0, s, a, tod, w_det,
+                       (const double *)nullptr, pl, tl, q, ql, gc);
+  } else if (tod) {
+    hipLaunchKernelGGL((k_scatter<T, double, 0>), grid, blk, 0, s, a, tod, w_det,
+                       (const double *)nullptr, pl, tl, q, ql, gc);
   } else if (pmap_f64) {
-    hipLaunchKernelGGL((k_scatter<T, double, true>), grid, blk, 0, s, a, tod, w_det,
-                       static_cast<const double *>(pmap), pl, tl, q, ql);
+    hipLaunchKernelGGL((k_scatter<T, double, 1>), grid, blk, 0, s, a, tod, w_det,
+                       static_cast<const double *>(pmap), pl, tl, q, ql, gc);
   } else {
-    hipLaunchKernelGGL((k_scatter<T, float, true>), grid, blk, 0, s, a, tod, w_det,
-                       static_cast<const float *>(pmap), pl, tl, q, ql);
+    hipLaunchKernelGGL((k_scatter<T, float, 1>), grid, blk, 0, s, a, tod, w_det,
+                       static_cast<const float *>(pmap), pl, tl, q, ql, gc);
   }
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }
 template furax_status launch_scatter<float>(const PtArgs<float> &, const float *, const double *,
                                             const void *, bool, MapLayout, double *, MapLayout,
-                                            hipStream_t);
+                                            hipStream_t, GeomCache<float>);
 template furax_status launch_scatter<double>(const PtArgs<double> &, const double *,
                                              const double *, const void *, bool, MapLayout,
-                                             double *, MapLayout, hipStream_t);
+                                             double *, MapLayout, hipStream_t,
+                                             GeomCache<double>);
 
 // ---------------------------------------------------------------------------
 // Block-Jacobi accumulation: M_p += g^2 w_k (1,c,s)^T (1,c,s), hits_p += 1.

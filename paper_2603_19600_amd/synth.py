@@ -193,7 +193,18 @@ def boresight_rotations(w: Workload, i0: int, n: int, device) -> torch.Tensor:
     r_s = _rot("z", ws * t + float(ph[1]))
     r_50 = _rot("y", torch.tensor(math.radians(w.spin_angle_deg), dtype=torch.float64,
                                   device=device))
-    return r_a @ r_p @ r_45 @ r_s @ r_50
+    out = _mat3(_mat3(_mat3(_mat3(r_a, r_p), r_45), r_s), r_50)
+    return out
+
+
+def _mat3(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+    """Batched 3x3 product written out element by element (no BLAS call)."""
+    a, b = torch.broadcast_tensors(a, b) if a.dim() == b.dim() else (a, b)
+    rows = []
+    for i in range(3):
+        rows.append(torch.stack([a[..., i, 0] * b[..., 0, j] + a[..., i, 1] * b[..., 1, j]
+                                 + a[..., i, 2] * b[..., 2, j] for j in range(3)], -1))
+    return torch.stack(rows, -2)
 
 
 @dataclass
@@ -228,7 +239,8 @@ def pointing(w: Workload, det0: int = 0, n_det: Optional[int] = None, i0: int = 
         c1 = min(n_det, c0 + det_chunk)
         u = torch.stack([_rot("x", offs[j, 1]) @ _rot("y", offs[j, 0]) @ zhat
                          for j in range(c0, c1)]).to(device)            # [d, 3]
-        v = torch.einsum("tij,dj->dti", rot, u)                          # [d, t, 3]
+        v = torch.stack([rot[None, :, i, 0] * u[:, None, 0] + rot[None, :, i, 1] * u[:, None, 1]
+                         + rot[None, :, i, 2] * u[:, None, 2] for i in range(3)], -1)  # [d, t, 3]
         vz = v[..., 2].clamp(-1.0, 1.0)
         theta[c0:c1] = torch.arccos(vz).to(dt)
         ph = torch.atan2(v[..., 1], v[..., 0])
@@ -274,14 +286,17 @@ def white_lags(w: Workload) -> np.ndarray:
 
 
 def noise(w: Workload, det0: int = 0, n_det: Optional[int] = None, i0: int = 0,
-          n_samp: Optional[int] = None, device="cpu") -> torch.Tensor:
-    """Noise streams [n_det][n_samp] float64: white sigma, or 1/f shaped in Fourier space."""
+          n_samp: Optional[int] = None, device="cpu", shape_1f: bool = True) -> torch.Tensor:
+    """Noise streams [n_det][n_samp] float64: white sigma, or 1/f shaped in Fourier space.
+
+    shape_1f=False returns the white streams even for a 1/f workload (the
+    operators' cost does not depend on the data values)."""
     n_det = w.n_det - det0 if n_det is None else n_det
     n_samp = w.n_samp - i0 if n_samp is None else n_samp
     out = torch.empty(n_det, n_samp, dtype=torch.float64, device=device)
     cnt = torch.arange(i0, i0 + n_samp, dtype=torch.int64, device=device)
     shape = None
-    if w.noise == "band":
+    if w.noise == "band" and shape_1f:
         f = np.arange(n_samp // 2 + 1) * (w.fs / n_samp)
         p = psd(w, f)
         p[0] = p[1] if n_samp > 2 else p[0]
