@@ -137,22 +137,6 @@ __device__ __forceinline__ Geom<T> sample_geom(const PtArgs<T> &a, int64_t k, in
   return g;
 }
 
-// Same as sample_geom, with the HWP term 2 alpha_i supplied by the caller
-// (tiled kernels tabulate it once per tile in LDS).
-template <typename T>
-__device__ __forceinline__ Geom<T> sample_geom_ta(const PtArgs<T> &a, int64_t k, int64_t off,
-                                                  double two_alpha) {
-#pragma clang fp contract(off)
-  Geom<T> g;
-  g.pix = ang2pix_ring(a.nside, (double)a.theta[off], (double)a.phi[off]);
-  if (g.pix >= 0 && a.valid && !a.valid[g.pix]) g.pix = -1;
-  double pe = (double)a.psi[off];
-  if (a.dpsi) pe = pe + a.dpsi[k];
-  if (a.hwp) pe = pe + two_alpha;
-  weights(2.0 * pe, g.c, g.s);
-  return g;
-}
-
 template <typename T>
 __device__ __forceinline__ T gain_of(const PtArgs<T> &a, int64_t k) {
   return a.gain ? (T)a.gain[k] : (T)1;
@@ -222,6 +206,7 @@ constexpr MapLayout kInterleaved = {1, 4};
 // Sample tiles: a workgroup owns `dets` detectors x `ts` consecutive samples
 // (ts a power of two), so that the waves of one CU sweep the same patch of
 // sky at the same time and share its map cache lines.
+constexpr int kMaxTileDets = 256;   // detectors per tile (LDS tables are sized by it)
 struct Tiling {
   int32_t dets, log2ts;
   int64_t n_tb, n_dg;    // time blocks per detector, detector groups
@@ -231,33 +216,25 @@ Tiling make_tiling(int64_t n_det, int64_t n_samp, int32_t nside, int64_t target_
                    int32_t min_log2ts);
 
 // Kernel-launch wrappers implemented in the individual translation units.
-// Transient per-sample geometry of one operator application: pixel (-1 when
-// flagged) and polariser weights, [n_det][n_samp] planes.  Written by the
-// gather of P and read back by the scatter of P^T in the same application, so
-// the pointing is expanded once per application instead of twice.
-template <typename T>
-struct GeomCache {
-  int32_t *pix;
-  T *c, *s;
-};
-
+//
+// tod = P map.  With pix_out (a [n_det][n_samp] int32 plane) the pixel of
+// every sample, -1 when flagged, is written as well.
 template <typename T>
 furax_status launch_pointing_apply(const PtArgs<T> &a, const void *map, bool map_f64,
                                    MapLayout ml, T *tod, hipStream_t s,
-                                   GeomCache<T> cache = {nullptr, nullptr, nullptr});
+                                   int32_t *pix_out = nullptr);
 // q(c, pix) += sum over samples of v (1, cos, sin) with
 //   v = g_k w_k tod[k,i]               when tod != null (w_det may be null: w = 1), or
 //   v = g_k w_k g_k (P p)[k,i]          when tod == null (fused diagonal normal operator;
 //                                        p read from pmap with layout pl).
+// With pix_in (tod != null), the pixels are read from that plane (written by
+// launch_pointing_apply over the same pointing) instead of being recomputed.
 // Accumulation is privatised per tile in an LDS hash table of FP64 sums and
 // flushed with one FP64 global atomic per touched pixel and Stokes component.
-// With a cache (tod != null), the pixels and weights are read from it instead
-// of being recomputed from the pointing.
 template <typename T>
 furax_status launch_scatter(const PtArgs<T> &a, const T *tod, const double *w_det,
                             const void *pmap, bool pmap_f64, MapLayout pl, double *q,
-                            MapLayout ql, hipStream_t s,
-                            GeomCache<T> cache = {nullptr, nullptr, nullptr});
+                            MapLayout ql, hipStream_t s, const int32_t *pix_in = nullptr);
 template <typename T>
 furax_status launch_noise(const furax_noise *N, const T *in, T *out, void *work,
                           size_t work_bytes, hipStream_t s);

@@ -77,11 +77,16 @@ __global__ void __launch_bounds__(kBlock) k_pq_final(const double *__restrict__ 
 }
 
 // x += alpha p; r -= alpha q (q interleaved); z = Minv r; partials of <r,z> and <r,r>.
+// The operator kernels do not flag samples of invalid pixels; q there holds
+// contributions that flagging would have dropped, so r is kept at 0 on invalid
+// pixels (p, z and Minv are 0 there, so the valid pixels see exactly the
+// flagged operator).
 __global__ void __launch_bounds__(kBlock) k_update1(int64_t npix, double *__restrict__ x,
                                                     double *__restrict__ r,
                                                     const double *__restrict__ p,
                                                     const double *__restrict__ q,
                                                     const double *__restrict__ Mi,
+                                                    const uint8_t *__restrict__ valid,
                                                     double *__restrict__ z,
                                                     const PcgScalars *__restrict__ sc,
                                                     double *__restrict__ partial) {
@@ -91,11 +96,12 @@ __global__ void __launch_bounds__(kBlock) k_update1(int64_t npix, double *__rest
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npix; i += stride) {
     double rr[3];
+    const bool ok = valid[i] != 0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int64_t j = c * npix + i;
       x[j] = x[j] + alpha * p[j];
-      rr[c] = r[j] - alpha * q[4 * i + c];
+      rr[c] = ok ? r[j] - alpha * q[4 * i + c] : 0.0;
       r[j] = rr[c];
     }
     const double a = Mi[i], b = Mi[npix + i], cc = Mi[2 * npix + i];
@@ -152,9 +158,11 @@ __global__ void __launch_bounds__(kBlock) k_update2(int64_t npix, double *__rest
   }
 }
 
-// z = Minv r (initial), r = b, p = z, x = 0; partials of <r,z>, <b,b>.
+// z = Minv r (initial), r = b on valid pixels (0 elsewhere), p = z, x = 0;
+// partials of <r,z>, <b,b>.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_init_vectors(int64_t npix, const double *__restrict__ b,
+                                                         const uint8_t *__restrict__ valid,
                                                          double *__restrict__ x,
                                                          double *__restrict__ r,
                                                          double *__restrict__ z,
@@ -166,9 +174,10 @@ __global__ void __launch_bounds__(kBlock) k_init_vectors(int64_t npix, const dou
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npix; i += stride) {
     double rr[3];
+    const bool ok = valid[i] != 0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      rr[c] = b[c * npix + i];
+      rr[c] = ok ? b[c * npix + i] : 0.0;
       r[c * npix + i] = rr[c];
       x[c * npix + i] = 0.0;
     }
@@ -207,13 +216,14 @@ static int64_t map_blocks(int64_t n) {
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct NormalLayout {
-  size_t spec = 0, y = 0, z = 0, pg = 0, qi = 0, wdet = 0, gpix = 0, gc = 0, gs = 0, total = 0;
+  size_t spec = 0, y = 0, z = 0, pg = 0, qi = 0, wdet = 0, gpix = 0, total = 0;
 };
 
 // Workspace of the normal operator: per-detector diagonal weights, the band
 // kernel's spectrum and two TOD buffers (band noise), and the interleaved
 // gather copy of p and the interleaved FP64 accumulator of q; with band noise
-// also the transient per-sample geometry shared by P and P^T.
+// also the per-sample pixel plane that P writes and P^T reads back, so the
+// pointing is pixelised once per application.
 template <typename T>
 static NormalLayout normal_layout(const furax_pointing *P, const furax_noise *N) {
   NormalLayout L;
@@ -225,10 +235,7 @@ static NormalLayout normal_layout(const furax_pointing *P, const furax_noise *N)
     L.spec = off; off += align256(noise_workspace_bytes<T>(N));
     L.y = off; off += align256(tod);
     L.z = off; off += align256(tod);
-    const size_t S = (size_t)P->n_det * P->n_samp;
-    L.gpix = off; off += align256(sizeof(int32_t) * S);
-    L.gc = off; off += align256(sizeof(T) * S);
-    L.gs = off; off += align256(sizeof(T) * S);
+    L.gpix = off; off += align256(sizeof(int32_t) * (size_t)P->n_det * P->n_samp);
   }
   L.pg = off; off += align256(sizeof(T) * 4 * npix);
   L.qi = off; off += align256(sizeof(double) * 4 * npix);
@@ -270,32 +277,35 @@ static furax_status normal_run(const NormalPlan<T> &pl, const T *pg, double *q, 
     return launch_scatter<T>(pl.a, nullptr, w, pg, f64, kInterleaved, q, kInterleaved, s);
   T *y = reinterpret_cast<T *>(pl.work + pl.L.y);
   T *z = reinterpret_cast<T *>(pl.work + pl.L.z);
-  const GeomCache<T> gc = {reinterpret_cast<int32_t *>(pl.work + pl.L.gpix),
-                           reinterpret_cast<T *>(pl.work + pl.L.gc),
-                           reinterpret_cast<T *>(pl.work + pl.L.gs)};
-  FX_TRY(launch_pointing_apply<T>(pl.a, pg, f64, kInterleaved, y, s, gc));
+  int32_t *pix = reinterpret_cast<int32_t *>(pl.work + pl.L.gpix);
+  FX_TRY(launch_pointing_apply<T>(pl.a, pg, f64, kInterleaved, y, s, pix));
   FX_TRY(noise_run<T>(pl.N, y, z, pl.work + pl.L.spec, s));
-  return launch_scatter<T>(pl.a, z, nullptr, nullptr, f64, kInterleaved, q, kInterleaved, s, gc);
+  return launch_scatter<T>(pl.a, z, nullptr, nullptr, f64, kInterleaved, q, kInterleaved, s, pix);
 }
 
-// planar FP64 [3][npix] -> interleaved [npix][4] of T (4th lane 0)
+// planar FP64 [3][npix] -> interleaved [npix][4] of T (4th lane 0), zero on
+// pixels with valid = 0 (when valid is given).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_to_interleaved(int64_t npix, const double *__restrict__ p,
+                                                           const uint8_t *__restrict__ valid,
                                                            T *__restrict__ g) {
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npix; i += stride) {
+    const bool ok = !valid || valid[i];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) g[4 * i + c] = (T)p[c * npix + i];
+    for (int c = 0; c < 3; ++c) g[4 * i + c] = ok ? (T)p[c * npix + i] : (T)0;
     g[4 * i + 3] = (T)0;
   }
 }
 
 __global__ void __launch_bounds__(kBlock) k_from_interleaved(int64_t npix, const double *__restrict__ qi,
+                                                             const uint8_t *__restrict__ valid,
                                                              double *__restrict__ q) {
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npix; i += stride) {
+    const bool ok = !valid || valid[i];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) q[c * npix + i] = qi[4 * i + c];
+    for (int c = 0; c < 3; ++c) q[c * npix + i] = ok ? qi[4 * i + c] : 0.0;
   }
 }
 
@@ -310,7 +320,10 @@ furax_status normal_apply_impl(const furax_pointing *P, const furax_noise *N, co
   NormalPlan<T> pl;
   pl.P = P;
   pl.N = N;
-  pl.a = pt_args<T>(P, valid);
+  // Flagging the samples of invalid pixels is done in the map domain: p is
+  // zeroed there on input (so those samples read 0) and q on output (so what
+  // they scatter is dropped), which is the flagged operator exactly.
+  pl.a = pt_args<T>(P, nullptr);
   pl.L = normal_layout<T>(P, N);
   pl.npix = npix_of(P->nside);
   DevBuf own;
@@ -323,10 +336,10 @@ furax_status normal_apply_impl(const furax_pointing *P, const furax_noise *N, co
   T *pg = reinterpret_cast<T *>(pl.work + pl.L.pg);
   double *qi = reinterpret_cast<double *>(pl.work + pl.L.qi);
   const unsigned nb = (unsigned)map_blocks(pl.npix);
-  hipLaunchKernelGGL(k_to_interleaved<T>, dim3(nb), dim3(kBlock), 0, s, pl.npix, p, pg);
+  hipLaunchKernelGGL(k_to_interleaved<T>, dim3(nb), dim3(kBlock), 0, s, pl.npix, p, valid, pg);
   FX_HIP(hipGetLastError());
   FX_TRY(normal_run<T>(pl, pg, qi, s));
-  hipLaunchKernelGGL(k_from_interleaved, dim3(nb), dim3(kBlock), 0, s, pl.npix, qi, q);
+  hipLaunchKernelGGL(k_from_interleaved, dim3(nb), dim3(kBlock), 0, s, pl.npix, qi, valid, q);
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }
@@ -443,8 +456,10 @@ static furax_status pcg_setup(furax_pcg_state *h, const void *tod) {
   FX_TRY(launch_bj_invert(npix, M6, hits, h->opt.rcond_min, h->opt.min_hits, h->opt.valid_in,
                           h->Minv, h->valid, nullptr, s));
 
-  // Right-hand side b = P^T N^-1 d with samples in invalid pixels flagged; b -> z buffer.
-  pl.a = pt_args<T>(&h->P, h->valid);
+  // Right-hand side b = P^T N^-1 d into the z buffer.  Samples in invalid
+  // pixels only add to b on those pixels, which k_init_vectors drops: that is
+  // b with those samples flagged.  The iterations flag the same way (p is 0 on
+  // invalid pixels and r is kept at 0 there), so pl.a carries no mask.
   double *b = h->z;
   FX_TRY(zero_async(b, sizeof(double) * 3 * npix, s));
   const T *d = static_cast<const T *>(tod);
@@ -460,7 +475,7 @@ static furax_status pcg_setup(furax_pcg_state *h, const void *tod) {
   // r = b (copied into r), x = 0, z = Minv r, p = z.  b lives in z; k_init_vectors
   // reads b[i] before writing z[i] for the same i, element by element.
   hipLaunchKernelGGL(k_init_vectors<T>, dim3((unsigned)kRedBlocks), dim3(kBlock), 0, s, npix, b,
-                     h->x, h->r, h->z, h->p, static_cast<T *>(h->pg), h->Minv, h->partial);
+                     h->valid, h->x, h->r, h->z, h->p, static_cast<T *>(h->pg), h->Minv, h->partial);
   FX_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_init_final, dim3(1), dim3(kBlock), 0, s, h->partial, h->opt.rtol, h->sc,
                      h->hist);
@@ -480,7 +495,7 @@ static furax_status pcg_step(furax_pcg_state *h) {
                      h->partial);
   hipLaunchKernelGGL(k_pq_final, dim3(1), dim3(kBlock), 0, s, h->partial, h->sc);
   hipLaunchKernelGGL(k_update1, dim3((unsigned)kRedBlocks), dim3(kBlock), 0, s, h->npix, h->x,
-                     h->r, h->p, h->q, h->Minv, h->z, h->sc, h->partial);
+                     h->r, h->p, h->q, h->Minv, h->valid, h->z, h->sc, h->partial);
   hipLaunchKernelGGL(k_rz_final, dim3(1), dim3(kBlock), 0, s, h->partial, h->sc, h->hist,
                      h->nhist);
   hipLaunchKernelGGL(k_update2<T>, dim3((unsigned)map_blocks(h->npix)), dim3(kBlock), 0, s,

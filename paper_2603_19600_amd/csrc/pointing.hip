@@ -70,7 +70,7 @@ Tiling make_tiling(int64_t n_det, int64_t n_samp, int32_t nside, int64_t target_
   // At most 256 detectors per tile: with a +-1 deg focal plane they cover a
   // patch a few tens of pixels wide, so a 64-sample stretch of all of them
   // revisits each pixel ~10 times at nside 512.
-  t.dets = (int32_t)std::min<int64_t>(n_det, 256);
+  t.dets = (int32_t)std::min<int64_t>(n_det, kMaxTileDets);
   int32_t l2 = nside >= 1024 ? 5 : 6;
   while (((int64_t)t.dets << l2) < target_samples && l2 < 10) ++l2;
   l2 = std::max(l2, min_log2ts);
@@ -92,84 +92,194 @@ __device__ __forceinline__ int64_t tile_of_block(int64_t bid, int64_t nblocks) {
   return (bid % 8) * per + bid / 8;
 }
 
-// 2 alpha_i for the tile's samples t0 .. t0 + 2^log2ts - 1, into LDS.
-template <typename T>
-__device__ __forceinline__ void fill_two_alpha(const PtArgs<T> &a, int64_t t0, int32_t log2ts,
-                                               double *ta, int nthreads) {
-  if (!a.hwp) return;
-  for (int t = threadIdx.x; t < (1 << log2ts); t += nthreads)
-    ta[t] = 2.0 * hwp_alpha(t0 + t, a.hwp_num_mod, a.hwp_den, a.hwp_phase0);
+
+// Samples per thread whose memory traffic is issued together.  A sample's
+// work is a chain of dependent accesses (pointing -> pixel -> map value, or
+// pixel -> hash slot); issuing the loads of kBatch samples before using any
+// of them keeps kBatch chains in flight per thread instead of one.
+constexpr int kBatch = 4;
+
+// Where slot s of a tile lives: detector k, sample offset within the tile's
+// time block, flat TOD offset.  Slots past the stream (ragged last time block
+// or detector group) get offset 0, so their loads stay in bounds; their
+// results are discarded.
+struct Slot {
+  int64_t k, off;
+  int32_t kl, il;   // detector and sample index within the tile
+  bool in;
+};
+
+__device__ __forceinline__ Slot slot_of(const Tiling &tl, int64_t d0, int64_t t0, int32_t s,
+                                        int64_t n_det, int64_t n_samp) {
+  Slot r;
+  r.kl = s >> tl.log2ts;
+  r.k = d0 + r.kl;
+  r.il = s & ((1 << tl.log2ts) - 1);
+  const int64_t i = t0 + r.il;
+  r.in = s < (tl.dets << tl.log2ts) && r.k < n_det && i < n_samp;
+  r.off = r.in ? r.k * n_samp + i : 0;
+  if (!r.in) r.k = 0;
+  return r;
 }
 
-template <typename MT>
-__device__ __forceinline__ void load_iqu(const MT *__restrict__ m, MapLayout l, int32_t pix,
-                                         MT &I, MT &Q, MT &U) {
-  const int64_t o = (int64_t)pix * l.ps;
-  I = m[o];
-  Q = m[o + l.cs];
-  U = m[o + 2 * l.cs];
-}
-
-// ---------------------------------------------------------------------------
-// P: tod[k,i] = g_k (I[p] + c Q[p] + s U[p]).
-// ---------------------------------------------------------------------------
-constexpr int kApplyThreads = 256;
+// Per-tile constants staged in LDS once per workgroup: the HWP term
+// 2 alpha_i of each of the tile's samples and each detector's gain, angle
+// offset and noise weight, so the per-sample work reads them from LDS.
 constexpr int kMaxTileSamples = 1024;   // longest tile (2^10 samples per detector)
 
-template <typename T, typename MT>
+struct TileConsts {
+  double two_alpha[kMaxTileSamples];
+  double gain[kMaxTileDets], dpsi[kMaxTileDets], w[kMaxTileDets];
+};
+
+template <typename T>
+__device__ __forceinline__ void load_tile_consts(const PtArgs<T> &a, const double *w_det,
+                                                 const Tiling &tl, int64_t d0, int64_t t0,
+                                                 TileConsts &tc) {
+  if (a.hwp) {
+    for (int t = threadIdx.x; t < (1 << tl.log2ts); t += blockDim.x)
+      tc.two_alpha[t] = 2.0 * hwp_alpha(t0 + t, a.hwp_num_mod, a.hwp_den, a.hwp_phase0);
+  }
+  for (int j = threadIdx.x; j < tl.dets; j += blockDim.x) {
+    const int64_t k = d0 + j < a.n_det ? d0 + j : 0;
+    tc.gain[j] = a.gain ? a.gain[k] : 1.0;
+    tc.dpsi[j] = a.dpsi ? a.dpsi[k] : 0.0;
+    tc.w[j] = w_det ? w_det[k] : 1.0;
+  }
+}
+
+// Polariser weights of a sample from its angle psi, its detector's angle
+// offset and the HWP term: cos / sin of 2 (psi + dpsi_k + 2 alpha_i).
+template <typename T>
+__device__ __forceinline__ void pol_weights(const PtArgs<T> &a, const TileConsts &tc,
+                                            const Slot &sl, T psi, T &c, T &s) {
+#pragma clang fp contract(off)
+  double pe = (double)psi;
+  if (a.dpsi) pe = pe + tc.dpsi[sl.kl];
+  if (a.hwp) pe = pe + tc.two_alpha[sl.il];
+  weights(2.0 * pe, c, s);
+}
+
+template <typename T>
+__device__ __forceinline__ int32_t pixel_of(const PtArgs<T> &a, T theta, T phi) {
+  int32_t p = ang2pix_ring(a.nside, (double)theta, (double)phi);
+  if (p >= 0 && a.valid && !a.valid[p]) p = -1;
+  return p;
+}
+
+// Stokes values of pixel pix of a map: planar [3][npix] (IL = false, cs =
+// npix) or interleaved [npix][4] (IL = true; one 16- or 32-byte load).
+template <bool IL, typename MT>
+__device__ __forceinline__ void load_iqu(const MT *__restrict__ m, int64_t cs, int32_t pix,
+                                         MT &I, MT &Q, MT &U) {
+  if constexpr (IL) {
+    if constexpr (sizeof(MT) == 4) {
+      const float4 v = reinterpret_cast<const float4 *>(m)[pix];
+      I = v.x;
+      Q = v.y;
+      U = v.z;
+    } else {
+      const double2 *q = reinterpret_cast<const double2 *>(m) + 2 * (int64_t)pix;
+      const double2 v0 = q[0], v1 = q[1];
+      I = v0.x;
+      Q = v0.y;
+      U = v1.x;
+    }
+  } else {
+    I = m[pix];
+    Q = m[cs + pix];
+    U = m[2 * cs + pix];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// P: tod[k,i] = g_k (I[p] + c Q[p] + s U[p]).  With pix_out, the pixel of
+// every sample (-1 when flagged) is also written, for the P^T that follows in
+// the same normal-operator application.
+// ---------------------------------------------------------------------------
+constexpr int kApplyThreads = 256;
+
+template <typename T, typename MT, bool IL>
 __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *__restrict__ map,
-                                                         MapLayout ml, Tiling tl,
-                                                         T *__restrict__ tod, GeomCache<T> gc) {
-  __shared__ double ta[kMaxTileSamples];
+                                                         int64_t map_cs, Tiling tl,
+                                                         T *__restrict__ tod,
+                                                         int32_t *__restrict__ pix_out) {
+  __shared__ TileConsts tc;
   const int64_t tile = tile_of_block(blockIdx.x, tl.blocks());
   const int64_t d0 = (tile / tl.n_tb) * tl.dets;
   const int64_t t0 = (tile % tl.n_tb) << tl.log2ts;
-  const int32_t tsm = (1 << tl.log2ts) - 1;
   const int32_t nsamp = tl.dets << tl.log2ts;
-  fill_two_alpha(a, t0, tl.log2ts, ta, kApplyThreads);
+  load_tile_consts(a, nullptr, tl, d0, t0, tc);
   __syncthreads();
-  for (int32_t s = threadIdx.x; s < nsamp; s += kApplyThreads) {
-    const int64_t k = d0 + (s >> tl.log2ts);
-    const int64_t i = t0 + (s & tsm);
-    if (k >= a.n_det || i >= a.n_samp) continue;
-    const int64_t off = k * a.n_samp + i;
-    const Geom<T> gm = sample_geom_ta(a, k, off, ta[s & tsm]);
-    T y = 0;
-    if (gm.pix >= 0) {
-      MT I, Q, U;
-      load_iqu(map, ml, gm.pix, I, Q, U);
-      y = (T)I + gm.c * (T)Q + gm.s * (T)U;
-      y = gain_of(a, k) * y;
+  for (int32_t s0 = threadIdx.x; s0 < nsamp; s0 += kBatch * kApplyThreads) {
+    Slot sl[kBatch];
+    T th[kBatch], ph[kBatch], ps[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      sl[b] = slot_of(tl, d0, t0, s0 + b * kApplyThreads, a.n_det, a.n_samp);
+      th[b] = a.theta[sl[b].off];
+      ph[b] = a.phi[sl[b].off];
+      ps[b] = a.psi[sl[b].off];
     }
-    tod[off] = y;
-    if (gc.pix) {
-      gc.pix[off] = gm.pix;
-      gc.c[off] = gm.c;
-      gc.s[off] = gm.s;
+    int32_t px[kBatch];
+    T c[kBatch], s[kBatch];
+    MT I[kBatch], Q[kBatch], U[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      px[b] = pixel_of(a, th[b], ph[b]);
+      pol_weights(a, tc, sl[b], ps[b], c[b], s[b]);
+      load_iqu<IL>(map, map_cs, px[b] >= 0 ? px[b] : 0, I[b], Q[b], U[b]);
+    }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      if (!sl[b].in) continue;
+      const T y = (T)I[b] + c[b] * (T)Q[b] + s[b] * (T)U[b];
+      tod[sl[b].off] = px[b] >= 0 ? (T)tc.gain[sl[b].kl] * y : (T)0;
+      if (pix_out) pix_out[sl[b].off] = px[b];
     }
   }
 }
 
+// Tile shape of the pointing kernels.  A tile's time runs are at least 128
+// bytes of each pointing plane, so a wave's loads cover whole cache lines.
+static Tiling tiling_for(const PtArgs<float> &a, int64_t target) {
+  return make_tiling(a.n_det, a.n_samp, a.nside, target, 5);
+}
+static Tiling tiling_for(const PtArgs<double> &a, int64_t target) {
+  return make_tiling(a.n_det, a.n_samp, a.nside, target, 4);
+}
+
 template <typename T>
 furax_status launch_pointing_apply(const PtArgs<T> &a, const void *map, bool map_f64,
-                                   MapLayout ml, T *tod, hipStream_t s, GeomCache<T> gc) {
+                                   MapLayout ml, T *tod, hipStream_t s, int32_t *pix_out) {
   if (a.n_samp == 0) return FURAX_OK;
-  const Tiling tl = make_tiling(a.n_det, a.n_samp, a.nside, 4096, 6);
-  if (map_f64)
-    hipLaunchKernelGGL((k_apply<T, double>), dim3((unsigned)tl.blocks()), dim3(kApplyThreads), 0,
-                       s, a, static_cast<const double *>(map), ml, tl, tod, gc);
-  else
-    hipLaunchKernelGGL((k_apply<T, float>), dim3((unsigned)tl.blocks()), dim3(kApplyThreads), 0,
-                       s, a, static_cast<const float *>(map), ml, tl, tod, gc);
+  const Tiling tl = tiling_for(a, 4096);
+  const dim3 grid((unsigned)tl.blocks()), blk(kApplyThreads);
+  const bool il = ml.ps == 4;
+  if (map_f64) {
+    const double *m = static_cast<const double *>(map);
+    if (il)
+      hipLaunchKernelGGL((k_apply<T, double, true>), grid, blk, 0, s, a, m, ml.cs, tl, tod,
+                         pix_out);
+    else
+      hipLaunchKernelGGL((k_apply<T, double, false>), grid, blk, 0, s, a, m, ml.cs, tl, tod,
+                         pix_out);
+  } else {
+    const float *m = static_cast<const float *>(map);
+    if (il)
+      hipLaunchKernelGGL((k_apply<T, float, true>), grid, blk, 0, s, a, m, ml.cs, tl, tod,
+                         pix_out);
+    else
+      hipLaunchKernelGGL((k_apply<T, float, false>), grid, blk, 0, s, a, m, ml.cs, tl, tod,
+                         pix_out);
+  }
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }
 template furax_status launch_pointing_apply<float>(const PtArgs<float> &, const void *, bool,
-                                                   MapLayout, float *, hipStream_t,
-                                                   GeomCache<float>);
+                                                   MapLayout, float *, hipStream_t, int32_t *);
 template furax_status launch_pointing_apply<double>(const PtArgs<double> &, const void *, bool,
-                                                    MapLayout, double *, hipStream_t,
-                                                    GeomCache<double>);
+                                                    MapLayout, double *, hipStream_t, int32_t *);
 
 // ---------------------------------------------------------------------------
 // P^T scatter-add with LDS privatisation.
@@ -188,79 +298,106 @@ constexpr int kScatterThreads = 1024;
 constexpr int kMaxProbe = 64;
 constexpr int32_t kEmpty = -1;
 
-// MODE 0: v from tod, geometry recomputed; 1: fused diagonal normal operator;
-// 2: v from tod, geometry read from the cache written by the gather.
-template <typename T, typename MT, int MODE>
+__device__ __forceinline__ void hash_add(int32_t *keys, double (*acc)[kHashSlots], int32_t pix,
+                                         double v0, double v1, double v2, double *__restrict__ q,
+                                         const MapLayout &ql) {
+  volatile int32_t *vkeys = keys;
+  uint32_t h = ((uint32_t)pix * 2654435761u) >> (32 - 12);   // 12 = log2(kHashSlots)
+  bool placed = false;
+  for (int probe = 0; probe < kMaxProbe; ++probe) {
+    int32_t cur = vkeys[h];
+    if (cur == kEmpty) cur = atomicCAS(&keys[h], kEmpty, pix);
+    if (cur == kEmpty || cur == pix) {
+      placed = true;
+      break;
+    }
+    h = (h + 1) & (kHashSlots - 1);
+  }
+  if (placed) {
+    atomicAdd(&acc[0][h], v0);
+    atomicAdd(&acc[1][h], v1);
+    atomicAdd(&acc[2][h], v2);
+  } else {
+    const int64_t o = (int64_t)pix * ql.ps;
+    atomicAdd(&q[o], v0);
+    atomicAdd(&q[o + ql.cs], v1);
+    atomicAdd(&q[o + 2 * ql.cs], v2);
+  }
+}
+
+// q(c, pix) += v (1, cos, sin) over the tile's samples, where
+//   MODE 0: v = g_k w_k tod[k,i], geometry recomputed from the pointing;
+//   MODE 1: v = g_k w_k g_k (P p)[k,i], the fused diagonal-noise normal
+//           operator (p read from pmap, interleaved when IL);
+//   MODE 2: v = g_k w_k tod[k,i], pixel read from pix_in (written by the P of
+//           the same application), weights recomputed from psi.
+// w_k = w_det[k], or 1 when w_det is null.
+template <typename T, typename MT, int MODE, bool IL>
 __global__ void __launch_bounds__(kScatterThreads)
 k_scatter(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_det,
-          const MT *__restrict__ pmap, MapLayout pl, Tiling tl, double *__restrict__ q,
-          MapLayout ql, GeomCache<T> gc) {
+          const MT *__restrict__ pmap, int64_t p_cs, Tiling tl, double *__restrict__ q,
+          MapLayout ql, const int32_t *__restrict__ pix_in) {
   __shared__ int32_t keys[kHashSlots];
   __shared__ double acc[3][kHashSlots];
-  __shared__ double ta[kMaxTileSamples];
+  __shared__ TileConsts tc;
   for (int h = threadIdx.x; h < kHashSlots; h += kScatterThreads) {
     keys[h] = kEmpty;
     acc[0][h] = 0.0;
     acc[1][h] = 0.0;
     acc[2][h] = 0.0;
   }
-  __syncthreads();
-
   const int64_t tile = tile_of_block(blockIdx.x, tl.blocks());
   const int64_t d0 = (tile / tl.n_tb) * tl.dets;
   const int64_t t0 = (tile % tl.n_tb) << tl.log2ts;
-  const int32_t tsm = (1 << tl.log2ts) - 1;
   const int32_t nsamp = tl.dets << tl.log2ts;
-  if constexpr (MODE != 2) fill_two_alpha(a, t0, tl.log2ts, ta, kScatterThreads);
+  load_tile_consts(a, w_det, tl, d0, t0, tc);
   __syncthreads();
-  volatile int32_t *vkeys = keys;
-  for (int32_t s = threadIdx.x; s < nsamp; s += kScatterThreads) {
-    const int64_t k = d0 + (s >> tl.log2ts);
-    const int64_t i = t0 + (s & tsm);
-    if (k >= a.n_det || i >= a.n_samp) continue;
-    const int64_t off = k * a.n_samp + i;
-    Geom<T> gm;
-    if constexpr (MODE == 2) {
-      gm.pix = gc.pix[off];
-      if (gm.pix < 0) continue;
-      gm.c = gc.c[off];
-      gm.s = gc.s[off];
-    } else {
-      gm = sample_geom_ta(a, k, off, ta[s & tsm]);
-      if (gm.pix < 0) continue;
-    }
-    const T g = gain_of(a, k);
-    T v;
-    if constexpr (MODE == 1) {
-      MT I, Q, U;
-      load_iqu(pmap, pl, gm.pix, I, Q, U);
-      const T y = g * ((T)I + gm.c * (T)Q + gm.s * (T)U);
-      v = g * ((T)w_det[k] * y);
-    } else {
-      v = g * tod[off];
-      if (w_det) v = v * (T)w_det[k];
-    }
-    const double v0 = (double)v, v1 = (double)(v * gm.c), v2 = (double)(v * gm.s);
-    uint32_t h = ((uint32_t)gm.pix * 2654435761u) >> (32 - 12);   // 12 = log2(kHashSlots)
-    bool placed = false;
-    for (int probe = 0; probe < kMaxProbe; ++probe) {
-      int32_t cur = vkeys[h];
-      if (cur == kEmpty) cur = atomicCAS(&keys[h], kEmpty, gm.pix);
-      if (cur == kEmpty || cur == gm.pix) {
-        placed = true;
-        break;
+
+  for (int32_t s0 = threadIdx.x; s0 < nsamp; s0 += kBatch * kScatterThreads) {
+    Slot sl[kBatch];
+    int32_t px[kBatch];
+    T th[kBatch], ph[kBatch], ps[kBatch], v[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      sl[b] = slot_of(tl, d0, t0, s0 + b * kScatterThreads, a.n_det, a.n_samp);
+      ps[b] = a.psi[sl[b].off];
+      if constexpr (MODE == 2) {
+        px[b] = pix_in[sl[b].off];
+      } else {
+        th[b] = a.theta[sl[b].off];
+        ph[b] = a.phi[sl[b].off];
       }
-      h = (h + 1) & (kHashSlots - 1);
+      if constexpr (MODE != 1) v[b] = tod[sl[b].off];
     }
-    if (placed) {
-      atomicAdd(&acc[0][h], v0);
-      atomicAdd(&acc[1][h], v1);
-      atomicAdd(&acc[2][h], v2);
+    T c[kBatch], s[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      if constexpr (MODE != 2) px[b] = pixel_of(a, th[b], ph[b]);
+      if (!sl[b].in) px[b] = -1;
+      pol_weights(a, tc, sl[b], ps[b], c[b], s[b]);
+    }
+    if constexpr (MODE == 1) {
+      MT I[kBatch], Q[kBatch], U[kBatch];
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) load_iqu<IL>(pmap, p_cs, px[b] >= 0 ? px[b] : 0, I[b], Q[b], U[b]);
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        const T g = (T)tc.gain[sl[b].kl];
+        const T y = g * ((T)I[b] + c[b] * (T)Q[b] + s[b] * (T)U[b]);
+        v[b] = g * ((T)tc.w[sl[b].kl] * y);
+      }
     } else {
-      const int64_t o = (int64_t)gm.pix * ql.ps;
-      atomicAdd(&q[o], v0);
-      atomicAdd(&q[o + ql.cs], v1);
-      atomicAdd(&q[o + 2 * ql.cs], v2);
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        v[b] = (T)tc.gain[sl[b].kl] * v[b];
+        if (w_det) v[b] = v[b] * (T)tc.w[sl[b].kl];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      if (px[b] < 0) continue;
+      hash_add(keys, acc, px[b], (double)v[b], (double)(v[b] * c[b]), (double)(v[b] * s[b]), q,
+               ql);
     }
   }
   __syncthreads();
@@ -277,33 +414,46 @@ k_scatter(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_d
 template <typename T>
 furax_status launch_scatter(const PtArgs<T> &a, const T *tod, const double *w_det,
                             const void *pmap, bool pmap_f64, MapLayout pl, double *q,
-                            MapLayout ql, hipStream_t s, GeomCache<T> gc) {
+                            MapLayout ql, hipStream_t s, const int32_t *pix_in) {
   if (a.n_samp == 0) return FURAX_OK;
-  const Tiling tl = make_tiling(a.n_det, a.n_samp, a.nside, 8192, 6);
+  const Tiling tl = tiling_for(a, 8192);
   const dim3 grid((unsigned)tl.blocks()), blk(kScatterThreads);
-  if (tod && gc.pix) {
-    hipLaunchKernelGGL((k_scatter<T, double, 2>), grid, blk, 0, s, a, tod, w_det,
-                       (const double *)nullptr, pl, tl, q, ql, gc);
+  const double *nul = nullptr;
+  if (tod && pix_in) {
+    hipLaunchKernelGGL((k_scatter<T, double, 2, false>), grid, blk, 0, s, a, tod, w_det, nul,
+                       int64_t(0), tl, q, ql, pix_in);
   } else if (tod) {
-    hipLaunchKernelGGL((k_scatter<T, double, 0>), grid, blk, 0, s, a, tod, w_det,
-                       (const double *)nullptr, pl, tl, q, ql, gc);
-  } else if (pmap_f64) {
-    hipLaunchKernelGGL((k_scatter<T, double, 1>), grid, blk, 0, s, a, tod, w_det,
-                       static_cast<const double *>(pmap), pl, tl, q, ql, gc);
+    hipLaunchKernelGGL((k_scatter<T, double, 0, false>), grid, blk, 0, s, a, tod, w_det, nul,
+                       int64_t(0), tl, q, ql, pix_in);
   } else {
-    hipLaunchKernelGGL((k_scatter<T, float, 1>), grid, blk, 0, s, a, tod, w_det,
-                       static_cast<const float *>(pmap), pl, tl, q, ql, gc);
+    const bool il = pl.ps == 4;
+    if (pmap_f64) {
+      const double *m = static_cast<const double *>(pmap);
+      if (il)
+        hipLaunchKernelGGL((k_scatter<T, double, 1, true>), grid, blk, 0, s, a, tod, w_det, m,
+                           pl.cs, tl, q, ql, pix_in);
+      else
+        hipLaunchKernelGGL((k_scatter<T, double, 1, false>), grid, blk, 0, s, a, tod, w_det, m,
+                           pl.cs, tl, q, ql, pix_in);
+    } else {
+      const float *m = static_cast<const float *>(pmap);
+      if (il)
+        hipLaunchKernelGGL((k_scatter<T, float, 1, true>), grid, blk, 0, s, a, tod, w_det, m,
+                           pl.cs, tl, q, ql, pix_in);
+      else
+        hipLaunchKernelGGL((k_scatter<T, float, 1, false>), grid, blk, 0, s, a, tod, w_det, m,
+                           pl.cs, tl, q, ql, pix_in);
+    }
   }
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }
 template furax_status launch_scatter<float>(const PtArgs<float> &, const float *, const double *,
                                             const void *, bool, MapLayout, double *, MapLayout,
-                                            hipStream_t, GeomCache<float>);
+                                            hipStream_t, const int32_t *);
 template furax_status launch_scatter<double>(const PtArgs<double> &, const double *,
                                              const double *, const void *, bool, MapLayout,
-                                             double *, MapLayout, hipStream_t,
-                                             GeomCache<double>);
+                                             double *, MapLayout, hipStream_t, const int32_t *);
 
 // ---------------------------------------------------------------------------
 // Block-Jacobi accumulation: M_p += g^2 w_k (1,c,s)^T (1,c,s), hits_p += 1.
