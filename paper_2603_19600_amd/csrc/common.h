@@ -217,12 +217,16 @@ Tiling make_tiling(int64_t n_det, int64_t n_samp, int32_t nside, int64_t target_
 
 // Kernel-launch wrappers implemented in the individual translation units.
 //
-// tod = P map.  With pix_out (a [n_det][n_samp] int32 plane) the pixel of
-// every sample, -1 when flagged, is written as well.
+// tod = P map.  With pix_out (a [n_det][n_samp] int32 plane) the ring pixel
+// of every sample, -1 when flagged, is written as well.  With local_out (an
+// interleaved map whose 4th lane holds each pixel's nested index as integer
+// bits) the sample's offset inside its superpixel, nested & (P - 1), is
+// written instead (0xffff when flagged).
 template <typename T>
 furax_status launch_pointing_apply(const PtArgs<T> &a, const void *map, bool map_f64,
                                    MapLayout ml, T *tod, hipStream_t s,
-                                   int32_t *pix_out = nullptr);
+                                   int32_t *pix_out = nullptr, uint16_t *local_out = nullptr,
+                                   int32_t local_mask = 0);
 // q(c, pix) += sum over samples of v (1, cos, sin) with
 //   v = g_k w_k tod[k,i]               when tod != null (w_det may be null: w = 1), or
 //   v = g_k w_k g_k (P p)[k,i]          when tod == null (fused diagonal normal operator;
@@ -235,6 +239,53 @@ template <typename T>
 furax_status launch_scatter(const PtArgs<T> &a, const T *tod, const double *w_det,
                             const void *pmap, bool pmap_f64, MapLayout pl, double *q,
                             MapLayout ql, hipStream_t s, const int32_t *pix_in = nullptr);
+// ---------------------------------------------------------------------------
+// Superpixel-major accumulation (superpix.hip).
+// ---------------------------------------------------------------------------
+constexpr int kSpPix = 1024;        // pixels per superpixel (32 x 32 nested block)
+constexpr int kChunkRuns = 1024;    // runs per accumulation workgroup
+constexpr int64_t kMaxRun = 1024;   // longest run of consecutive samples
+
+struct SpChunk {
+  int64_t r0;   // first run (index into the sorted run list)
+  int32_t nr;   // number of runs
+  int32_t sp;   // superpixel
+  int32_t w;    // samples in the chunk (sum of its run lengths)
+  int32_t pad;
+};
+
+// Everything the superpixel accumulation needs, built once per pointing.
+struct SpPlan {
+  int32_t nside = 0, log2P = 0, n_values = 0;
+  int64_t npix = 0, n_sp = 0, n_runs = 0, n_chunks = 0;
+  int32_t *n2r = nullptr, *r2n = nullptr;   // nested -> ring, ring -> nested [npix]
+  uint64_t *runs = nullptr;                 // offset << 24 | chunk-local prefix of lengths
+  SpChunk *chunks = nullptr;                // [n_chunks], ordered by superpixel
+  int32_t *sp_chunk = nullptr;              // [n_sp + 1]: first chunk of each superpixel
+  double *partial = nullptr;                // [n_chunks][n_values][P]
+  void release(hipStream_t s);
+};
+
+// The superpixel path needs a power-of-two nside (the nested scheme) and
+// fewer than 2^31 samples (one 32-bit selection / sort).
+bool sp_supported(int64_t nside, int64_t S);
+furax_status sp_nest_tables(SpPlan &sp, int64_t nside, hipStream_t s);
+template <typename T>
+furax_status sp_nest_plane(const SpPlan &sp, const PtArgs<T> &a, int32_t *plane, hipStream_t s);
+template <typename T>
+furax_status sp_build_runs(SpPlan &sp, const PtArgs<T> &a, const int32_t *nest_plane,
+                           int32_t n_values, hipStream_t s);
+// q = P^T (w tod) in ring order (every pixel written).  The per-sample pixel
+// comes from `local` (offset inside its superpixel, as written by
+// launch_pointing_apply) or, when local is null, from the nested plane.
+template <typename T>
+furax_status sp_transpose(const SpPlan &sp, const PtArgs<T> &a, const T *tod,
+                          const double *w_det, const uint16_t *local, const int32_t *nest_plane,
+                          double *q, MapLayout ql, hipStream_t s);
+template <typename T>
+furax_status sp_bj_build(const SpPlan &sp, const PtArgs<T> &a, const double *w_det,
+                         const int32_t *nest_plane, double *M6, int32_t *hits, hipStream_t s);
+
 template <typename T>
 furax_status launch_noise(const furax_noise *N, const T *in, T *out, void *work,
                           size_t work_bytes, hipStream_t s);

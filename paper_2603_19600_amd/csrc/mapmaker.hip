@@ -158,6 +158,16 @@ __global__ void __launch_bounds__(kBlock) k_update2(int64_t npix, double *__rest
   }
 }
 
+// The 4th lane of pixel i of an interleaved gather map carries a tag as
+// integer bits: the pixel's nested index when tag is given (read back by P to
+// label each sample with its superpixel offset), else 0.
+template <typename T>
+__device__ __forceinline__ void set_tag(T *g, int64_t i, const int32_t *tag) {
+  const int32_t v = tag ? tag[i] : 0;
+  if constexpr (sizeof(T) == 8) reinterpret_cast<int64_t *>(g)[4 * i + 3] = v;
+  else reinterpret_cast<int32_t *>(g)[4 * i + 3] = v;
+}
+
 // z = Minv r (initial), r = b on valid pixels (0 elsewhere), p = z, x = 0;
 // partials of <r,z>, <b,b>.
 template <typename T>
@@ -168,6 +178,7 @@ __global__ void __launch_bounds__(kBlock) k_init_vectors(int64_t npix, const dou
                                                          double *__restrict__ z,
                                                          double *__restrict__ p,
                                                          T *__restrict__ pg,
+                                                         const int32_t *__restrict__ tag,
                                                          const double *__restrict__ Mi,
                                                          double *__restrict__ partial) {
   double v[2] = {0.0, 0.0};
@@ -193,7 +204,7 @@ __global__ void __launch_bounds__(kBlock) k_init_vectors(int64_t npix, const dou
       v[0] += rr[c] * zz[c];
       v[1] += rr[c] * rr[c];
     }
-    pg[4 * i + 3] = (T)0;
+    set_tag(pg, i, tag);
   }
   block_sum<2>(v, partial + blockIdx.x, kRedBlocks);
 }
@@ -216,14 +227,16 @@ static int64_t map_blocks(int64_t n) {
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct NormalLayout {
-  size_t spec = 0, y = 0, z = 0, pg = 0, qi = 0, wdet = 0, gpix = 0, total = 0;
+  size_t spec = 0, y = 0, z = 0, pg = 0, qi = 0, wdet = 0, gpix = 0, local = 0, total = 0;
 };
 
 // Workspace of the normal operator: per-detector diagonal weights, the band
 // kernel's spectrum and two TOD buffers (band noise), and the interleaved
 // gather copy of p and the interleaved FP64 accumulator of q; with band noise
-// also the per-sample pixel plane that P writes and P^T reads back, so the
-// pointing is pixelised once per application.
+// also the per-sample label that P writes and P^T reads back, so the pointing
+// is pixelised once per application: the sample's offset inside its
+// superpixel (uint16) on the superpixel path, its ring pixel (int32) on the
+// tiled path.
 template <typename T>
 static NormalLayout normal_layout(const furax_pointing *P, const furax_noise *N) {
   NormalLayout L;
@@ -235,7 +248,12 @@ static NormalLayout normal_layout(const furax_pointing *P, const furax_noise *N)
     L.spec = off; off += align256(noise_workspace_bytes<T>(N));
     L.y = off; off += align256(tod);
     L.z = off; off += align256(tod);
-    L.gpix = off; off += align256(sizeof(int32_t) * (size_t)P->n_det * P->n_samp);
+    const size_t S = (size_t)P->n_det * P->n_samp;
+    if (sp_supported(P->nside, (int64_t)S)) {
+      L.local = off; off += align256(sizeof(uint16_t) * S);
+    } else {
+      L.gpix = off; off += align256(sizeof(int32_t) * S);
+    }
   }
   L.pg = off; off += align256(sizeof(T) * 4 * npix);
   L.qi = off; off += align256(sizeof(double) * 4 * npix);
@@ -252,6 +270,8 @@ struct NormalPlan {
   char *work;
   NormalLayout L;
   int64_t npix;
+  bool use_sp = false;   // superpixel-major P^T (power-of-two nside)
+  SpPlan sp;
 };
 
 template <typename T>
@@ -266,20 +286,48 @@ static furax_status normal_prepare(NormalPlan<T> &pl, hipStream_t s) {
   return FURAX_OK;
 }
 
-// q = P^T N^-1 P p with p given as its interleaved gather copy pg (precision T)
-// and q an interleaved [npix][4] FP64 accumulator (overwritten).
+// Superpixel tables, runs and chunk partials of the plan's pointing (power-of-
+// two nside).  With M6/hits, the block-Jacobi blocks are accumulated on the
+// way; with nest_keep, the nested plane is handed to the caller (who frees it).
+template <typename T>
+static furax_status sp_prepare(NormalPlan<T> &pl, const double *w, double *M6, int32_t *hits,
+                               DevBuf *nest_keep, hipStream_t s) {
+  const int64_t S = pl.P->n_det * pl.P->n_samp;
+  FX_TRY(sp_nest_tables(pl.sp, pl.P->nside, s));
+  DevBuf own;
+  DevBuf &plane = nest_keep ? *nest_keep : own;
+  FX_TRY(plane.alloc(sizeof(int32_t) * S, s));
+  int32_t *np = static_cast<int32_t *>(plane.ptr);
+  FX_TRY(sp_nest_plane<T>(pl.sp, pl.a, np, s));
+  FX_TRY(sp_build_runs<T>(pl.sp, pl.a, np, M6 ? 7 : 3, s));
+  if (M6) FX_TRY(sp_bj_build<T>(pl.sp, pl.a, w, np, M6, hits, s));
+  return FURAX_OK;
+}
+
+// q = P^T N^-1 P p with p given as its interleaved gather copy pg (precision T;
+// on the superpixel path its 4th lane holds the nested index) and q an
+// interleaved [npix][4] FP64 accumulator (overwritten).
 template <typename T>
 static furax_status normal_run(const NormalPlan<T> &pl, const T *pg, double *q, hipStream_t s) {
   const double *w = reinterpret_cast<const double *>(pl.work + pl.L.wdet);
-  FX_TRY(zero_async(q, sizeof(double) * 4 * pl.npix, s));
   constexpr bool f64 = sizeof(T) == 8;
-  if (pl.N->kind == 0)
+  if (pl.N->kind == 0) {
+    FX_TRY(zero_async(q, sizeof(double) * 4 * pl.npix, s));
     return launch_scatter<T>(pl.a, nullptr, w, pg, f64, kInterleaved, q, kInterleaved, s);
+  }
   T *y = reinterpret_cast<T *>(pl.work + pl.L.y);
   T *z = reinterpret_cast<T *>(pl.work + pl.L.z);
+  if (pl.use_sp) {
+    uint16_t *local = reinterpret_cast<uint16_t *>(pl.work + pl.L.local);
+    FX_TRY(launch_pointing_apply<T>(pl.a, pg, f64, kInterleaved, y, s, nullptr, local,
+                                    (1 << pl.sp.log2P) - 1));
+    FX_TRY(noise_run<T>(pl.N, y, z, pl.work + pl.L.spec, s));
+    return sp_transpose<T>(pl.sp, pl.a, z, nullptr, local, nullptr, q, kInterleaved, s);
+  }
   int32_t *pix = reinterpret_cast<int32_t *>(pl.work + pl.L.gpix);
   FX_TRY(launch_pointing_apply<T>(pl.a, pg, f64, kInterleaved, y, s, pix));
   FX_TRY(noise_run<T>(pl.N, y, z, pl.work + pl.L.spec, s));
+  FX_TRY(zero_async(q, sizeof(double) * 4 * pl.npix, s));
   return launch_scatter<T>(pl.a, z, nullptr, nullptr, f64, kInterleaved, q, kInterleaved, s, pix);
 }
 
@@ -288,13 +336,14 @@ static furax_status normal_run(const NormalPlan<T> &pl, const T *pg, double *q, 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_to_interleaved(int64_t npix, const double *__restrict__ p,
                                                            const uint8_t *__restrict__ valid,
+                                                           const int32_t *__restrict__ tag,
                                                            T *__restrict__ g) {
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npix; i += stride) {
     const bool ok = !valid || valid[i];
 #pragma unroll
     for (int c = 0; c < 3; ++c) g[4 * i + c] = ok ? (T)p[c * npix + i] : (T)0;
-    g[4 * i + 3] = (T)0;
+    set_tag(g, i, tag);
   }
 }
 
@@ -326,6 +375,7 @@ furax_status normal_apply_impl(const furax_pointing *P, const furax_noise *N, co
   pl.a = pt_args<T>(P, nullptr);
   pl.L = normal_layout<T>(P, N);
   pl.npix = npix_of(P->nside);
+  pl.use_sp = N->kind == 1 && pl.L.local != 0;
   DevBuf own;
   if (!work) {
     FX_TRY(own.alloc(pl.L.total, s));
@@ -333,15 +383,23 @@ furax_status normal_apply_impl(const furax_pointing *P, const furax_noise *N, co
   }
   pl.work = static_cast<char *>(work);
   FX_TRY(normal_prepare<T>(pl, s));
-  T *pg = reinterpret_cast<T *>(pl.work + pl.L.pg);
-  double *qi = reinterpret_cast<double *>(pl.work + pl.L.qi);
-  const unsigned nb = (unsigned)map_blocks(pl.npix);
-  hipLaunchKernelGGL(k_to_interleaved<T>, dim3(nb), dim3(kBlock), 0, s, pl.npix, p, valid, pg);
-  FX_HIP(hipGetLastError());
-  FX_TRY(normal_run<T>(pl, pg, qi, s));
-  hipLaunchKernelGGL(k_from_interleaved, dim3(nb), dim3(kBlock), 0, s, pl.npix, qi, valid, q);
-  FX_HIP(hipGetLastError());
-  return FURAX_OK;
+  furax_status st = FURAX_OK;
+  if (pl.use_sp) st = sp_prepare<T>(pl, nullptr, nullptr, nullptr, nullptr, s);
+  if (st == FURAX_OK) {
+    T *pg = reinterpret_cast<T *>(pl.work + pl.L.pg);
+    double *qi = reinterpret_cast<double *>(pl.work + pl.L.qi);
+    const unsigned nb = (unsigned)map_blocks(pl.npix);
+    hipLaunchKernelGGL(k_to_interleaved<T>, dim3(nb), dim3(kBlock), 0, s, pl.npix, p, valid,
+                       pl.use_sp ? pl.sp.r2n : nullptr, pg);
+    st = hipGetLastError() == hipSuccess ? FURAX_OK : set_error(FURAX_EHIP, "launch failed");
+    if (st == FURAX_OK) st = normal_run<T>(pl, pg, qi, s);
+    if (st == FURAX_OK) {
+      hipLaunchKernelGGL(k_from_interleaved, dim3(nb), dim3(kBlock), 0, s, pl.npix, qi, valid, q);
+      st = hipGetLastError() == hipSuccess ? FURAX_OK : set_error(FURAX_EHIP, "launch failed");
+    }
+  }
+  pl.sp.release(s);
+  return st;
 }
 template furax_status normal_apply_impl<float>(const furax_pointing *, const furax_noise *,
                                                const double *, double *, const uint8_t *, void *,
@@ -450,9 +508,18 @@ static furax_status pcg_setup(furax_pcg_state *h, const void *tod) {
   pl.a = pt_args<T>(&h->P, nullptr);
   FX_TRY(normal_prepare<T>(pl, s));
   const double *w = reinterpret_cast<const double *>(pl.work + pl.L.wdet);
-  FX_TRY(zero_async(M6, sizeof(double) * 6 * npix, s));
-  FX_TRY(zero_async(hits, sizeof(int32_t) * npix, s));
-  FX_TRY(launch_bj_build<T>(pl.a, w, M6, hits, s));
+  const int64_t S = h->P.n_det * h->P.n_samp;
+  pl.use_sp = sp_supported(h->P.nside, S);
+  DevBuf nest_plane;
+  if (pl.use_sp) {
+    // superpixel plan (kept for the iterations) and the blocks on the way
+    FX_TRY(sp_prepare<T>(pl, w, M6, hits, &nest_plane, s));
+    pl.use_sp = h->N.kind == 1 && pl.L.local != 0;
+  } else {
+    FX_TRY(zero_async(M6, sizeof(double) * 6 * npix, s));
+    FX_TRY(zero_async(hits, sizeof(int32_t) * npix, s));
+    FX_TRY(launch_bj_build<T>(pl.a, w, M6, hits, s));
+  }
   FX_TRY(launch_bj_invert(npix, M6, hits, h->opt.rcond_min, h->opt.min_hits, h->opt.valid_in,
                           h->Minv, h->valid, nullptr, s));
 
@@ -461,21 +528,29 @@ static furax_status pcg_setup(furax_pcg_state *h, const void *tod) {
   // b with those samples flagged.  The iterations flag the same way (p is 0 on
   // invalid pixels and r is kept at 0 there), so pl.a carries no mask.
   double *b = h->z;
-  FX_TRY(zero_async(b, sizeof(double) * 3 * npix, s));
   const T *d = static_cast<const T *>(tod);
-  if (h->N.kind == 0) {
-    FX_TRY(launch_scatter<T>(pl.a, d, w, nullptr, false, planar_layout(npix), b,
-                              planar_layout(npix), s));
+  const T *zt = d;
+  const double *wd = w;
+  if (h->N.kind == 1) {
+    T *zbuf = reinterpret_cast<T *>(pl.work + pl.L.z);
+    FX_TRY(noise_run<T>(&h->N, d, zbuf, pl.work + pl.L.spec, s));
+    zt = zbuf;
+    wd = nullptr;
+  }
+  if (nest_plane.ptr) {
+    FX_TRY(sp_transpose<T>(pl.sp, pl.a, zt, wd, nullptr, static_cast<const int32_t *>(nest_plane.ptr),
+                           b, planar_layout(npix), s));
   } else {
-    T *zt = reinterpret_cast<T *>(pl.work + pl.L.z);
-    FX_TRY(noise_run<T>(&h->N, d, zt, pl.work + pl.L.spec, s));
-    FX_TRY(launch_scatter<T>(pl.a, zt, nullptr, nullptr, false, planar_layout(npix), b,
+    FX_TRY(zero_async(b, sizeof(double) * 3 * npix, s));
+    FX_TRY(launch_scatter<T>(pl.a, zt, wd, nullptr, false, planar_layout(npix), b,
                               planar_layout(npix), s));
   }
+  if (!pl.use_sp && pl.sp.n2r) pl.sp.release(s);   // diagonal noise: tables no longer needed
   // r = b (copied into r), x = 0, z = Minv r, p = z.  b lives in z; k_init_vectors
   // reads b[i] before writing z[i] for the same i, element by element.
   hipLaunchKernelGGL(k_init_vectors<T>, dim3((unsigned)kRedBlocks), dim3(kBlock), 0, s, npix, b,
-                     h->valid, h->x, h->r, h->z, h->p, static_cast<T *>(h->pg), h->Minv, h->partial);
+                     h->valid, h->x, h->r, h->z, h->p, static_cast<T *>(h->pg),
+                     pl.use_sp ? pl.sp.r2n : nullptr, h->Minv, h->partial);
   FX_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_init_final, dim3(1), dim3(kBlock), 0, s, h->partial, h->opt.rtol, h->sc,
                      h->hist);
@@ -517,7 +592,10 @@ furax_status pcg_create(const furax_pointing *P, const furax_noise *N, int32_t t
   h->precision = opt->precision;
   furax_status st = opt->precision == FURAX_F32 ? pcg_setup<float>(h, tod) : pcg_setup<double>(h, tod);
   if (st != FURAX_OK) {
+    h->pl32.sp.release(s);
+    h->pl64.sp.release(s);
     if (h->mem) (void)hipFreeAsync(h->mem, s);
+    (void)hipStreamSynchronize(s);
     delete h;
     return st;
   }
@@ -603,6 +681,8 @@ furax_status pcg_finish(furax_pcg h, double *map_out, uint8_t *valid_out, furax_
 
 furax_status pcg_destroy(furax_pcg h) {
   if (!h) return FURAX_OK;
+  h->pl32.sp.release(h->s);
+  h->pl64.sp.release(h->s);
   if (h->mem) FX_HIP(hipFreeAsync(h->mem, h->s));
   FX_HIP(hipStreamSynchronize(h->s));
   delete h;

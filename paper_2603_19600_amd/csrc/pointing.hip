@@ -168,22 +168,27 @@ __device__ __forceinline__ int32_t pixel_of(const PtArgs<T> &a, T theta, T phi) 
 }
 
 // Stokes values of pixel pix of a map: planar [3][npix] (IL = false, cs =
-// npix) or interleaved [npix][4] (IL = true; one 16- or 32-byte load).
+// npix) or interleaved [npix][4] (IL = true; one 16- or 32-byte load, whose
+// 4th lane -- a tag, the pixel's nested index as integer bits in the solver's
+// maps -- comes with it).
 template <bool IL, typename MT>
 __device__ __forceinline__ void load_iqu(const MT *__restrict__ m, int64_t cs, int32_t pix,
-                                         MT &I, MT &Q, MT &U) {
+                                         MT &I, MT &Q, MT &U, int32_t &tag) {
+  tag = 0;
   if constexpr (IL) {
     if constexpr (sizeof(MT) == 4) {
       const float4 v = reinterpret_cast<const float4 *>(m)[pix];
       I = v.x;
       Q = v.y;
       U = v.z;
+      tag = __float_as_int(v.w);
     } else {
       const double2 *q = reinterpret_cast<const double2 *>(m) + 2 * (int64_t)pix;
       const double2 v0 = q[0], v1 = q[1];
       I = v0.x;
       Q = v0.y;
       U = v1.x;
+      tag = (int32_t)__double_as_longlong(v1.y);
     }
   } else {
     I = m[pix];
@@ -203,7 +208,9 @@ template <typename T, typename MT, bool IL>
 __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *__restrict__ map,
                                                          int64_t map_cs, Tiling tl,
                                                          T *__restrict__ tod,
-                                                         int32_t *__restrict__ pix_out) {
+                                                         int32_t *__restrict__ pix_out,
+                                                         uint16_t *__restrict__ local_out,
+                                                         int32_t local_mask) {
   __shared__ TileConsts tc;
   const int64_t tile = tile_of_block(blockIdx.x, tl.blocks());
   const int64_t d0 = (tile / tl.n_tb) * tl.dets;
@@ -221,14 +228,14 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *
       ph[b] = a.phi[sl[b].off];
       ps[b] = a.psi[sl[b].off];
     }
-    int32_t px[kBatch];
+    int32_t px[kBatch], tag[kBatch];
     T c[kBatch], s[kBatch];
     MT I[kBatch], Q[kBatch], U[kBatch];
 #pragma unroll
     for (int b = 0; b < kBatch; ++b) {
       px[b] = pixel_of(a, th[b], ph[b]);
       pol_weights(a, tc, sl[b], ps[b], c[b], s[b]);
-      load_iqu<IL>(map, map_cs, px[b] >= 0 ? px[b] : 0, I[b], Q[b], U[b]);
+      load_iqu<IL>(map, map_cs, px[b] >= 0 ? px[b] : 0, I[b], Q[b], U[b], tag[b]);
     }
 #pragma unroll
     for (int b = 0; b < kBatch; ++b) {
@@ -236,6 +243,7 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *
       const T y = (T)I[b] + c[b] * (T)Q[b] + s[b] * (T)U[b];
       tod[sl[b].off] = px[b] >= 0 ? (T)tc.gain[sl[b].kl] * y : (T)0;
       if (pix_out) pix_out[sl[b].off] = px[b];
+      if (local_out) local_out[sl[b].off] = px[b] >= 0 ? (uint16_t)(tag[b] & local_mask) : 0xffff;
     }
   }
 }
@@ -251,7 +259,8 @@ static Tiling tiling_for(const PtArgs<double> &a, int64_t target) {
 
 template <typename T>
 furax_status launch_pointing_apply(const PtArgs<T> &a, const void *map, bool map_f64,
-                                   MapLayout ml, T *tod, hipStream_t s, int32_t *pix_out) {
+                                   MapLayout ml, T *tod, hipStream_t s, int32_t *pix_out,
+                                   uint16_t *local_out, int32_t local_mask) {
   if (a.n_samp == 0) return FURAX_OK;
   const Tiling tl = tiling_for(a, 4096);
   const dim3 grid((unsigned)tl.blocks()), blk(kApplyThreads);
@@ -260,26 +269,28 @@ furax_status launch_pointing_apply(const PtArgs<T> &a, const void *map, bool map
     const double *m = static_cast<const double *>(map);
     if (il)
       hipLaunchKernelGGL((k_apply<T, double, true>), grid, blk, 0, s, a, m, ml.cs, tl, tod,
-                         pix_out);
+                         pix_out, local_out, local_mask);
     else
       hipLaunchKernelGGL((k_apply<T, double, false>), grid, blk, 0, s, a, m, ml.cs, tl, tod,
-                         pix_out);
+                         pix_out, local_out, local_mask);
   } else {
     const float *m = static_cast<const float *>(map);
     if (il)
       hipLaunchKernelGGL((k_apply<T, float, true>), grid, blk, 0, s, a, m, ml.cs, tl, tod,
-                         pix_out);
+                         pix_out, local_out, local_mask);
     else
       hipLaunchKernelGGL((k_apply<T, float, false>), grid, blk, 0, s, a, m, ml.cs, tl, tod,
-                         pix_out);
+                         pix_out, local_out, local_mask);
   }
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }
 template furax_status launch_pointing_apply<float>(const PtArgs<float> &, const void *, bool,
-                                                   MapLayout, float *, hipStream_t, int32_t *);
+                                                   MapLayout, float *, hipStream_t, int32_t *,
+                                                   uint16_t *, int32_t);
 template furax_status launch_pointing_apply<double>(const PtArgs<double> &, const void *, bool,
-                                                    MapLayout, double *, hipStream_t, int32_t *);
+                                                    MapLayout, double *, hipStream_t, int32_t *,
+                                                    uint16_t *, int32_t);
 
 // ---------------------------------------------------------------------------
 // P^T scatter-add with LDS privatisation.
@@ -379,7 +390,10 @@ k_scatter(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_d
     if constexpr (MODE == 1) {
       MT I[kBatch], Q[kBatch], U[kBatch];
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) load_iqu<IL>(pmap, p_cs, px[b] >= 0 ? px[b] : 0, I[b], Q[b], U[b]);
+      for (int b = 0; b < kBatch; ++b) {
+        int32_t tag;
+        load_iqu<IL>(pmap, p_cs, px[b] >= 0 ? px[b] : 0, I[b], Q[b], U[b], tag);
+      }
 #pragma unroll
       for (int b = 0; b < kBatch; ++b) {
         const T g = (T)tc.gain[sl[b].kl];
