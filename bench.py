@@ -60,47 +60,26 @@ def make_inputs(w, dev):
     return P, N, d
 
 
-def time_kernels(fx, P, N, d, reps=5):
-    """Average duration (ms) of each kernel of q = P^T N^-1 P p, with HIP events on
-    the stream the library launches on (torch's current stream)."""
-    import torch
-
-    dev = d.device
-    p = torch.randn(3, P.npix, dtype=torch.float64, device=dev)
-    y = torch.empty_like(d)
-    z = torch.empty_like(d)
-    q = torch.zeros(3, P.npix, dtype=torch.float64, device=dev)
-    out = {}
-
-    def run(name, fn):
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        out[name] = e0.elapsed_time(e1) / reps
-
-    run("pointing_apply", lambda: fx.pointing_apply(P, p, out=y))
-    run("noise_apply", lambda: fx.noise_apply(N, y, out=z))
-    run("pointing_transpose", lambda: fx.pointing_transpose(P, z, out=q, accumulate=True))
-    return out
-
-
-def kernel_bytes(P, N, esize):
-    """Algorithmic HBM bytes per launch of each kernel (what the kernel must move)."""
-    S = P.n_det * P.n_samp
-    map_b = 3 * P.npix * 8
+def kernel_bytes(w):
+    """Algorithmic HBM bytes per launch of each phase of one PCG iteration (what
+    the operator must move as the method defines it, whatever the kernel reads)."""
+    e = 8 if w.dtype == "f64" else 4
+    S = w.n_det * w.n_samp
     return {
-        # theta, phi, psi in; TOD out; the FP64 map read once
-        "pointing_apply": S * (3 * esize + esize) + map_b,
-        # TOD in, TOD out
-        "noise_apply": S * 2 * esize,
-        # theta, phi, psi and TOD in; the FP64 accumulator read and written once
-        "pointing_transpose": S * (3 * esize + esize) + 2 * map_b,
+        # P: theta, phi, psi in, TOD out, the map read once
+        "apply": S * (3 * e + e) + 3 * w.npix * e,
+        # N^-1: TOD in, TOD out
+        "noise": S * 2 * e,
+        # P^T: theta, phi, psi and TOD in, the FP64 map written once
+        "transpose": S * (3 * e + e) + 3 * w.npix * 8,
     }
+
+
+def operator_bytes(w):
+    """Algorithmic bytes of a whole PCG iteration: the pointing stream once plus
+    the map-domain vectors (p, q, x, r, z, preconditioner: ~52 FP64 per pixel)."""
+    e = 8 if w.dtype == "f64" else 4
+    return w.n_det * w.n_samp * 3 * e + 52 * 8 * w.npix
 
 
 def run_pcg(fx, P, N, d, steps, warmup):
@@ -109,6 +88,9 @@ def run_pcg(fx, P, N, d, steps, warmup):
     sess = fx.PCGSession(P, N, d, max_iter=steps + warmup, rtol=0.0, no_early_exit=True)
     sess.iterate(warmup)
     torch.cuda.synchronize()
+    sess.set_timing(True)
+    sess.read_timing()
+    # the library launches on torch's current stream, where these events go too
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record()
@@ -116,39 +98,49 @@ def run_pcg(fx, P, N, d, steps, warmup):
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    phases = sess.read_timing()
     x, valid, info, st = sess.finish()
     sess.close()
     ms = e0.elapsed_time(e1) / steps
-    return ms, wall, info, x
+    return ms, wall, info, phases
 
 
-def measure(w, dev, steps, warmup, with_kernels=True):
+def measure(w, dev, steps, warmup):
     import torch
 
     from paper_2603_19600_amd import furax as fx
 
     P, N, d = make_inputs(w, dev)
-    ms, wall, info, x = run_pcg(fx, P, N, d, steps, warmup)
+    ms, wall, info, phases = run_pcg(fx, P, N, d, steps, warmup)
     S = w.n_det * w.n_samp
     res = {"ms_per_step": ms, "value": S / (ms * 1e-3), "wall_s": wall, "iters": info.iters,
            "rel_resid": info.rel_resid, "n_valid": info.n_valid}
+    kb = kernel_bytes(w)
+    n = max(phases["iters"], 1)
+    res["kernels"] = {}
+    for k in ("apply", "noise", "transpose", "update"):
+        t = phases[k] / n
+        row = {"ms": t}
+        if k in kb and t > 0:
+            row["alg_bytes"] = kb[k]
+            row["GB_s"] = kb[k] / (t * 1e-3) / 1e9
+        res["kernels"][k] = row
+    ob = operator_bytes(w)
+    res["operator"] = {"alg_bytes_per_iter": ob, "B_alg_per_sample": ob / S,
+                       "GB_s": ob / (ms * 1e-3) / 1e9, "frac_hbm_peak": ob / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     log(f"{w.name}: {ms:.3f} ms/iter, {res['value']:.4g} samples/s, rel resid {info.rel_resid:.3e}")
-    if with_kernels:
-        esize = 8 if w.dtype == "f64" else 4
-        kt = time_kernels(fx, P, N, d)
-        kb = kernel_bytes(P, N, esize)
-        res["kernels"] = {k: {"ms": kt[k], "alg_bytes": kb[k],
-                              "GB_s": kb[k] / (kt[k] * 1e-3) / 1e9} for k in kt}
-        log("kernels: " + ", ".join(f"{k} {v['ms']:.3f} ms {v['GB_s']:.0f} GB/s"
-                                    for k, v in res["kernels"].items()))
-    del P, N, d, x
+    log("phases: " + ", ".join(f"{k} {v['ms']:.3f} ms" + (f" {v['GB_s']:.0f} GB/s" if "GB_s" in v else "")
+                               for k, v in res["kernels"].items()))
+    del P, N, d
     torch.cuda.empty_cache()
     return res
 
 
-def cpu_baseline(w, n_det, seconds_hint=20.0):
-    """The FP64 NumPy oracle's P^T N^-1 P on a detector prefix of the same workload."""
+def cpu_baseline(w, n_det):
+    """The FP64 NumPy oracle's P^T N^-1 P on a detector prefix of the same workload,
+    on one host core (BLAS/OpenMP pools limited to one thread)."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
 
     from oracle import mapmaker as omm
     from paper_2603_19600_amd import synth
@@ -160,15 +152,18 @@ def cpu_baseline(w, n_det, seconds_hint=20.0):
                        pt.psi.double().numpy(), w.noise,
                        inv_var=None if lags is not None else np.ones(n_det), lags=lags, hwp=hwp)
     x = synth.sky_map(w).numpy()
-    t0 = time.perf_counter()
-    pix, c, s = prob.geometry()           # pointing is expanded at every application
-    omm.normal_apply(prob, pix, c, s, x)
-    dt = time.perf_counter() - t0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        c0 = time.process_time()
+        pix, c, s = prob.geometry()           # pointing is expanded at every application
+        omm.normal_apply(prob, pix, c, s, x)
+        cpu = time.process_time() - c0
+        dt = time.perf_counter() - t0
     S = n_det * w.n_samp
     return {"value": S / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
             "sample": f"one application of P^T N^-1 P (FP64 NumPy oracle, pointing expanded, "
                       f"FFT band-Toeplitz) on a {n_det}-detector x {w.n_samp}-sample prefix of "
-                      f"the workload, {dt:.1f} s",
+                      f"the workload, {dt:.1f} s wall, {cpu:.1f} s CPU",
             "seconds": dt}
 
 
@@ -195,8 +190,7 @@ def main():
     ap.add_argument("--config", type=int, default=2, help="workload number (2, 3 or 5)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 variant")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-kernels", action="store_true")
-    ap.add_argument("--cpu-dets", type=int, default=24)
+    ap.add_argument("--cpu-dets", type=int, default=64)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -211,18 +205,18 @@ def main():
 
     dev = torch.device("cuda:0")
     w = synth.WORKLOADS[args.config]
-    primary = measure(w, dev, args.steps, args.warmup, not args.no_kernels)
+    primary = measure(w, dev, args.steps, args.warmup)
     fp32 = None
     if not args.no_fp32 and w.dtype == "f64":
         w32 = synth.WORKLOADS[3] if args.config == 2 else w.with_(dtype="f32")
-        fp32 = measure(w32, dev, args.steps, args.warmup, not args.no_kernels)
+        fp32 = measure(w32, dev, args.steps, args.warmup)
 
-    roofline = None
-    if "kernels" in primary:
-        name, k = max(primary["kernels"].items(), key=lambda kv: kv[1]["ms"])
-        roofline = {"bound": "hbm", "kernel": name, "achieved": k["GB_s"], "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": k["GB_s"] / HBM_PEAK_GBS, "traffic": None,
-                    "alg_bytes_per_launch": k["alg_bytes"], "ms_per_launch": k["ms"]}
+    # the dominant operator kernel of the iteration
+    name, k = max(((n, v) for n, v in primary["kernels"].items() if "alg_bytes" in v),
+                  key=lambda kv: kv[1]["ms"])
+    roofline = {"bound": "hbm", "kernel": name, "achieved": k["GB_s"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": k["GB_s"] / HBM_PEAK_GBS, "traffic": None,
+                "alg_bytes_per_launch": k["alg_bytes"], "ms_per_launch": k["ms"]}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -248,11 +242,13 @@ def main():
                    "pcg_precision": w.dtype, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "kernels": primary.get("kernels"),
+        "kernels": primary["kernels"],
+        "operator": primary["operator"],
         "fp32": None if fp32 is None else {
             "workload": synth.WORKLOADS[3].name if args.config == 2 else w.name + "_f32",
             "value": fp32["value"], "ms_per_step": fp32["ms_per_step"],
-            "kernels": fp32.get("kernels"), "speedup_vs_fp64": fp32["value"] / primary["value"]},
+            "kernels": fp32["kernels"], "operator": fp32["operator"],
+            "speedup_vs_fp64": fp32["value"] / primary["value"]},
         "host": host_info(),
     }
     print(json.dumps(line), flush=True)

@@ -216,6 +216,23 @@ furax_status furax_pcg_finish(furax_pcg h, double *map_out, uint8_t *valid_out,
                               furax_pcg_info *info);
 furax_status furax_pcg_destroy(furax_pcg h);
 
+/* Device time of each phase of the iterations, for profiling a session.
+ * After furax_pcg_set_timing(h, 1), every furax_pcg_iterate iteration records
+ * HIP events on the session's stream between its phases (a few microseconds
+ * per iteration).  furax_pcg_read_timing synchronises the stream, returns the
+ * sums over the iterations timed since the previous read and resets them.
+ * With diagonal noise, P, N^-1 and P^T are one fused kernel, reported as
+ * ms_transpose (ms_apply = ms_noise = 0). */
+typedef struct {
+  int32_t iters;           /* timed iterations                                      */
+  double ms_apply;         /* P: pointing expanded, map gathered into the TOD      */
+  double ms_noise;         /* N^-1                                                  */
+  double ms_transpose;     /* P^T: binning into the map                            */
+  double ms_update;        /* dot products, preconditioner, vector updates         */
+} furax_pcg_timing;
+furax_status furax_pcg_set_timing(furax_pcg h, int32_t enable);
+furax_status furax_pcg_read_timing(furax_pcg h, furax_pcg_timing *out);
+
 /* Chi-square of the data model Eq. (1) and its vector-Jacobian product
  * (the differentiable path of "Summary" / "Research Impact Statement").
  * With s = P m (gains and angle offsets of P included) and r = d - s:

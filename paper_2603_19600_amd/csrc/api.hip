@@ -104,6 +104,8 @@ furax_status pcg_create(const furax_pointing *P, const furax_noise *N, int32_t t
 furax_status pcg_iterate(furax_pcg h, int32_t n_iter);
 furax_status pcg_finish(furax_pcg h, double *map_out, uint8_t *valid_out, furax_pcg_info *info);
 furax_status pcg_destroy(furax_pcg h);
+furax_status pcg_set_timing(furax_pcg h, int32_t enable);
+furax_status pcg_read_timing(furax_pcg h, furax_pcg_timing *out);
 template <typename T>
 furax_status chi2_impl(const furax_pointing *P, const furax_noise *N, int32_t map_dt,
                        const void *map, const T *tod, double *chi2_out, T *resid_w,
@@ -262,6 +264,16 @@ furax_status furax_pcg_finish(furax_pcg h, double *map_out, uint8_t *valid_out,
 }
 
 furax_status furax_pcg_destroy(furax_pcg h) { return pcg_destroy(h); }
+
+furax_status furax_pcg_set_timing(furax_pcg h, int32_t enable) {
+  if (!h) return set_error(FURAX_EINVAL, "NULL handle");
+  return pcg_set_timing(h, enable);
+}
+
+furax_status furax_pcg_read_timing(furax_pcg h, furax_pcg_timing *out) {
+  if (!h || !out) return set_error(FURAX_EINVAL, "NULL handle or output");
+  return pcg_read_timing(h, out);
+}
 
 furax_status furax_pcg_mapmake(const furax_pointing *P, const furax_noise *N, int32_t tod_dt,
                                const void *tod, double *map_out, uint8_t *valid_out,

@@ -304,16 +304,34 @@ static furax_status sp_prepare(NormalPlan<T> &pl, const double *w, double *M6, i
   return FURAX_OK;
 }
 
+// Events recorded on the stream between the phases of one PCG iteration:
+// e[0] before P, e[1] after P, e[2] after N^-1, e[3] after P^T, e[4] after the
+// map-domain updates (the diagonal-noise path fuses the three operator phases
+// into the P^T one).
+struct PhaseEvents {
+  hipEvent_t e[5];
+};
+
+static furax_status mark(const PhaseEvents *ev, int i, hipStream_t s) {
+  if (ev) FX_HIP(hipEventRecord(ev->e[i], s));
+  return FURAX_OK;
+}
+
 // q = P^T N^-1 P p with p given as its interleaved gather copy pg (precision T;
 // on the superpixel path its 4th lane holds the nested index) and q an
 // interleaved [npix][4] FP64 accumulator (overwritten).
 template <typename T>
-static furax_status normal_run(const NormalPlan<T> &pl, const T *pg, double *q, hipStream_t s) {
+static furax_status normal_run(const NormalPlan<T> &pl, const T *pg, double *q, hipStream_t s,
+                               const PhaseEvents *ev = nullptr) {
   const double *w = reinterpret_cast<const double *>(pl.work + pl.L.wdet);
   constexpr bool f64 = sizeof(T) == 8;
+  FX_TRY(mark(ev, 0, s));
   if (pl.N->kind == 0) {
+    FX_TRY(mark(ev, 1, s));
+    FX_TRY(mark(ev, 2, s));
     FX_TRY(zero_async(q, sizeof(double) * 4 * pl.npix, s));
-    return launch_scatter<T>(pl.a, nullptr, w, pg, f64, kInterleaved, q, kInterleaved, s);
+    FX_TRY(launch_scatter<T>(pl.a, nullptr, w, pg, f64, kInterleaved, q, kInterleaved, s));
+    return mark(ev, 3, s);
   }
   T *y = reinterpret_cast<T *>(pl.work + pl.L.y);
   T *z = reinterpret_cast<T *>(pl.work + pl.L.z);
@@ -321,14 +339,20 @@ static furax_status normal_run(const NormalPlan<T> &pl, const T *pg, double *q, 
     uint16_t *local = reinterpret_cast<uint16_t *>(pl.work + pl.L.local);
     FX_TRY(launch_pointing_apply<T>(pl.a, pg, f64, kInterleaved, y, s, nullptr, local,
                                     (1 << pl.sp.log2P) - 1));
+    FX_TRY(mark(ev, 1, s));
     FX_TRY(noise_run<T>(pl.N, y, z, pl.work + pl.L.spec, s));
-    return sp_transpose<T>(pl.sp, pl.a, z, nullptr, local, nullptr, q, kInterleaved, s);
+    FX_TRY(mark(ev, 2, s));
+    FX_TRY(sp_transpose<T>(pl.sp, pl.a, z, nullptr, local, nullptr, q, kInterleaved, s));
+    return mark(ev, 3, s);
   }
   int32_t *pix = reinterpret_cast<int32_t *>(pl.work + pl.L.gpix);
   FX_TRY(launch_pointing_apply<T>(pl.a, pg, f64, kInterleaved, y, s, pix));
+  FX_TRY(mark(ev, 1, s));
   FX_TRY(noise_run<T>(pl.N, y, z, pl.work + pl.L.spec, s));
+  FX_TRY(mark(ev, 2, s));
   FX_TRY(zero_async(q, sizeof(double) * 4 * pl.npix, s));
-  return launch_scatter<T>(pl.a, z, nullptr, nullptr, f64, kInterleaved, q, kInterleaved, s, pix);
+  FX_TRY(launch_scatter<T>(pl.a, z, nullptr, nullptr, f64, kInterleaved, q, kInterleaved, s, pix));
+  return mark(ev, 3, s);
 }
 
 // planar FP64 [3][npix] -> interleaved [npix][4] of T (4th lane 0), zero on
@@ -450,6 +474,9 @@ struct furax_pcg_state {
   fx::NormalPlan<double> pl64;
   int32_t nhist = 0;
   int32_t iters_launched = 0;
+  bool timing = false;
+  std::vector<fx::PhaseEvents> events;   // pool, reused after each read
+  int32_t n_timed = 0;
 };
 
 namespace fx {
@@ -565,7 +592,16 @@ static furax_status pcg_step(furax_pcg_state *h) {
     if constexpr (sizeof(T) == 4) return h->pl32;
     else return h->pl64;
   }();
-  FX_TRY(normal_run<T>(pl, static_cast<const T *>(h->pg), h->q, s));
+  const PhaseEvents *ev = nullptr;
+  if (h->timing) {
+    if ((size_t)h->n_timed == h->events.size()) {
+      PhaseEvents pe;
+      for (hipEvent_t &e : pe.e) FX_HIP(hipEventCreate(&e));
+      h->events.push_back(pe);
+    }
+    ev = &h->events[h->n_timed++];
+  }
+  FX_TRY(normal_run<T>(pl, static_cast<const T *>(h->pg), h->q, s, ev));
   hipLaunchKernelGGL(k_dot_pq, dim3((unsigned)kRedBlocks), dim3(kBlock), 0, s, h->npix, h->p, h->q,
                      h->partial);
   hipLaunchKernelGGL(k_pq_final, dim3(1), dim3(kBlock), 0, s, h->partial, h->sc);
@@ -576,6 +612,29 @@ static furax_status pcg_step(furax_pcg_state *h) {
   hipLaunchKernelGGL(k_update2<T>, dim3((unsigned)map_blocks(h->npix)), dim3(kBlock), 0, s,
                      h->npix, h->p, h->z, static_cast<T *>(h->pg), h->sc);
   FX_HIP(hipGetLastError());
+  return mark(ev, 4, s);
+}
+
+furax_status pcg_set_timing(furax_pcg h, int32_t enable) {
+  h->timing = enable != 0;
+  return FURAX_OK;
+}
+
+furax_status pcg_read_timing(furax_pcg h, furax_pcg_timing *out) {
+  FX_HIP(hipStreamSynchronize(h->s));
+  furax_pcg_timing t = {0, 0.0, 0.0, 0.0, 0.0};
+  for (int32_t i = 0; i < h->n_timed; ++i) {
+    float ms[4];
+    for (int j = 0; j < 4; ++j)
+      FX_HIP(hipEventElapsedTime(&ms[j], h->events[i].e[j], h->events[i].e[j + 1]));
+    t.ms_apply += ms[0];
+    t.ms_noise += ms[1];
+    t.ms_transpose += ms[2];
+    t.ms_update += ms[3];
+  }
+  t.iters = h->n_timed;
+  h->n_timed = 0;
+  *out = t;
   return FURAX_OK;
 }
 
@@ -681,6 +740,8 @@ furax_status pcg_finish(furax_pcg h, double *map_out, uint8_t *valid_out, furax_
 
 furax_status pcg_destroy(furax_pcg h) {
   if (!h) return FURAX_OK;
+  for (fx::PhaseEvents &pe : h->events)
+    for (hipEvent_t e : pe.e) (void)hipEventDestroy(e);
   h->pl32.sp.release(h->s);
   h->pl64.sp.release(h->s);
   if (h->mem) FX_HIP(hipFreeAsync(h->mem, h->s));

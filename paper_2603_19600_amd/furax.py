@@ -50,6 +50,11 @@ class _PcgOpts(C.Structure):
                 ("no_early_exit", C.c_int32)]
 
 
+class _PcgTiming(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("ms_apply", C.c_double), ("ms_noise", C.c_double),
+                ("ms_transpose", C.c_double), ("ms_update", C.c_double)]
+
+
 class _PcgInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("stop_reason", C.c_int32), ("rel_resid", C.c_double),
                 ("resid_history", C.POINTER(C.c_double)), ("n_valid", C.c_int64)]
@@ -76,6 +81,8 @@ def _load() -> C.CDLL:
         "furax_pcg_iterate": [vp, i32],
         "furax_pcg_finish": [vp, vp, vp, C.POINTER(_PcgInfo)],
         "furax_pcg_destroy": [vp],
+        "furax_pcg_set_timing": [vp, i32],
+        "furax_pcg_read_timing": [vp, C.POINTER(_PcgTiming)],
         "furax_chi2": [P, N, i32, vp, vp, vp, vp, vp],
         "furax_pointing_vjp": [P, i32, vp, vp, vp, vp, vp, vp],
         "furax_last_error": [],
@@ -99,6 +106,7 @@ EXPORTS = ("furax_ang2pix", "furax_pointing_apply", "furax_pointing_transpose",
            "furax_noise_apply", "furax_bj_build", "furax_bj_invert",
            "furax_normal_workspace_bytes", "furax_normal_apply", "furax_pcg_mapmake",
            "furax_pcg_create", "furax_pcg_iterate", "furax_pcg_finish", "furax_pcg_destroy",
+           "furax_pcg_set_timing", "furax_pcg_read_timing",
            "furax_chi2", "furax_pointing_vjp", "furax_last_error", "furax_release_caches",
            "furax_version")
 
@@ -370,6 +378,17 @@ class PCGSession:
 
     def iterate(self, n: int):
         _check(_lib.furax_pcg_iterate(self._h, int(n)))
+
+    def set_timing(self, enable: bool = True):
+        """Record HIP events between the phases of every following iteration."""
+        _check(_lib.furax_pcg_set_timing(self._h, 1 if enable else 0))
+
+    def read_timing(self) -> dict:
+        """Device ms of each phase summed over the iterations timed since the last read."""
+        t = _PcgTiming()
+        _check(_lib.furax_pcg_read_timing(self._h, C.byref(t)))
+        return {"iters": t.iters, "apply": t.ms_apply, "noise": t.ms_noise,
+                "transpose": t.ms_transpose, "update": t.ms_update}
 
     def finish(self, raise_on: Sequence[int] = (EINVAL, ENOMEM, EHIP, EUNSUPPORTED)):
         out = torch.empty(3, self.P.npix, dtype=torch.float64, device=self.P.device)
