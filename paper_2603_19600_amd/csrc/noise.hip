@@ -109,8 +109,25 @@ __device__ __forceinline__ C2<T> twiddle(C2<T> a, C2<T> w) {
   return INV ? cmulc(a, w) : cmul(a, w);
 }
 
-template <typename T, int M, int NT, int R, bool INV>
-__device__ __forceinline__ void stockham_pass(C2<T> *s, const C2<T> *__restrict__ tw, int Ns) {
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations,
+// not for its global loads, so loads issued before it (the next block's input)
+// stay in flight across the FFT passes.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// exp(-2 pi i j / L) from two LDS tables: hi[j >> kTwLoBits] lo[j & mask].
+constexpr int kTwLoBits = 7;
+template <typename T>
+struct TwTab {
+  const C2<T> *hi, *lo;
+  __device__ __forceinline__ C2<T> operator()(int j) const {
+    return cmul(hi[j >> kTwLoBits], lo[j & ((1 << kTwLoBits) - 1)]);
+  }
+};
+
+template <typename T, int M, int NT, int R, bool INV, typename TW>
+__device__ __forceinline__ void stockham_pass(C2<T> *s, const TW &tw, int Ns) {
   constexpr int NB = M / R;
   constexpr int PER = (NB + NT - 1) / NT;
   const int tid = threadIdx.x;
@@ -123,7 +140,7 @@ __device__ __forceinline__ void stockham_pass(C2<T> *s, const C2<T> *__restrict_
       for (int r = 0; r < R; ++r) v[q][r] = s[pad16(j + r * NB)];
     }
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int j = tid + q * NT;
@@ -132,7 +149,7 @@ __device__ __forceinline__ void stockham_pass(C2<T> *s, const C2<T> *__restrict_
     if (Ns > 1) {
       const int b = 2 * k * (M / (R * Ns));
       if constexpr (R == 16) {
-        const C2<T> w1 = tw[b], w2 = tw[2 * b], w4 = tw[4 * b], w8 = tw[8 * b];
+        const C2<T> w1 = tw(b), w2 = tw(2 * b), w4 = tw(4 * b), w8 = tw(8 * b);
         const C2<T> w3 = cmul(w1, w2), w5 = cmul(w1, w4), w6 = cmul(w2, w4), w7 = cmul(w3, w4);
         const C2<T> w[16] = {w1, w1, w2, w3, w4, w5, w6, w7, w8, cmul(w1, w8), cmul(w2, w8),
                              cmul(w3, w8), cmul(w4, w8), cmul(w5, w8), cmul(w6, w8), cmul(w7, w8)};
@@ -140,7 +157,7 @@ __device__ __forceinline__ void stockham_pass(C2<T> *s, const C2<T> *__restrict_
         for (int r = 1; r < 16; ++r) v[q][r] = twiddle<T, INV>(v[q][r], w[r]);
       } else {
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[q][r] = twiddle<T, INV>(v[q][r], tw[r * b]);
+        for (int r = 1; r < R; ++r) v[q][r] = twiddle<T, INV>(v[q][r], tw(r * b));
       }
     }
     const int d = (j - k) * R + k;
@@ -157,11 +174,11 @@ __device__ __forceinline__ void stockham_pass(C2<T> *s, const C2<T> *__restrict_
       s[pad16(d + Ns)] = csub(v[q][0], v[q][1]);
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
-template <typename T, int M, int NT, bool INV>
-__device__ __forceinline__ void fft_lds(C2<T> *s, const C2<T> *__restrict__ tw) {
+template <typename T, int M, int NT, bool INV, typename TW>
+__device__ __forceinline__ void fft_lds(C2<T> *s, const TW &tw) {
   constexpr int log2m = __builtin_ctz(M);
   constexpr int n16 = log2m / 4;
   constexpr int rem = M >> (4 * n16);
@@ -181,77 +198,103 @@ __device__ __forceinline__ void fft_lds(C2<T> *s, const C2<T> *__restrict__ tw) 
   }
 }
 
-// Block index -> (detector, time block) with consecutive time blocks of one
-// detector kept on the same XCD (workgroups are dealt round-robin over the 8
-// XCDs), so the halo a block shares with its neighbours is read through the
-// same L2.
+
+// Block index -> task (detector-major, block-minor) with consecutive blocks
+// of one detector kept on the same XCD (workgroups are dealt round-robin over
+// the 8 XCDs), so the halo a block shares with its neighbours is read through
+// the same L2.
 __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
   const int64_t per = nblocks / 8;
   if (per == 0 || bid >= per * 8) return bid;
   return (bid % 8) * per + bid / 8;
 }
 
-template <typename T, int M, int NT>
+// A workgroup transforms a contiguous range of (detector, block) tasks, one
+// per workgroup unless PREFETCH: then a persistent workgroup walks a range of
+// consecutive blocks and loads the next task's input into registers while the
+// current one is transformed (it costs VGPRs the transform also needs, so it
+// is kept as an option).
+template <typename T, int M, int NT, bool PREFETCH>
 __global__ void __launch_bounds__(NT) k_overlap_save(const T *__restrict__ in, T *__restrict__ out,
-                                                     int64_t n_det, int64_t n, int32_t b,
-                                                     int64_t nblk, const T *__restrict__ spec,
+                                                     int64_t n, int32_t b, int64_t nblk,
+                                                     int64_t ntask, const T *__restrict__ spec,
                                                      int64_t spec_stride,
                                                      const C2<T> *__restrict__ tw) {
   __shared__ C2<T> s[M + M / 16];
   constexpr int L = 2 * M;
+  __shared__ C2<T> tw_hi[L >> kTwLoBits], tw_lo[1 << kTwLoBits];
   const int V = L - 2 * (b - 1);
-  const int64_t bid = xcd_remap(blockIdx.x, (int64_t)gridDim.x);
-  const int64_t det = bid / nblk;
-  const int64_t blk = bid % nblk;
-  const int64_t s0 = blk * V - (b - 1);
-  const T *x = in + det * n;
   const int tid = threadIdx.x;
+  for (int j = tid; j < (L >> kTwLoBits); j += NT) tw_hi[j] = tw[j << kTwLoBits];
+  for (int j = tid; j < (1 << kTwLoBits); j += NT) tw_lo[j] = tw[j];
+  const TwTab<T> W = {tw_hi, tw_lo};
 
-  for (int m = tid; m < M; m += NT) {
-    const int64_t g = s0 + 2 * m;
-    C2<T> v;
-    v.x = (g >= 0 && g < n) ? x[g] : (T)0;
-    v.y = (g + 1 >= 0 && g + 1 < n) ? x[g + 1] : (T)0;
-    s[pad16(m)] = v;
-  }
-  __syncthreads();
-  fft_lds<T, M, NT, false>(s, tw);
-
-  const T *H = spec + det * spec_stride;   // H[0..M], already divided by M
-  for (int k = tid; k <= M / 2; k += NT) {
-    const int k2 = (M - k) & (M - 1);
-    const C2<T> z1 = s[pad16(k)], z2 = s[pad16(k2)];
-    C2<T> r1, r2;
+  const int64_t t_beg = PREFETCH ? ntask * blockIdx.x / gridDim.x
+                                 : xcd_remap(blockIdx.x, (int64_t)gridDim.x);
+  const int64_t t_end = PREFETCH ? ntask * (blockIdx.x + 1) / gridDim.x : t_beg + 1;
+  constexpr int PER = M / NT;
+  static_assert(M % NT == 0, "whole complex values per thread");
+  C2<T> buf[PER];
+  // input of task t: L real samples from s0 = blk V - (b - 1), zero outside
+  // the detector's stream, packed as M complex values (even -> re, odd -> im)
+  auto fetch = [&](int64_t t) {
+    const int64_t det = t / nblk, blk = t - det * nblk;
+    const int64_t s0 = blk * V - (b - 1);
+    const T *x = in + det * n;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int kk = h ? k2 : k;
-      const C2<T> za = h ? z2 : z1;
-      const C2<T> zb = h ? z1 : z2;               // Z[M - kk]
-      const C2<T> zc = {zb.x, -zb.y};             // conj(Z[M - kk])
-      const C2<T> E = cscale(cadd(za, zc), (T)0.5);
-      const C2<T> Dh = cscale(csub(za, zc), (T)0.5);
-      const C2<T> O = {Dh.y, -Dh.x};              // (Z[k] - conj Z[M-k]) / (2i)
-      const T Hk = H[kk], Hm = H[M - kk];
-      const T hp = (Hk + Hm) * (T)0.5, hm = (Hk - Hm) * (T)0.5;
-      const C2<T> W = tw[kk];                     // exp(-2 pi i kk / L)
-      const C2<T> A = cadd(cscale(E, hp), cscale(cmul(W, O), hm));
-      const C2<T> B = cadd(cscale(cmulc(E, W), hm), cscale(O, hp));
-      const C2<T> r = {A.x - B.y, A.y + B.x};     // A + i B
-      if (h) r2 = r; else r1 = r;
+    for (int q = 0; q < PER; ++q) {
+      const int64_t g = s0 + 2 * (tid + q * NT);
+      buf[q].x = (g >= 0 && g < n) ? x[g] : (T)0;
+      buf[q].y = (g + 1 >= 0 && g + 1 < n) ? x[g + 1] : (T)0;
     }
-    s[pad16(k)] = r1;
-    if (k2 != k) s[pad16(k2)] = r2;
-  }
-  __syncthreads();
-  fft_lds<T, M, NT, true>(s, tw);
+  };
+  if (t_beg < t_end) fetch(t_beg);
+  for (int64_t t = t_beg; t < t_end; ++t) {
+    lds_barrier();   // the previous task's outputs have been read out of LDS
+#pragma unroll
+    for (int q = 0; q < PER; ++q) s[pad16(tid + q * NT)] = buf[q];
+    if (PREFETCH && t + 1 < t_end) fetch(t + 1);   // in flight during this task's transforms
+    lds_barrier();
+    fft_lds<T, M, NT, false>(s, W);
 
-  T *z = out + det * n;
-  const int lo = b - 1, hi = b - 1 + V;
-  for (int m = tid; m < M; m += NT) {
-    const int e = 2 * m;
-    const C2<T> v = s[pad16(m)];
-    if (e >= lo && e < hi && s0 + e < n) z[s0 + e] = v.x;
-    if (e + 1 >= lo && e + 1 < hi && s0 + e + 1 < n) z[s0 + e + 1] = v.y;
+    const int64_t det = t / nblk, blk = t - det * nblk;
+    const T *H = spec + det * spec_stride;   // H[0..M], already divided by M
+    for (int k = tid; k <= M / 2; k += NT) {
+      const int k2 = (M - k) & (M - 1);
+      const C2<T> z1 = s[pad16(k)], z2 = s[pad16(k2)];
+      C2<T> r1, r2;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int kk = h ? k2 : k;
+        const C2<T> za = h ? z2 : z1;
+        const C2<T> zb = h ? z1 : z2;               // Z[M - kk]
+        const C2<T> zc = {zb.x, -zb.y};             // conj(Z[M - kk])
+        const C2<T> E = cscale(cadd(za, zc), (T)0.5);
+        const C2<T> Dh = cscale(csub(za, zc), (T)0.5);
+        const C2<T> O = {Dh.y, -Dh.x};              // (Z[k] - conj Z[M-k]) / (2i)
+        const T Hk = H[kk], Hm = H[M - kk];
+        const T hp = (Hk + Hm) * (T)0.5, hm = (Hk - Hm) * (T)0.5;
+        const C2<T> Wk = W(kk);                     // exp(-2 pi i kk / L)
+        const C2<T> A = cadd(cscale(E, hp), cscale(cmul(Wk, O), hm));
+        const C2<T> B = cadd(cscale(cmulc(E, Wk), hm), cscale(O, hp));
+        const C2<T> r = {A.x - B.y, A.y + B.x};     // A + i B
+        if (h) r2 = r; else r1 = r;
+      }
+      s[pad16(k)] = r1;
+      if (k2 != k) s[pad16(k2)] = r2;
+    }
+    lds_barrier();
+    fft_lds<T, M, NT, true>(s, W);
+
+    const int64_t s0 = blk * V - (b - 1);
+    T *z = out + det * n;
+    const int lo = b - 1, hi = b - 1 + V;
+    for (int m = tid; m < M; m += NT) {
+      const int e = 2 * m;
+      const C2<T> v = s[pad16(m)];
+      if (e >= lo && e < hi && s0 + e < n) z[s0 + e] = v.x;
+      if (e + 1 >= lo && e + 1 < hi && s0 + e + 1 < n) z[s0 + e + 1] = v.y;
+    }
   }
 }
 
@@ -400,10 +443,10 @@ static furax_status launch_os(const furax_noise *N, const T *in, T *out, const T
   const int b = (int)N->bandwidth;
   const int64_t V = 2 * M - 2 * (int64_t)(b - 1);
   const int64_t nblk = (N->n_samp + V - 1) / V;
-  const int64_t blocks = N->n_det * nblk;
+  const int64_t ntask = N->n_det * nblk;
   const int64_t spec_stride = N->toeplitz_stride ? (M + 1) : 0;
-  hipLaunchKernelGGL((k_overlap_save<T, M, NT>), dim3((unsigned)blocks), dim3(NT), 0, s, in, out,
-                     N->n_det, N->n_samp, b, nblk, spec, spec_stride, tw);
+  hipLaunchKernelGGL((k_overlap_save<T, M, NT, false>), dim3((unsigned)ntask), dim3(NT), 0, s, in,
+                     out, N->n_samp, b, nblk, ntask, spec, spec_stride, tw);
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }
