@@ -58,13 +58,19 @@ __device__ __forceinline__ int32_t ang2pix_ring(int32_t n, double theta, double 
   if (!(phi - phi == 0.0)) return -1;                   // rejects NaN and +-inf
   const double N = (double)n;
   const double two_pi = 2.0 * kPi;
-  const double half_pi = 0.5 * kPi;
+  constexpr double half_pi_c = 0.5 * kPi;
+  const double half_pi = half_pi_c;
   const double z = cos(theta);
   const double za = fabs(z);
   // fmod(phi, 2 pi) is phi itself on [0, 2 pi): skip the library call there
   double phr = (phi >= 0.0 && phi < two_pi) ? phi : fmod(phi, two_pi);
   if (phr < 0.0) phr = phr + two_pi;
-  const double tt = phr / half_pi;                      // in [0, 4]
+  // tt = phr / (pi/2) rounded as IEEE division does, from phr * RN(2/pi) and
+  // one residual correction (Markstein): equal to the quotient for phr >
+  // 2^-900; below that tt only meets 0.5 + tt and floors, which round alike.
+  constexpr double inv_half_pi = 1.0 / half_pi_c;
+  const double q0 = phr * inv_half_pi;
+  const double tt = fma(fma(-q0, half_pi, phr), inv_half_pi, q0);   // in [0, 4]
   int32_t pix;
   if (za <= 2.0 / 3.0) {
     const double t1 = N * (0.5 + tt);
@@ -73,8 +79,8 @@ __device__ __forceinline__ int32_t ang2pix_ring(int32_t n, double theta, double 
     const int32_t jm = (int32_t)floor(t1 + t2);
     const int32_t ir = n + 1 + jp - jm;                 // 1 .. 2n+1
     const int32_t kshift = 1 - (ir & 1);
-    int32_t ip = (jp + jm - n + kshift + 1) / 2;        // non-negative
-    ip = ip % (4 * n);
+    int32_t ip = (jp + jm - n + kshift + 1) / 2;        // in [0, 4n + 1]
+    if (ip >= 4 * n) ip -= 4 * n;                       // ip mod 4n
     pix = 2 * n * (n - 1) + (ir - 1) * (4 * n) + ip;
   } else {
     const double tp = tt - floor(tt);
@@ -82,8 +88,8 @@ __device__ __forceinline__ int32_t ang2pix_ring(int32_t n, double theta, double 
     const int32_t jp = (int32_t)floor(tp * w);
     const int32_t jm = (int32_t)floor((1.0 - tp) * w);
     const int32_t ir = jp + jm + 1;                     // 1 .. n
-    int32_t ip = (int32_t)floor(tt * (double)ir);
-    ip = ip % (4 * ir);
+    int32_t ip = (int32_t)floor(tt * (double)ir);       // in [0, 4 ir]
+    if (ip >= 4 * ir) ip -= 4 * ir;                     // ip mod 4 ir
     pix = (z > 0.0) ? 2 * ir * (ir - 1) + ip : 12 * n * n - 2 * ir * (ir + 1) + ip;
   }
   return ((uint32_t)pix < (uint32_t)(12 * n * n)) ? pix : -1;
