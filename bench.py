@@ -54,7 +54,10 @@ def make_inputs(w, dev):
                                         device=dev))
     m_true = synth.sky_map(w, device=dev)
     d = fx.pointing_apply(P, m_true)                       # signal (HIP path; bench only)
-    d += synth.noise(w, device=dev).to(d.dtype)
+    # white noise streams: the 1/f model enters through the band-Toeplitz
+    # weights, and no operator's cost depends on the data values (this also
+    # keeps library FFTs, which the counter profiler cannot follow, out of it)
+    d += synth.noise(w, device=dev, shape_1f=False).to(d.dtype)
     torch.cuda.synchronize()
     log(f"{w.name}: inputs generated in {time.time() - t0:.1f} s")
     return P, N, d
@@ -204,6 +207,13 @@ def main():
     from paper_2603_19600_amd import synth
 
     dev = torch.device("cuda:0")
+    # a plain 1 GiB device copy: the reference that scales rocprofv3's
+    # FETCH_SIZE / WRITE_SIZE counters to bytes (it reads and writes 1 GiB)
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
     w = synth.WORKLOADS[args.config]
     primary = measure(w, dev, args.steps, args.warmup)
     fp32 = None
@@ -236,7 +246,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": w.dtype,
-        "data": "synthetic (seeded spin+precession scan, random IQU sky, 1/f noise)",
+        "data": "synthetic (seeded spin+precession scan, random IQU sky, white noise data, 1/f band-Toeplitz weights)",
         "config": {"workload": w.name, "nside": w.nside, "n_det": w.n_det, "n_samp": w.n_samp,
                    "samples": S, "noise": w.noise, "bandwidth": w.bandwidth, "hwp": w.hwp,
                    "pcg_precision": w.dtype, "parallelism": "single GPU"},

@@ -447,6 +447,50 @@ def pointing_vjp(P: Pointing, m: Optional[torch.Tensor], cot: torch.Tensor,
     return (grad_map if want_map else None), gg, gd
 
 
+class Chi2Fn(torch.autograd.Function):
+    """chi2(m, g, dpsi) = r^T N^-1 r,  r = d - P(psi + dpsi; g) m  (diagonal N).
+
+    Forward runs furax_chi2 and saves only (m, g, dpsi).  Backward recomputes the
+    pointing and the weighted residual u = N^-1 r on the device, then applies the
+    hand-written adjoint furax_pointing_vjp:
+        d chi2 / d m     = -2 P^T u,
+        d chi2 / d g_k   = -2 sum_i u[k,i] (P_1 m)[k,i],
+        d chi2 / d dpsi_k = -2 sum_i u[k,i] g_k (-2 Q sin 2psi_eff + 2 U cos 2psi_eff).
+    Use through chi2_loss(); P's own gain/dpsi are replaced by the arguments.
+    """
+
+    @staticmethod
+    def forward(ctx, m, gain, dpsi, P, N, d):
+        Pg = P.with_(gain=gain.detach().contiguous(), dpsi=dpsi.detach().contiguous())
+        val, _ = chi2(Pg, N, m.detach().contiguous(), d)
+        ctx.save_for_backward(m, gain, dpsi)
+        ctx.P, ctx.N, ctx.d = P, N, d
+        return val
+
+    @staticmethod
+    def backward(ctx, gout):
+        m, gain, dpsi = ctx.saved_tensors
+        P = ctx.P.with_(gain=gain.detach().contiguous(), dpsi=dpsi.detach().contiguous())
+        m = m.detach().contiguous()
+        _, u = chi2(P, ctx.N, m, ctx.d, want_resid=True)     # pointing recomputed here
+        gm, gg, gd = pointing_vjp(P, m, u, want_map=ctx.needs_input_grad[0],
+                                  want_gain=ctx.needs_input_grad[1],
+                                  want_dpsi=ctx.needs_input_grad[2])
+        s = -2.0 * gout
+        return (None if gm is None else (s * gm).to(m.dtype),
+                None if gg is None else s * gg,
+                None if gd is None else s * gd, None, None, None)
+
+
+def chi2_loss(P: Pointing, N: Noise, d: torch.Tensor, m: torch.Tensor, gain: torch.Tensor,
+              dpsi: torch.Tensor) -> torch.Tensor:
+    """Differentiable chi-square of the data d for the map m, detector gains and
+    polarisation-angle offsets (0-d float64 device tensor)."""
+    if N.kind != "diag":
+        raise ValueError("chi2_loss supports diagonal noise")
+    return Chi2Fn.apply(m, gain, dpsi, P, N, d)
+
+
 def release_caches():
     _lib.furax_release_caches()
 

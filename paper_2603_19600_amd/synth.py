@@ -78,14 +78,18 @@ def stream_key(seed: int, stream: int, sub: int = 0) -> int:
     return _mix64_int(k ^ ((sub + 1) * 0x8CB92BA72F3D8DD7))
 
 
-def uniform(key: int, counter: torch.Tensor) -> torch.Tensor:
-    """U[0,1) doubles: output `counter` of the SplitMix64 sequence started at `key`."""
-    z = (counter.to(torch.int64) + 1) * _s64(_GOLDEN) + _s64(key)
+def uniform(key, counter: torch.Tensor) -> torch.Tensor:
+    """U[0,1) doubles: output `counter` of the SplitMix64 sequence started at `key`.
+
+    key is one stream key (a Python int) or an int64 tensor of signed keys that
+    broadcasts against counter (several streams at once)."""
+    k = key if isinstance(key, torch.Tensor) else _s64(key)
+    z = (counter.to(torch.int64) + 1) * _s64(_GOLDEN) + k
     z = _mix64(z)
     return _srl(z, 11).to(torch.float64) * (2.0 ** -53)
 
 
-def normal(key: int, counter: torch.Tensor) -> torch.Tensor:
+def normal(key, counter: torch.Tensor) -> torch.Tensor:
     """N(0,1) doubles by Box-Muller from the uniform pair (2c, 2c+1)."""
     c = counter.to(torch.int64)
     u1 = uniform(key, 2 * c)
@@ -301,12 +305,15 @@ def noise(w: Workload, det0: int = 0, n_det: Optional[int] = None, i0: int = 0,
         p = psd(w, f)
         p[0] = p[1] if n_samp > 2 else p[0]
         shape = torch.from_numpy(np.sqrt(p) / w.sigma).to(device)
-    for j in range(n_det):
-        key = stream_key(w.seed, 2 + det0 + j, SUB_NOISE)
-        x = normal(key, cnt) * w.sigma
+    chunk = 32                                  # detectors drawn per batch of kernels
+    for j0 in range(0, n_det, chunk):
+        j1 = min(n_det, j0 + chunk)
+        keys = torch.tensor([_s64(stream_key(w.seed, 2 + det0 + j, SUB_NOISE))
+                             for j in range(j0, j1)], dtype=torch.int64, device=device)
+        x = normal(keys[:, None], cnt[None, :]) * w.sigma
         if shape is not None:
-            x = torch.fft.irfft(torch.fft.rfft(x) * shape, n=n_samp)
-        out[j] = x
+            x = torch.fft.irfft(torch.fft.rfft(x, dim=-1) * shape, n=n_samp, dim=-1)
+        out[j0:j1] = x
     return out
 
 
