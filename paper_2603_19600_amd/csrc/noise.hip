@@ -116,18 +116,51 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// exp(-2 pi i j / L) from two LDS tables: hi[j >> kTwLoBits] lo[j & mask].
-constexpr int kTwLoBits = 7;
-template <typename T>
-struct TwTab {
-  const C2<T> *hi, *lo;
-  __device__ __forceinline__ C2<T> operator()(int j) const {
-    return cmul(hi[j >> kTwLoBits], lo[j & ((1 << kTwLoBits) - 1)]);
+// Passes of the length-M FFT: radix 16 while it divides, then 4 and/or 2.
+// Pass p has radix R(p) and span Ns(p) = product of the earlier radices.
+template <int M>
+struct FftPlan {
+  static constexpr int n16 = __builtin_ctz(M) / 4;
+  static constexpr int rem = M >> (4 * n16);
+  static constexpr int npass = n16 + (rem == 8 ? 2 : (rem > 1 ? 1 : 0));
+  static constexpr int R(int p) { return p < n16 ? 16 : (rem == 8 ? (p == n16 ? 4 : 2) : rem); }
+  static constexpr int Ns(int p) {
+    int n = 1;
+    for (int i = 0; i < p; ++i) n *= R(i);
+    return n;
+  }
+  // Twiddle stage t < npass - 1 serves pass t + 1 (pass 0 needs none): its
+  // butterfly k (k < Ns) multiplies by powers of w1(k) = exp(-2 pi i k step / L),
+  // step = L / (R Ns).  The last stage serves the real-spectrum split, where
+  // w1(k) = exp(-2 pi i k / L) for k <= M.
+  static constexpr int nstage = npass;
+  static constexpr int K(int t) { return t < npass - 1 ? Ns(t + 1) : M + 1; }
+  static constexpr int step(int t) { return t < npass - 1 ? 2 * M / (R(t + 1) * Ns(t + 1)) : 1; }
+  static constexpr int nlo(int t) { return K(t) < 128 ? K(t) : 128; }
+  static constexpr int nhi(int t) { return (K(t) + 127) / 128; }
+  static constexpr int off(int t) {
+    int o = 0;
+    for (int i = 0; i < t; ++i) o += nlo(i) + nhi(i);
+    return o;
+  }
+  static constexpr int total = off(nstage);
+};
+
+// w1(k) of one twiddle stage from two small FP64 LDS tables, lo[k mod 128]
+// (step k) and hi[k / 128] (step 128 k): consecutive lanes read consecutive
+// lo entries, so the lookups do not pile onto a few LDS banks.
+struct TwStage {
+  const C2<double> *lo, *hi;
+  __device__ __forceinline__ C2<double> operator()(int k) const {
+    return cmul(hi[k >> 7], lo[k & 127]);
   }
 };
 
-template <typename T, int M, int NT, int R, bool INV, typename TW>
-__device__ __forceinline__ void stockham_pass(C2<T> *s, const TW &tw, int Ns) {
+template <typename T>
+__device__ __forceinline__ C2<T> narrow(C2<double> a) { return {(T)a.x, (T)a.y}; }
+
+template <typename T, int M, int NT, int R, bool INV>
+__device__ __forceinline__ void stockham_pass(C2<T> *s, const TwStage &tw, int Ns) {
   constexpr int NB = M / R;
   constexpr int PER = (NB + NT - 1) / NT;
   const int tid = threadIdx.x;
@@ -147,17 +180,24 @@ __device__ __forceinline__ void stockham_pass(C2<T> *s, const TW &tw, int Ns) {
     if (j >= NB) continue;
     const int k = j & (Ns - 1);
     if (Ns > 1) {
-      const int b = 2 * k * (M / (R * Ns));
+      // powers of w1 = exp(-2 pi i k / (R Ns)), squared in FP64
+      const C2<double> W1 = tw(k);
       if constexpr (R == 16) {
-        const C2<T> w1 = tw(b), w2 = tw(2 * b), w4 = tw(4 * b), w8 = tw(8 * b);
+        const C2<double> W2 = cmul(W1, W1), W4 = cmul(W2, W2), W8 = cmul(W4, W4);
+        const C2<T> w1 = narrow<T>(W1), w2 = narrow<T>(W2), w4 = narrow<T>(W4),
+                    w8 = narrow<T>(W8);
         const C2<T> w3 = cmul(w1, w2), w5 = cmul(w1, w4), w6 = cmul(w2, w4), w7 = cmul(w3, w4);
         const C2<T> w[16] = {w1, w1, w2, w3, w4, w5, w6, w7, w8, cmul(w1, w8), cmul(w2, w8),
                              cmul(w3, w8), cmul(w4, w8), cmul(w5, w8), cmul(w6, w8), cmul(w7, w8)};
 #pragma unroll
         for (int r = 1; r < 16; ++r) v[q][r] = twiddle<T, INV>(v[q][r], w[r]);
+      } else if constexpr (R == 4) {
+        const C2<double> W2 = cmul(W1, W1), W3 = cmul(W1, W2);
+        v[q][1] = twiddle<T, INV>(v[q][1], narrow<T>(W1));
+        v[q][2] = twiddle<T, INV>(v[q][2], narrow<T>(W2));
+        v[q][3] = twiddle<T, INV>(v[q][3], narrow<T>(W3));
       } else {
-#pragma unroll
-        for (int r = 1; r < R; ++r) v[q][r] = twiddle<T, INV>(v[q][r], tw(r * b));
+        v[q][1] = twiddle<T, INV>(v[q][1], narrow<T>(W1));
       }
     }
     const int d = (j - k) * R + k;
@@ -177,24 +217,30 @@ __device__ __forceinline__ void stockham_pass(C2<T> *s, const TW &tw, int Ns) {
   lds_barrier();
 }
 
-template <typename T, int M, int NT, bool INV, typename TW>
-__device__ __forceinline__ void fft_lds(C2<T> *s, const TW &tw) {
-  constexpr int log2m = __builtin_ctz(M);
-  constexpr int n16 = log2m / 4;
-  constexpr int rem = M >> (4 * n16);
+template <int M>
+__device__ __forceinline__ TwStage stage_of(const C2<double> *tab, int t) {
+  using Pl = FftPlan<M>;
+  const int o = Pl::off(t);
+  return {tab + o, tab + o + Pl::nlo(t)};
+}
+
+template <typename T, int M, int NT, bool INV>
+__device__ __forceinline__ void fft_lds(C2<T> *s, const C2<double> *tab) {
+  using Pl = FftPlan<M>;
   int Ns = 1;
 #pragma unroll
-  for (int p = 0; p < n16; ++p) {
-    stockham_pass<T, M, NT, 16, INV>(s, tw, Ns);
+  for (int p = 0; p < Pl::n16; ++p) {
+    stockham_pass<T, M, NT, 16, INV>(s, stage_of<M>(tab, p > 0 ? p - 1 : 0), Ns);
     Ns *= 16;
   }
-  if constexpr (rem == 8) {
-    stockham_pass<T, M, NT, 4, INV>(s, tw, Ns);
-    stockham_pass<T, M, NT, 2, INV>(s, tw, Ns * 4);
-  } else if constexpr (rem == 4) {
-    stockham_pass<T, M, NT, 4, INV>(s, tw, Ns);
-  } else if constexpr (rem == 2) {
-    stockham_pass<T, M, NT, 2, INV>(s, tw, Ns);
+  constexpr int q = Pl::n16;   // index of the first non-radix-16 pass
+  if constexpr (Pl::rem == 8) {
+    stockham_pass<T, M, NT, 4, INV>(s, stage_of<M>(tab, q - 1), Ns);
+    stockham_pass<T, M, NT, 2, INV>(s, stage_of<M>(tab, q), Ns * 4);
+  } else if constexpr (Pl::rem == 4) {
+    stockham_pass<T, M, NT, 4, INV>(s, stage_of<M>(tab, q - 1), Ns);
+  } else if constexpr (Pl::rem == 2) {
+    stockham_pass<T, M, NT, 2, INV>(s, stage_of<M>(tab, q - 1), Ns);
   }
 }
 
@@ -219,15 +265,21 @@ __global__ void __launch_bounds__(NT) k_overlap_save(const T *__restrict__ in, T
                                                      int64_t n, int32_t b, int64_t nblk,
                                                      int64_t ntask, const T *__restrict__ spec,
                                                      int64_t spec_stride,
-                                                     const C2<T> *__restrict__ tw) {
+                                                     const C2<double> *__restrict__ tw) {
   __shared__ C2<T> s[M + M / 16];
   constexpr int L = 2 * M;
-  __shared__ C2<T> tw_hi[L >> kTwLoBits], tw_lo[1 << kTwLoBits];
+  using Pl = FftPlan<M>;
+  __shared__ C2<double> tab[Pl::total];
   const int V = L - 2 * (b - 1);
   const int tid = threadIdx.x;
-  for (int j = tid; j < (L >> kTwLoBits); j += NT) tw_hi[j] = tw[j << kTwLoBits];
-  for (int j = tid; j < (1 << kTwLoBits); j += NT) tw_lo[j] = tw[j];
-  const TwTab<T> W = {tw_hi, tw_lo};
+  // twiddle stage tables from the FP64 table tw[j] = exp(-2 pi i j / L)
+#pragma unroll
+  for (int t = 0; t < Pl::nstage; ++t) {
+    const int o = Pl::off(t), nl = Pl::nlo(t), st = Pl::step(t);
+    for (int i = tid; i < nl; i += NT) tab[o + i] = tw[st * i];
+    for (int i = tid; i < Pl::nhi(t); i += NT) tab[o + nl + i] = tw[st * 128 * i];
+  }
+  const TwStage W = stage_of<M>(tab, Pl::nstage - 1);   // the split's twiddles
 
   const int64_t t_beg = PREFETCH ? ntask * blockIdx.x / gridDim.x
                                  : xcd_remap(blockIdx.x, (int64_t)gridDim.x);
@@ -255,7 +307,7 @@ __global__ void __launch_bounds__(NT) k_overlap_save(const T *__restrict__ in, T
     for (int q = 0; q < PER; ++q) s[pad16(tid + q * NT)] = buf[q];
     if (PREFETCH && t + 1 < t_end) fetch(t + 1);   // in flight during this task's transforms
     lds_barrier();
-    fft_lds<T, M, NT, false>(s, W);
+    fft_lds<T, M, NT, false>(s, tab);
 
     const int64_t det = t / nblk, blk = t - det * nblk;
     const T *H = spec + det * spec_stride;   // H[0..M], already divided by M
@@ -274,7 +326,7 @@ __global__ void __launch_bounds__(NT) k_overlap_save(const T *__restrict__ in, T
         const C2<T> O = {Dh.y, -Dh.x};              // (Z[k] - conj Z[M-k]) / (2i)
         const T Hk = H[kk], Hm = H[M - kk];
         const T hp = (Hk + Hm) * (T)0.5, hm = (Hk - Hm) * (T)0.5;
-        const C2<T> Wk = W(kk);                     // exp(-2 pi i kk / L)
+        const C2<T> Wk = narrow<T>(W(kk));          // exp(-2 pi i kk / L)
         const C2<T> A = cadd(cscale(E, hp), cscale(cmul(Wk, O), hm));
         const C2<T> B = cadd(cscale(cmulc(E, Wk), hm), cscale(O, hp));
         const C2<T> r = {A.x - B.y, A.y + B.x};     // A + i B
@@ -284,7 +336,7 @@ __global__ void __launch_bounds__(NT) k_overlap_save(const T *__restrict__ in, T
       if (k2 != k) s[pad16(k2)] = r2;
     }
     lds_barrier();
-    fft_lds<T, M, NT, true>(s, W);
+    fft_lds<T, M, NT, true>(s, tab);
 
     const int64_t s0 = blk * V - (b - 1);
     T *z = out + det * n;
@@ -325,13 +377,13 @@ __global__ void __launch_bounds__(kBlock) k_spectrum(const double *__restrict__ 
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_twiddles(int32_t L, C2<double> *tw64, C2<float> *tw32) {
+// tw64[j] = exp(-2 pi i j / L) in FP64 (both precisions' FFTs read it).
+__global__ void __launch_bounds__(kBlock) k_twiddles(int32_t L, C2<double> *tw64) {
   const int j = blockIdx.x * kBlock + threadIdx.x;
   if (j >= L) return;
   double s, c;
   sincospi(2.0 * (double)j / (double)L, &s, &c);
   tw64[j] = {c, -s};
-  if (tw32) tw32[j] = {(float)c, (float)-s};
 }
 
 template <typename T, int M, int NT>
@@ -350,7 +402,6 @@ __global__ void __launch_bounds__(kBlock) k_diag(const T *__restrict__ in, T *__
 // ---------------------------------------------------------------------------
 struct TwTables {
   C2<double> *tw64 = nullptr;
-  C2<float> *tw32 = nullptr;
 };
 static std::mutex g_tw_mu;
 static std::map<std::pair<int, int>, TwTables> g_tw;   // (device, L) -> tables
@@ -365,13 +416,9 @@ static furax_status get_twiddles(int L, hipStream_t s, TwTables &out) {
     return FURAX_OK;
   }
   TwTables t;
-  FX_HIP(hipMalloc(&t.tw64, sizeof(C2<double>) * L));
-  if (hipMalloc(&t.tw32, sizeof(C2<float>) * L) != hipSuccess) {
-    (void)hipFree(t.tw64);
+  if (hipMalloc(&t.tw64, sizeof(C2<double>) * L) != hipSuccess)
     return set_error(FURAX_ENOMEM, "twiddle table allocation failed");
-  }
-  hipLaunchKernelGGL(k_twiddles, dim3((L + kBlock - 1) / kBlock), dim3(kBlock), 0, s, L, t.tw64,
-                     t.tw32);
+  hipLaunchKernelGGL(k_twiddles, dim3((L + kBlock - 1) / kBlock), dim3(kBlock), 0, s, L, t.tw64);
   FX_HIP(hipGetLastError());
   g_tw[{dev, L}] = t;
   out = t;
@@ -386,7 +433,6 @@ void release_twiddles() {
     (void)hipSetDevice(kv.first.first);
     (void)hipDeviceSynchronize();
     (void)hipFree(kv.second.tw64);
-    (void)hipFree(kv.second.tw32);
     (void)hipSetDevice(cur);
   }
   g_tw.clear();
@@ -439,7 +485,7 @@ template furax_status noise_prepare<double>(const furax_noise *, void *, hipStre
 
 template <typename T, int M, int NT>
 static furax_status launch_os(const furax_noise *N, const T *in, T *out, const T *spec,
-                              const C2<T> *tw, hipStream_t s) {
+                              const C2<double> *tw, hipStream_t s) {
   const int b = (int)N->bandwidth;
   const int64_t V = 2 * M - 2 * (int64_t)(b - 1);
   const int64_t nblk = (N->n_samp + V - 1) / V;
@@ -468,8 +514,7 @@ furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *sp
   TwTables tw;
   FX_TRY(get_twiddles(2 * M, s, tw));
   const T *sp = static_cast<const T *>(spec);
-  const C2<T> *t = reinterpret_cast<const C2<T> *>(sizeof(T) == 4 ? (const void *)tw.tw32
-                                                                  : (const void *)tw.tw64);
+  const C2<double> *t = tw.tw64;   // FP64 twiddles for both precisions
   switch (M) {
     case 512: return launch_os<T, 512, 64>(N, in, out, sp, t, s);
     case 1024: return launch_os<T, 1024, 64>(N, in, out, sp, t, s);
