@@ -155,7 +155,12 @@ furax_status furax_bj_invert(int64_t npix, const double *M6, const int32_t *hits
  *   valid: [npix] uint8 or NULL.  When given, samples in pixels with
  *          valid = 0 are flagged (read 0, contribute nothing).
  *   work: device scratch of furax_normal_workspace_bytes() bytes, or NULL to
- *         let the library allocate it stream-ordered for this call. */
+ *         let the library allocate it stream-ordered for this call.
+ * With band N and a power-of-two nside the call also builds, stream-ordered,
+ * the per-sample schedule of its P^T (samples sorted by nested superpixel of
+ * 1024 pixels) and frees it before returning; a PCG session builds that
+ * schedule once and reuses it for every iteration.  Its P^T sums in a fixed
+ * order, so q is reproducible bit for bit from run to run. */
 int64_t furax_normal_workspace_bytes(const furax_pointing *P, const furax_noise *N,
                                      int32_t precision);
 furax_status furax_normal_apply(const furax_pointing *P, const furax_noise *N, int32_t precision,
