@@ -11,7 +11,8 @@ Conventions fixed here (the paper is silent on all of them):
   * tt = phi_reduced / (pi/2) with a true division;
   * the equatorial branch is |z| <= 2/3 with the double constant 2.0/3.0;
   * every floor is of a non-negative value;
-  * theta outside [0, pi] or a non-finite angle gives pixel -1 (flagged).
+  * theta outside [0, pi] or a non-finite angle gives pixel -1 (flagged);
+    given z = cos(theta) directly (zphi2pix_ring), z outside [-1, 1] does.
   * no fused multiply-add: every product and sum is rounded on its own
     (NumPy element-wise arithmetic never fuses).
 
@@ -42,22 +43,37 @@ def ang2pix_ring(nside: int, theta, phi) -> np.ndarray:
     theta = np.asarray(theta, dtype=np.float64)
     phi = np.asarray(phi, dtype=np.float64)
     theta, phi = np.broadcast_arrays(theta, phi)
+    valid = np.isfinite(theta) & np.isfinite(phi) & (theta >= 0.0) & (theta <= math.pi)
+    th = np.where(valid, theta, 0.5)
+    return _pix_of_z(nside, np.cos(th), np.where(valid, phi, 0.0), valid)
+
+
+def zphi2pix_ring(nside: int, z, phi) -> np.ndarray:
+    """Ring-scheme pixel of each direction given by z = cos(theta) and phi.
+
+    This is the same pixelisation with the cosine already known (a direction
+    vector's third component, as quaternion pointing produces it).  Returns -1
+    where the input is non-finite or z is outside [-1, 1].
+    """
+    z = np.asarray(z, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    z, phi = np.broadcast_arrays(z, phi)
+    valid = np.isfinite(z) & np.isfinite(phi) & (z >= -1.0) & (z <= 1.0)
+    return _pix_of_z(nside, np.where(valid, z, 0.0), np.where(valid, phi, 0.0), valid)
+
+
+def _pix_of_z(nside: int, z, ph, valid) -> np.ndarray:
     N = float(nside)
     n = int(nside)
     npx = npix(n)
     ncap = 2 * n * (n - 1)
 
-    valid = np.isfinite(theta) & np.isfinite(phi) & (theta >= 0.0) & (theta <= math.pi)
-    th = np.where(valid, theta, 0.5)
-    ph = np.where(valid, phi, 0.0)
-
-    z = np.cos(th)
     za = np.abs(z)
     phr = np.fmod(ph, TWO_PI)
     phr = np.where(phr < 0.0, phr + TWO_PI, phr)
     tt = phr / HALF_PI                                  # in [0, 4]
 
-    out = np.full(theta.shape, -1, dtype=np.int64)
+    out = np.full(z.shape, -1, dtype=np.int64)
 
     # Equatorial belt: |z| <= 2/3.
     eq = za <= TWO_THIRDS

@@ -41,6 +41,8 @@ import numpy as np
 
 from . import noise as _noise
 from . import pointing as _pt
+from . import quaternion as _quat
+from .healpix import zphi2pix_ring
 
 STOP_MAXITER = 0
 STOP_RTOL = 1
@@ -136,22 +138,32 @@ class Problem:
     gain: np.ndarray | None = None
     dpsi: np.ndarray | None = None
     hwp: tuple | None = None            # (num, den, phase0)
+    bore_quat: np.ndarray | None = None # [n_samp, 4]: quaternion pointing (theta/phi/psi None)
+    det_quat: np.ndarray | None = None  # [n_det, 4]
 
     @property
     def npix(self):
         return 12 * self.nside * self.nside
 
+    @property
+    def n_det(self):
+        return self.det_quat.shape[0] if self.bore_quat is not None else self.theta.shape[0]
+
     def geometry(self):
-        pix = _pt.pixels(self.nside, self.theta, self.phi)
-        c, s = _pt.weights(self.psi, self.dpsi, self.hwp)
+        if self.bore_quat is not None:
+            z, phi, psi = _quat.expand(self.bore_quat, self.det_quat)
+            pix = zphi2pix_ring(self.nside, z, phi)
+        else:
+            pix = _pt.pixels(self.nside, self.theta, self.phi)
+            psi = self.psi
+        c, s = _pt.weights(psi, self.dpsi, self.hwp)
         return pix, c, s
 
     def ninv(self, y):
         return _noise.noise_apply(self.noise_kind, y, self.inv_var, self.lags)
 
     def wdiag(self):
-        return _noise.diag_of_inverse(self.noise_kind, self.theta.shape[0], self.inv_var,
-                                      self.lags)
+        return _noise.diag_of_inverse(self.noise_kind, self.n_det, self.inv_var, self.lags)
 
 
 def flag_invalid(pix, valid) -> np.ndarray:

@@ -109,6 +109,7 @@ class Workload:
     bandwidth: int = 1            # number of Toeplitz lags t[0..b-1]
     hwp: bool = False
     dtype: str = "f64"            # canonical pointing / TOD dtype: "f64" or "f32"
+    pointing: str = "angles"      # "angles": theta/phi/psi planes; "quat": boresight quaternions
     iters: int = 20
     offsets_deg: float = 1.0      # detector offsets uniform in +-offsets_deg (0: boresight)
     fs: float = 50.0              # sampling rate [Hz]
@@ -255,6 +256,66 @@ def pointing(w: Workload, det0: int = 0, n_det: Optional[int] = None, i0: int = 
             psi[j] = (uniform(key, counters) * two_pi).to(dt)
         del v
     return Pointing(theta, phi, psi)
+
+
+# ---------------------------------------------------------------------------
+# Boresight-quaternion form of the same scan: one attitude per sample for the
+# telescope and one fixed attitude per detector.  Quaternions are (w, x, y, z),
+# scalar first; the scan's own rotations are composed here only to MAKE the
+# boresight attitudes (input generation).
+# ---------------------------------------------------------------------------
+def _axis_quat(axis: str, a: torch.Tensor) -> torch.Tensor:
+    """Unit quaternion of a right-handed rotation by angle a about a coordinate axis."""
+    h = 0.5 * a
+    q = torch.zeros(a.shape + (4,), dtype=torch.float64, device=a.device)
+    q[..., 0] = torch.cos(h)
+    q[..., "xyz".index(axis) + 1] = torch.sin(h)
+    return q
+
+
+def _compose(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+    """Attitude a followed by b in the body frame (quaternion product a b)."""
+    aw, ax, ay, az = a.unbind(-1)
+    bw, bx, by, bz = b.unbind(-1)
+    return torch.stack([aw * bw - ax * bx - ay * by - az * bz,
+                        aw * bx + ax * bw + ay * bz - az * by,
+                        aw * by - ax * bz + ay * bw + az * bx,
+                        aw * bz + ax * by - ay * bx + az * bw], -1)
+
+
+def boresight_quaternions(w: Workload, i0: int = 0, n: Optional[int] = None,
+                          device="cpu") -> torch.Tensor:
+    """Boresight attitude of samples i0..i0+n-1, [n, 4] float64: the scan of
+    boresight_rotations (R(q) equals that rotation matrix)."""
+    n = w.n_samp - i0 if n is None else n
+    key = stream_key(w.seed, STREAM_SCAN, 0)
+    ph = uniform(key, torch.arange(2)) * (2.0 * math.pi)
+    t = torch.arange(i0, i0 + n, dtype=torch.float64, device=device) / w.fs
+    wp = 2.0 * math.pi / w.prec_period
+    ws = 2.0 * math.pi / w.spin_period
+    one = torch.ones((), dtype=torch.float64, device=device)
+    q = _axis_quat("y", one * (math.pi / 2))
+    q = _compose(q, _axis_quat("z", wp * t + float(ph[0])))
+    q = _compose(q, _axis_quat("y", one * math.radians(w.prec_angle_deg)))
+    q = _compose(q, _axis_quat("z", ws * t + float(ph[1])))
+    q = _compose(q, _axis_quat("y", one * math.radians(w.spin_angle_deg)))
+    return q / torch.linalg.vector_norm(q, dim=-1, keepdim=True)
+
+
+def detector_quaternions(w: Workload, det0: int = 0, n_det: Optional[int] = None,
+                         device="cpu") -> torch.Tensor:
+    """Detector attitudes relative to the boresight, [n_det, 4] float64: the
+    focal-plane offset of detector_offsets (R_x(dy) R_y(dx)) followed by a turn
+    of the polarisation direction about the line of sight by (k mod 4) pi/4
+    (the usual four orientations of a focal plane)."""
+    n_det = w.n_det - det0 if n_det is None else n_det
+    dets = torch.arange(det0, det0 + n_det)
+    offs = detector_offsets(w, dets)
+    chi = (dets % 4).to(torch.float64) * (math.pi / 4)
+    q = _compose(_compose(_axis_quat("x", offs[:, 1]), _axis_quat("y", offs[:, 0])),
+                 _axis_quat("z", chi))
+    q = q / torch.linalg.vector_norm(q, dim=-1, keepdim=True)
+    return q.to(device)
 
 
 def sky_map(w: Workload, device="cpu") -> torch.Tensor:
