@@ -71,20 +71,42 @@ typedef enum { FURAX_F32 = 0, FURAX_F64 = 1 } furax_dtype;
  * ideal-HWP identity R(t) o HWP = HWP o R(-t) ("Algebraic reductions"); the
  * HWP angle is formed from integers so that long scans keep full precision.
  * Pointing is expanded on the fly at every application, never stored
- * (PointingOperator, "Map-making classes"). */
+ * (PointingOperator, "Map-making classes").
+ *
+ * Two representations of the pointing are accepted:
+ *  - angle planes: theta, phi, psi given per sample (bore_quat = det_quat =
+ *    NULL), in the dtype of the struct;
+ *  - boresight quaternions (theta = phi = psi = NULL): the time-dependent
+ *    telescope attitude q_b[i] ([n_samp][4] FP64, (w, x, y, z), unit norm)
+ *    and each detector's fixed attitude relative to it q_k ([n_det][4] FP64).
+ *    Every application expands, per sample, q = q_b[i] (x) q_k (Hamilton
+ *    product), the line of sight d = R(q) z_hat and the polarisation
+ *    direction e = R(q) x_hat; then
+ *        p   = ring pixel of (z = d_z clipped to [-1, 1], phi = atan2(d_y, d_x)),
+ *        psi = atan2(-e . e_phi, -e . e_theta)   (from local north towards
+ *              west, the HEALPix convention; 0 where both vanish),
+ *    and the formulas above apply with that psi.  The rotation is evaluated
+ *    in FP64 without fused multiply-add in both precisions, so pixels are
+ *    those of a plain IEEE evaluation (up to a 1-ulp difference of atan2).
+ *    dtype then selects the TOD precision and the precision of the
+ *    polariser products.  Both arrays must be 16-byte aligned.  The per-sample
+ *    pointing stream disappears: 32 bytes per time sample serve every
+ *    detector. */
 typedef struct {
   int64_t nside;           /* 1 <= nside <= 8192                                     */
   int64_t n_det, n_samp;   /* n_det >= 1, n_samp >= 0                                */
   int32_t dtype;           /* furax_dtype of theta/phi/psi                           */
-  const void *theta;       /* [n_det][n_samp]                                        */
-  const void *phi;         /* [n_det][n_samp]                                        */
-  const void *psi;         /* [n_det][n_samp]                                        */
+  const void *theta;       /* [n_det][n_samp], or NULL with bore_quat                */
+  const void *phi;         /* [n_det][n_samp], or NULL with bore_quat                */
+  const void *psi;         /* [n_det][n_samp], or NULL with bore_quat                */
   const double *gain;      /* [n_det] or NULL (all 1)                                */
   const double *dpsi;      /* [n_det] or NULL (all 0): polarisation-angle offsets    */
   int32_t hwp;             /* 0: no half-wave plate, 1: ideal HWP                    */
   int64_t hwp_num;         /* HWP turns per hwp_den samples (f_hwp / f_samp = num/den) */
   int64_t hwp_den;         /* > 0 when hwp = 1                                       */
   double hwp_phase0;       /* HWP angle at sample 0                                  */
+  const double *bore_quat; /* [n_samp][4] or NULL: boresight attitude per sample     */
+  const double *det_quat;  /* [n_det][4] (with bore_quat): detector attitudes        */
 } furax_pointing;
 
 /* N^-1, block-diagonal over detectors (BlockDiagonalOperator of Table 2).
@@ -140,7 +162,10 @@ furax_status furax_noise_apply(const furax_noise *N, int32_t dt, const void *tod
  * furax_bj_invert then writes Minv6 [6][npix] and valid [npix] (1 iff
  * hits >= min_hits and the 1-norm reciprocal condition number
  * 1/(|M|_1 |M^-1|_1) >= rcond_min; Minv is 0 elsewhere) and, if rcond is not
- * NULL, rcond [npix] FP64. */
+ * NULL, rcond [npix] FP64.  M^-1 comes from the Cholesky factorisation of the
+ * (positive semi-definite) block, so a block that is singular in exact
+ * arithmetic gets a tiny rcond; a non-positive pivot gives rcond 0 and
+ * Minv 0. */
 furax_status furax_bj_build(const furax_pointing *P, const furax_noise *N, double *M6,
                             int32_t *hits, hipStream_t stream);
 furax_status furax_bj_invert(int64_t npix, const double *M6, const int32_t *hits,

@@ -24,6 +24,8 @@ import numpy as np
 
 from . import noise as _noise
 from . import pointing as _pt
+from . import quaternion as _quat
+from .healpix import zphi2pix_ring
 
 
 def chi2(nside, theta, phi, psi, d, m, gain, dpsi, noise_kind="diag", inv_var=None,
@@ -37,10 +39,24 @@ def chi2(nside, theta, phi, psi, d, m, gain, dpsi, noise_kind="diag", inv_var=No
 def chi2_grad(nside, theta, phi, psi, d, m, gain, dpsi, noise_kind="diag", inv_var=None,
               lags=None, hwp=None):
     """(chi2, grad_m [3, npix], grad_gain [n_det], grad_dpsi [n_det])."""
-    m = np.asarray(m, dtype=np.float64)
-    gain = np.asarray(gain, dtype=np.float64)
     pix = _pt.pixels(nside, theta, phi)
     c, s = _pt.weights(psi, dpsi, hwp)
+    return chi2_grad_geom(nside, pix, c, s, d, m, gain, noise_kind, inv_var, lags)
+
+
+def chi2_grad_quat(nside, bore_quat, det_quat, d, m, gain, dpsi, noise_kind="diag",
+                   inv_var=None, lags=None, hwp=None):
+    """chi2_grad with boresight-quaternion pointing (quaternion.expand gives psi)."""
+    z, phi, psi = _quat.expand(bore_quat, det_quat)
+    pix = zphi2pix_ring(nside, z, phi)
+    c, s = _pt.weights(psi, dpsi, hwp)
+    return chi2_grad_geom(nside, pix, c, s, d, m, gain, noise_kind, inv_var, lags)
+
+
+def chi2_grad_geom(nside, pix, c, s, d, m, gain, noise_kind="diag", inv_var=None, lags=None):
+    """chi2 and its gradient given each sample's pixel and weights at psi_eff."""
+    m = np.asarray(m, dtype=np.float64)
+    gain = np.asarray(gain, dtype=np.float64)
     s1 = _pt.apply_pix(pix, c, s, m)                  # unit-gain signal P_1 m
     sig = gain[:, None] * s1
     r = np.asarray(d, dtype=np.float64) - sig

@@ -81,33 +81,55 @@ def sym3(M6) -> np.ndarray:
 
 
 def bj_invert(M6, hits, rcond_min: float = 1e-3, min_hits: int = 3):
-    """Closed-form (adjugate / determinant) inverse of each 3x3 block.
+    """Inverse of each symmetric 3x3 block from its Cholesky factorisation.
+
+    The blocks are sums of w (1, c, s)^T (1, c, s) with w > 0, hence positive
+    semi-definite, and M = L L^T is the backward-stable way to invert them:
+    a block that is singular in exact arithmetic (every sample of the pixel at
+    the same polariser angle, or at two angles pi/2 apart) meets a pivot that
+    is zero, negative or of rounding size, so its computed inverse is huge and
+    its rcond tiny.  (The adjugate / determinant formula does not have that
+    property: for a rank-one block every cofactor is rounding noise and their
+    ratio can be of order one.)  M^-1 = L^-T L^-1 with L^-1 formed by forward
+    substitution.
 
     Returns (Minv [6, npix], valid [npix] bool, rcond [npix]).  rcond is the
-    1-norm reciprocal condition number 1 / (||M||_1 ||M^-1||_1); it is 0
-    where the determinant vanishes.
+    1-norm reciprocal condition number 1 / (||M||_1 ||M^-1||_1); a block
+    whose factorisation meets a non-positive pivot has inverse 0 and rcond 0.
     """
-    a, b, c, d, e, f = M6
-    # cofactors of [[a b c] [b d e] [c e f]]
-    A = d * f - e * e
-    B = c * e - b * f
-    C = b * e - c * d
-    D = a * f - c * c
-    E = b * c - a * e
-    F = a * d - b * b
-    det = a * A + b * B + c * C
+    a, b, c, d, e, f = (np.asarray(v, dtype=np.float64) for v in M6)
     with np.errstate(divide="ignore", invalid="ignore"):
-        inv = np.stack([A, B, C, D, E, F]) / det
-    n1 = np.maximum.reduce([np.abs(a) + np.abs(b) + np.abs(c),
-                            np.abs(b) + np.abs(d) + np.abs(e),
-                            np.abs(c) + np.abs(e) + np.abs(f)])
-    ia, ib, ic, id_, ie, if_ = inv
-    n1i = np.maximum.reduce([np.abs(ia) + np.abs(ib) + np.abs(ic),
-                             np.abs(ib) + np.abs(id_) + np.abs(ie),
-                             np.abs(ic) + np.abs(ie) + np.abs(if_)])
-    with np.errstate(divide="ignore", invalid="ignore"):
+        l11 = np.sqrt(a)
+        l21 = b / l11
+        l31 = c / l11
+        t22 = d - l21 * l21
+        l22 = np.sqrt(t22)
+        l32 = (e - l31 * l21) / l22
+        t33 = f - l31 * l31 - l32 * l32
+        l33 = np.sqrt(t33)
+        i11 = 1.0 / l11
+        i22 = 1.0 / l22
+        i33 = 1.0 / l33
+        i21 = -(l21 * i11) * i22
+        i32 = -(l32 * i22) * i33
+        i31 = -(l31 * i11 + l32 * i21) * i33
+        inv = np.stack([i11 * i11 + i21 * i21 + i31 * i31,
+                        i21 * i22 + i31 * i32,
+                        i31 * i33,
+                        i22 * i22 + i32 * i32,
+                        i32 * i33,
+                        i33 * i33])
+        ok = (a > 0.0) & (t22 > 0.0) & (t33 > 0.0) & np.isfinite(inv).all(axis=0)
+        inv = np.where(ok[None, :], inv, 0.0)
+        n1 = np.maximum.reduce([np.abs(a) + np.abs(b) + np.abs(c),
+                                np.abs(b) + np.abs(d) + np.abs(e),
+                                np.abs(c) + np.abs(e) + np.abs(f)])
+        ia, ib, ic, id_, ie, if_ = inv
+        n1i = np.maximum.reduce([np.abs(ia) + np.abs(ib) + np.abs(ic),
+                                 np.abs(ib) + np.abs(id_) + np.abs(ie),
+                                 np.abs(ic) + np.abs(ie) + np.abs(if_)])
         rcond = 1.0 / (n1 * n1i)
-    rcond = np.where(np.isfinite(rcond) & (det != 0.0), rcond, 0.0)
+    rcond = np.where(ok & np.isfinite(rcond), rcond, 0.0)
     valid = (hits >= min_hits) & (rcond >= rcond_min)
     inv = np.where(valid[None, :], inv, 0.0)
     return inv, valid, rcond

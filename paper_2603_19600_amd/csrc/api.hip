@@ -43,8 +43,16 @@ furax_status check_pointing(const furax_pointing *P) {
   if (P->n_det > ((int64_t)1 << 31) || P->n_samp > ((int64_t)1 << 40))
     return set_error(FURAX_EINVAL, "pointing too large");
   if (!dtype_ok(P->dtype)) return set_error(FURAX_EINVAL, "pointing dtype must be F32 or F64");
-  if (P->n_samp > 0 && (!P->theta || !P->phi || !P->psi))
+  if (P->bore_quat || P->det_quat) {
+    if (P->theta || P->phi || P->psi)
+      return set_error(FURAX_EINVAL, "give either theta/phi/psi or quaternions, not both");
+    if (!P->det_quat || (P->n_samp > 0 && !P->bore_quat))
+      return set_error(FURAX_EINVAL, "quaternion pointing needs bore_quat and det_quat");
+    if ((reinterpret_cast<uintptr_t>(P->bore_quat) | reinterpret_cast<uintptr_t>(P->det_quat)) & 15)
+      return set_error(FURAX_EINVAL, "quaternion arrays must be 16-byte aligned");
+  } else if (P->n_samp > 0 && (!P->theta || !P->phi || !P->psi)) {
     return set_error(FURAX_EINVAL, "theta, phi and psi must be non-NULL");
+  }
   if (P->hwp != 0 && P->hwp != 1) return set_error(FURAX_EINVAL, "hwp must be 0 or 1");
   if (P->hwp && (P->hwp_den <= 0 || P->hwp_num < 0))
     return set_error(FURAX_EINVAL, "hwp requires hwp_den > 0 and hwp_num >= 0");
@@ -133,7 +141,7 @@ extern "C" {
 
 const char *furax_last_error(void) { return g_last_error.c_str(); }
 
-int32_t furax_version(void) { return 100; }
+int32_t furax_version(void) { return 200; }
 
 void furax_release_caches(void) { release_twiddles(); }
 

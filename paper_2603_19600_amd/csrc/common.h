@@ -45,22 +45,20 @@ struct PtArgs {
   int64_t hwp_num_mod, hwp_den;   // hwp_num reduced mod hwp_den
   double hwp_phase0;
   const uint8_t *valid; // [npix] or null: samples in pixels with valid == 0 are flagged
+  const double *qb;     // [n_samp][4] boresight attitudes, or null (angle planes)
+  const double *qd;     // [n_det][4] detector attitudes (with qb)
 };
 
-// HEALPix ring-scheme ang2pix in FP64 (ring-scheme formulas of Gorski et al.
-// 2005).  Every operation is rounded on its own (no contraction) so that the
-// result equals a plain IEEE evaluation of the same expression sequence; the
-// only libm call is cos().  Returns -1 for non-finite input or theta outside
-// [0, pi].
-__device__ __forceinline__ int32_t ang2pix_ring(int32_t n, double theta, double phi) {
+// HEALPix ring-scheme pixel in FP64 (ring-scheme formulas of Gorski et al.
+// 2005) of the direction with z = cos(theta) and longitude phi, both already
+// validated.  Every operation is rounded on its own (no contraction) so that
+// the result equals a plain IEEE evaluation of the same expression sequence.
+__device__ __forceinline__ int32_t pix_of_z(int32_t n, double z, double phi) {
 #pragma clang fp contract(off)
-  if (!(theta >= 0.0 && theta <= kPi)) return -1;      // also rejects NaN
-  if (!(phi - phi == 0.0)) return -1;                   // rejects NaN and +-inf
   const double N = (double)n;
   const double two_pi = 2.0 * kPi;
   constexpr double half_pi_c = 0.5 * kPi;
   const double half_pi = half_pi_c;
-  const double z = cos(theta);
   const double za = fabs(z);
   // fmod(phi, 2 pi) is phi itself on [0, 2 pi): skip the library call there
   double phr = (phi >= 0.0 && phi < two_pi) ? phi : fmod(phi, two_pi);
@@ -95,6 +93,70 @@ __device__ __forceinline__ int32_t ang2pix_ring(int32_t n, double theta, double 
   return ((uint32_t)pix < (uint32_t)(12 * n * n)) ? pix : -1;
 }
 
+// Ring pixel of (theta, phi); the only libm call on the way is cos().
+// Returns -1 for non-finite input or theta outside [0, pi].
+__device__ __forceinline__ int32_t ang2pix_ring(int32_t n, double theta, double phi) {
+  if (!(theta >= 0.0 && theta <= kPi)) return -1;      // also rejects NaN
+  if (!(phi - phi == 0.0)) return -1;                   // rejects NaN and +-inf
+  return pix_of_z(n, cos(theta), phi);
+}
+
+// Ring pixel of (z, phi); -1 for non-finite input or z outside [-1, 1].
+__device__ __forceinline__ int32_t zphi2pix_ring(int32_t n, double z, double phi) {
+  if (!(z >= -1.0 && z <= 1.0)) return -1;
+  if (!(phi - phi == 0.0)) return -1;
+  return pix_of_z(n, z, phi);
+}
+
+// ---------------------------------------------------------------------------
+// Boresight-quaternion pointing: a sample's attitude is q_b[i] (x) q_k
+// (Hamilton product of (w, x, y, z) quaternions), its line of sight
+// d = R(q) z_hat and its polarisation direction e = R(q) x_hat.
+// ---------------------------------------------------------------------------
+struct Quat {
+  double w, x, y, z;
+};
+
+__device__ __forceinline__ Quat load_quat(const double *q, int64_t idx) {
+  const double2 *p = reinterpret_cast<const double2 *>(q + 4 * idx);   // 16-byte aligned
+  const double2 a = p[0], b = p[1];
+  return {a.x, a.y, b.x, b.y};
+}
+
+__device__ __forceinline__ Quat qmul(const Quat &a, const Quat &b) {
+#pragma clang fp contract(off)
+  return {a.w * b.w - a.x * b.x - a.y * b.y - a.z * b.z,
+          a.w * b.x + a.x * b.w + a.y * b.z - a.z * b.y,
+          a.w * b.y - a.x * b.z + a.y * b.w + a.z * b.x,
+          a.w * b.z + a.x * b.y - a.y * b.x + a.z * b.w};
+}
+
+// What the pointing needs of an attitude: z = d_z clipped to [-1, 1] (NaN
+// kept), phi = atan2(d_y, d_x), and the polarisation direction's components
+// towards local west and local north scaled by sin(theta):
+//   west  = -e . e_phi   * sin(theta) = d_y e_x - d_x e_y,
+//   north = -e . e_theta * sin(theta) = e_z        (e is orthogonal to d),
+// so that psi = atan2(west, north).
+struct QuatDir {
+  double z, phi, west, north;
+};
+
+__device__ __forceinline__ QuatDir quat_dir(const Quat &q) {
+#pragma clang fp contract(off)
+  const double dx = 2.0 * (q.x * q.z + q.w * q.y);
+  const double dy = 2.0 * (q.y * q.z - q.w * q.x);
+  const double dz = 1.0 - 2.0 * (q.x * q.x + q.y * q.y);
+  const double ex = 1.0 - 2.0 * (q.y * q.y + q.z * q.z);
+  const double ey = 2.0 * (q.x * q.y + q.w * q.z);
+  const double ez = 2.0 * (q.x * q.z - q.w * q.y);
+  QuatDir g;
+  g.z = dz < -1.0 ? -1.0 : (dz > 1.0 ? 1.0 : dz);
+  g.phi = atan2(dy, dx);
+  g.west = dy * ex - dx * ey;
+  g.north = ez;
+  return g;
+}
+
 // HWP angle alpha_i = 2 pi ((num * i) mod den) / den + phase0, from integers.
 __device__ __forceinline__ double hwp_alpha(int64_t i, int64_t num_mod, int64_t den,
                                             double phase0) {
@@ -126,6 +188,32 @@ __device__ __forceinline__ void weights(double ang, float &c, float &s) {
   sincosf((float)r, &s, &c);
 }
 
+// cos / sin of 2 (psi + beta) where psi = atan2(west, north): cos 2 psi and
+// sin 2 psi follow from (west, north) algebraically in FP64, and the turn by
+// 2 beta (detector angle offset plus twice the HWP angle) is applied with the
+// precision's weights() of that angle.  psi = 0 where west = north = 0.
+template <typename T>
+__device__ __forceinline__ void quat_weights(const QuatDir &g, bool has_beta, double beta, T &c,
+                                             T &s) {
+#pragma clang fp contract(off)
+  const double ww = g.west * g.west, nn = g.north * g.north, r2 = ww + nn;
+  double c2 = 1.0, s2 = 0.0;
+  if (r2 > 0.0) {
+    c2 = (nn - ww) / r2;
+    s2 = (2.0 * (g.west * g.north)) / r2;
+  }
+  if (!has_beta) {
+    c = (T)c2;
+    s = (T)s2;
+    return;
+  }
+  T cb, sb;
+  weights(2.0 * beta, cb, sb);
+  const T ct = (T)c2, st = (T)s2;
+  c = ct * cb - st * sb;
+  s = st * cb + ct * sb;
+}
+
 // Geometry of one sample: pixel (or -1) and polariser weights.
 template <typename T>
 struct Geom {
@@ -135,11 +223,20 @@ struct Geom {
 
 template <typename T>
 __device__ __forceinline__ Geom<T> sample_geom(const PtArgs<T> &a, int64_t k, int64_t i) {
-  const int64_t off = k * a.n_samp + i;
   Geom<T> g;
-  g.pix = ang2pix_ring(a.nside, (double)a.theta[off], (double)a.phi[off]);
+  if (a.qb) {
+#pragma clang fp contract(off)
+    const QuatDir d = quat_dir(qmul(load_quat(a.qb, i), load_quat(a.qd, k)));
+    g.pix = zphi2pix_ring(a.nside, d.z, d.phi);
+    double beta = a.dpsi ? a.dpsi[k] : 0.0;
+    if (a.hwp) beta = beta + 2.0 * hwp_alpha(i, a.hwp_num_mod, a.hwp_den, a.hwp_phase0);
+    quat_weights(d, a.dpsi || a.hwp, beta, g.c, g.s);
+  } else {
+    const int64_t off = k * a.n_samp + i;
+    g.pix = ang2pix_ring(a.nside, (double)a.theta[off], (double)a.phi[off]);
+    weights(two_psi_eff(a, k, i, (double)a.psi[off]), g.c, g.s);
+  }
   if (g.pix >= 0 && a.valid && !a.valid[g.pix]) g.pix = -1;
-  weights(two_psi_eff(a, k, i, (double)a.psi[off]), g.c, g.s);
   return g;
 }
 
@@ -182,6 +279,8 @@ PtArgs<T> pt_args(const furax_pointing *P, const uint8_t *valid) {
   a.hwp_num_mod = P->hwp ? (P->hwp_num % a.hwp_den) : 0;
   a.hwp_phase0 = P->hwp ? P->hwp_phase0 : 0.0;
   a.valid = valid;
+  a.qb = P->bore_quat;
+  a.qd = P->det_quat;
   return a;
 }
 

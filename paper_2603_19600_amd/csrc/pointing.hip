@@ -3,8 +3,9 @@
 //
 // Every kernel expands the pointing on the fly (PointingOperator, section
 // "Software Design", "Map-making classes"): theta/phi/psi are streamed once,
-// coalesced along time, and the pixel and the polariser weights are rebuilt in
-// registers; nothing per-sample is stored.
+// coalesced along time -- or, with quaternion pointing, each sample's attitude
+// is composed from the boresight's and its detector's -- and the pixel and the
+// polariser weights are rebuilt in registers; nothing per-sample is stored.
 #include "common.h"
 
 namespace fx {
@@ -167,6 +168,28 @@ __device__ __forceinline__ int32_t pixel_of(const PtArgs<T> &a, T theta, T phi) 
   return p;
 }
 
+// Quaternion pointing: the tile's detector attitudes are staged in LDS next to
+// the other per-detector constants; a slot's geometry then needs its boresight
+// attitude (shared by all detectors of the time block, so cache-resident) and
+// one Hamilton product.
+__device__ __forceinline__ void load_tile_quats(const double *qd, int64_t n_det,
+                                                const Tiling &tl, int64_t d0, Quat *tq) {
+  for (int j = threadIdx.x; j < tl.dets; j += blockDim.x)
+    tq[j] = load_quat(qd, d0 + j < n_det ? d0 + j : 0);
+}
+
+template <typename T>
+__device__ __forceinline__ void quat_slot(const PtArgs<T> &a, const TileConsts &tc,
+                                          const Slot &sl, const QuatDir &d, int32_t &pix, T &c,
+                                          T &s) {
+#pragma clang fp contract(off)
+  pix = zphi2pix_ring(a.nside, d.z, d.phi);
+  if (pix >= 0 && a.valid && !a.valid[pix]) pix = -1;
+  double beta = a.dpsi ? tc.dpsi[sl.kl] : 0.0;
+  if (a.hwp) beta = beta + tc.two_alpha[sl.il];
+  quat_weights(d, a.dpsi || a.hwp, beta, c, s);
+}
+
 // Stokes values of pixel pix of a map: planar [3][npix] (IL = false, cs =
 // npix) or interleaved [npix][4] (IL = true; one 16- or 32-byte load, whose
 // 4th lane -- a tag, the pixel's nested index as integer bits in the solver's
@@ -204,7 +227,7 @@ __device__ __forceinline__ void load_iqu(const MT *__restrict__ m, int64_t cs, i
 // ---------------------------------------------------------------------------
 constexpr int kApplyThreads = 256;
 
-template <typename T, typename MT, bool IL>
+template <typename T, typename MT, bool IL, bool QUAT>
 __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *__restrict__ map,
                                                          int64_t map_cs, Tiling tl,
                                                          T *__restrict__ tod,
@@ -212,31 +235,47 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *
                                                          uint16_t *__restrict__ local_out,
                                                          int32_t local_mask) {
   __shared__ TileConsts tc;
+  __shared__ Quat tq[QUAT ? kMaxTileDets : 1];
   const int64_t tile = tile_of_block(blockIdx.x, tl.blocks());
   const int64_t d0 = (tile / tl.n_tb) * tl.dets;
   const int64_t t0 = (tile % tl.n_tb) << tl.log2ts;
   const int32_t nsamp = tl.dets << tl.log2ts;
   load_tile_consts(a, nullptr, tl, d0, t0, tc);
+  if constexpr (QUAT) load_tile_quats(a.qd, a.n_det, tl, d0, tq);
   __syncthreads();
   for (int32_t s0 = threadIdx.x; s0 < nsamp; s0 += kBatch * kApplyThreads) {
     Slot sl[kBatch];
-    T th[kBatch], ph[kBatch], ps[kBatch];
-#pragma unroll
-    for (int b = 0; b < kBatch; ++b) {
-      sl[b] = slot_of(tl, d0, t0, s0 + b * kApplyThreads, a.n_det, a.n_samp);
-      th[b] = a.theta[sl[b].off];
-      ph[b] = a.phi[sl[b].off];
-      ps[b] = a.psi[sl[b].off];
-    }
     int32_t px[kBatch], tag[kBatch];
     T c[kBatch], s[kBatch];
+    if constexpr (QUAT) {
+      Quat qb[kBatch];
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        sl[b] = slot_of(tl, d0, t0, s0 + b * kApplyThreads, a.n_det, a.n_samp);
+        qb[b] = load_quat(a.qb, t0 + sl[b].il < a.n_samp ? t0 + sl[b].il : 0);
+      }
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b)
+        quat_slot(a, tc, sl[b], quat_dir(qmul(qb[b], tq[sl[b].kl])), px[b], c[b], s[b]);
+    } else {
+      T th[kBatch], ph[kBatch], ps[kBatch];
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        sl[b] = slot_of(tl, d0, t0, s0 + b * kApplyThreads, a.n_det, a.n_samp);
+        th[b] = a.theta[sl[b].off];
+        ph[b] = a.phi[sl[b].off];
+        ps[b] = a.psi[sl[b].off];
+      }
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        px[b] = pixel_of(a, th[b], ph[b]);
+        pol_weights(a, tc, sl[b], ps[b], c[b], s[b]);
+      }
+    }
     MT I[kBatch], Q[kBatch], U[kBatch];
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b) {
-      px[b] = pixel_of(a, th[b], ph[b]);
-      pol_weights(a, tc, sl[b], ps[b], c[b], s[b]);
+    for (int b = 0; b < kBatch; ++b)
       load_iqu<IL>(map, map_cs, px[b] >= 0 ? px[b] : 0, I[b], Q[b], U[b], tag[b]);
-    }
 #pragma unroll
     for (int b = 0; b < kBatch; ++b) {
       if (!sl[b].in) continue;
@@ -257,30 +296,40 @@ static Tiling tiling_for(const PtArgs<double> &a, int64_t target) {
   return make_tiling(a.n_det, a.n_samp, a.nside, target, 4);
 }
 
+template <typename T, typename MT, bool QUAT>
+static void launch_apply(const PtArgs<T> &a, const MT *m, MapLayout ml, bool il, const Tiling &tl,
+                         T *tod, hipStream_t s, int32_t *pix_out, uint16_t *local_out,
+                         int32_t local_mask) {
+  const dim3 grid((unsigned)tl.blocks()), blk(kApplyThreads);
+  if (il)
+    hipLaunchKernelGGL((k_apply<T, MT, true, QUAT>), grid, blk, 0, s, a, m, ml.cs, tl, tod,
+                       pix_out, local_out, local_mask);
+  else
+    hipLaunchKernelGGL((k_apply<T, MT, false, QUAT>), grid, blk, 0, s, a, m, ml.cs, tl, tod,
+                       pix_out, local_out, local_mask);
+}
+
 template <typename T>
 furax_status launch_pointing_apply(const PtArgs<T> &a, const void *map, bool map_f64,
                                    MapLayout ml, T *tod, hipStream_t s, int32_t *pix_out,
                                    uint16_t *local_out, int32_t local_mask) {
   if (a.n_samp == 0) return FURAX_OK;
   const Tiling tl = tiling_for(a, 4096);
-  const dim3 grid((unsigned)tl.blocks()), blk(kApplyThreads);
   const bool il = ml.ps == 4;
-  if (map_f64) {
-    const double *m = static_cast<const double *>(map);
-    if (il)
-      hipLaunchKernelGGL((k_apply<T, double, true>), grid, blk, 0, s, a, m, ml.cs, tl, tod,
-                         pix_out, local_out, local_mask);
+  if (a.qb) {
+    if (map_f64)
+      launch_apply<T, double, true>(a, static_cast<const double *>(map), ml, il, tl, tod, s,
+                                    pix_out, local_out, local_mask);
     else
-      hipLaunchKernelGGL((k_apply<T, double, false>), grid, blk, 0, s, a, m, ml.cs, tl, tod,
-                         pix_out, local_out, local_mask);
+      launch_apply<T, float, true>(a, static_cast<const float *>(map), ml, il, tl, tod, s,
+                                   pix_out, local_out, local_mask);
   } else {
-    const float *m = static_cast<const float *>(map);
-    if (il)
-      hipLaunchKernelGGL((k_apply<T, float, true>), grid, blk, 0, s, a, m, ml.cs, tl, tod,
-                         pix_out, local_out, local_mask);
+    if (map_f64)
+      launch_apply<T, double, false>(a, static_cast<const double *>(map), ml, il, tl, tod, s,
+                                     pix_out, local_out, local_mask);
     else
-      hipLaunchKernelGGL((k_apply<T, float, false>), grid, blk, 0, s, a, m, ml.cs, tl, tod,
-                         pix_out, local_out, local_mask);
+      launch_apply<T, float, false>(a, static_cast<const float *>(map), ml, il, tl, tod, s,
+                                    pix_out, local_out, local_mask);
   }
   FX_HIP(hipGetLastError());
   return FURAX_OK;
@@ -343,7 +392,7 @@ __device__ __forceinline__ void hash_add(int32_t *keys, double (*acc)[kHashSlots
 //   MODE 2: v = g_k w_k tod[k,i], pixel read from pix_in (written by the P of
 //           the same application), weights recomputed from psi.
 // w_k = w_det[k], or 1 when w_det is null.
-template <typename T, typename MT, int MODE, bool IL>
+template <typename T, typename MT, int MODE, bool IL, bool QUAT>
 __global__ void __launch_bounds__(kScatterThreads)
 k_scatter(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_det,
           const MT *__restrict__ pmap, int64_t p_cs, Tiling tl, double *__restrict__ q,
@@ -351,6 +400,7 @@ k_scatter(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_d
   __shared__ int32_t keys[kHashSlots];
   __shared__ double acc[3][kHashSlots];
   __shared__ TileConsts tc;
+  __shared__ Quat tq[QUAT ? kMaxTileDets : 1];
   for (int h = threadIdx.x; h < kHashSlots; h += kScatterThreads) {
     keys[h] = kEmpty;
     acc[0][h] = 0.0;
@@ -362,30 +412,49 @@ k_scatter(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_d
   const int64_t t0 = (tile % tl.n_tb) << tl.log2ts;
   const int32_t nsamp = tl.dets << tl.log2ts;
   load_tile_consts(a, w_det, tl, d0, t0, tc);
+  if constexpr (QUAT) load_tile_quats(a.qd, a.n_det, tl, d0, tq);
   __syncthreads();
 
   for (int32_t s0 = threadIdx.x; s0 < nsamp; s0 += kBatch * kScatterThreads) {
     Slot sl[kBatch];
     int32_t px[kBatch];
-    T th[kBatch], ph[kBatch], ps[kBatch], v[kBatch];
+    T v[kBatch], c[kBatch], s[kBatch];
+    if constexpr (QUAT) {
+      Quat qb[kBatch];
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b) {
-      sl[b] = slot_of(tl, d0, t0, s0 + b * kScatterThreads, a.n_det, a.n_samp);
-      ps[b] = a.psi[sl[b].off];
-      if constexpr (MODE == 2) {
-        px[b] = pix_in[sl[b].off];
-      } else {
-        th[b] = a.theta[sl[b].off];
-        ph[b] = a.phi[sl[b].off];
+      for (int b = 0; b < kBatch; ++b) {
+        sl[b] = slot_of(tl, d0, t0, s0 + b * kScatterThreads, a.n_det, a.n_samp);
+        qb[b] = load_quat(a.qb, t0 + sl[b].il < a.n_samp ? t0 + sl[b].il : 0);
+        if constexpr (MODE == 2) px[b] = pix_in[sl[b].off];
+        if constexpr (MODE != 1) v[b] = tod[sl[b].off];
       }
-      if constexpr (MODE != 1) v[b] = tod[sl[b].off];
-    }
-    T c[kBatch], s[kBatch];
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b) {
-      if constexpr (MODE != 2) px[b] = pixel_of(a, th[b], ph[b]);
-      if (!sl[b].in) px[b] = -1;
-      pol_weights(a, tc, sl[b], ps[b], c[b], s[b]);
+      for (int b = 0; b < kBatch; ++b) {
+        int32_t pq;
+        quat_slot(a, tc, sl[b], quat_dir(qmul(qb[b], tq[sl[b].kl])), pq, c[b], s[b]);
+        if constexpr (MODE != 2) px[b] = pq;
+        if (!sl[b].in) px[b] = -1;
+      }
+    } else {
+      T th[kBatch], ph[kBatch], ps[kBatch];
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        sl[b] = slot_of(tl, d0, t0, s0 + b * kScatterThreads, a.n_det, a.n_samp);
+        ps[b] = a.psi[sl[b].off];
+        if constexpr (MODE == 2) {
+          px[b] = pix_in[sl[b].off];
+        } else {
+          th[b] = a.theta[sl[b].off];
+          ph[b] = a.phi[sl[b].off];
+        }
+        if constexpr (MODE != 1) v[b] = tod[sl[b].off];
+      }
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        if constexpr (MODE != 2) px[b] = pixel_of(a, th[b], ph[b]);
+        if (!sl[b].in) px[b] = -1;
+        pol_weights(a, tc, sl[b], ps[b], c[b], s[b]);
+      }
     }
     if constexpr (MODE == 1) {
       MT I[kBatch], Q[kBatch], U[kBatch];
@@ -425,40 +494,50 @@ k_scatter(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_d
   }
 }
 
-template <typename T>
-furax_status launch_scatter(const PtArgs<T> &a, const T *tod, const double *w_det,
-                            const void *pmap, bool pmap_f64, MapLayout pl, double *q,
-                            MapLayout ql, hipStream_t s, const int32_t *pix_in) {
-  if (a.n_samp == 0) return FURAX_OK;
+template <typename T, bool QUAT>
+static void launch_scatter_k(const PtArgs<T> &a, const T *tod, const double *w_det,
+                             const void *pmap, bool pmap_f64, MapLayout pl, double *q,
+                             MapLayout ql, hipStream_t s, const int32_t *pix_in) {
   const Tiling tl = tiling_for(a, 8192);
   const dim3 grid((unsigned)tl.blocks()), blk(kScatterThreads);
   const double *nul = nullptr;
   if (tod && pix_in) {
-    hipLaunchKernelGGL((k_scatter<T, double, 2, false>), grid, blk, 0, s, a, tod, w_det, nul,
-                       int64_t(0), tl, q, ql, pix_in);
+    hipLaunchKernelGGL((k_scatter<T, double, 2, false, QUAT>), grid, blk, 0, s, a, tod, w_det,
+                       nul, int64_t(0), tl, q, ql, pix_in);
   } else if (tod) {
-    hipLaunchKernelGGL((k_scatter<T, double, 0, false>), grid, blk, 0, s, a, tod, w_det, nul,
-                       int64_t(0), tl, q, ql, pix_in);
+    hipLaunchKernelGGL((k_scatter<T, double, 0, false, QUAT>), grid, blk, 0, s, a, tod, w_det,
+                       nul, int64_t(0), tl, q, ql, pix_in);
   } else {
     const bool il = pl.ps == 4;
     if (pmap_f64) {
       const double *m = static_cast<const double *>(pmap);
       if (il)
-        hipLaunchKernelGGL((k_scatter<T, double, 1, true>), grid, blk, 0, s, a, tod, w_det, m,
-                           pl.cs, tl, q, ql, pix_in);
+        hipLaunchKernelGGL((k_scatter<T, double, 1, true, QUAT>), grid, blk, 0, s, a, tod,
+                           w_det, m, pl.cs, tl, q, ql, pix_in);
       else
-        hipLaunchKernelGGL((k_scatter<T, double, 1, false>), grid, blk, 0, s, a, tod, w_det, m,
-                           pl.cs, tl, q, ql, pix_in);
+        hipLaunchKernelGGL((k_scatter<T, double, 1, false, QUAT>), grid, blk, 0, s, a, tod,
+                           w_det, m, pl.cs, tl, q, ql, pix_in);
     } else {
       const float *m = static_cast<const float *>(pmap);
       if (il)
-        hipLaunchKernelGGL((k_scatter<T, float, 1, true>), grid, blk, 0, s, a, tod, w_det, m,
-                           pl.cs, tl, q, ql, pix_in);
+        hipLaunchKernelGGL((k_scatter<T, float, 1, true, QUAT>), grid, blk, 0, s, a, tod,
+                           w_det, m, pl.cs, tl, q, ql, pix_in);
       else
-        hipLaunchKernelGGL((k_scatter<T, float, 1, false>), grid, blk, 0, s, a, tod, w_det, m,
-                           pl.cs, tl, q, ql, pix_in);
+        hipLaunchKernelGGL((k_scatter<T, float, 1, false, QUAT>), grid, blk, 0, s, a, tod,
+                           w_det, m, pl.cs, tl, q, ql, pix_in);
     }
   }
+}
+
+template <typename T>
+furax_status launch_scatter(const PtArgs<T> &a, const T *tod, const double *w_det,
+                            const void *pmap, bool pmap_f64, MapLayout pl, double *q,
+                            MapLayout ql, hipStream_t s, const int32_t *pix_in) {
+  if (a.n_samp == 0) return FURAX_OK;
+  if (a.qb)
+    launch_scatter_k<T, true>(a, tod, w_det, pmap, pmap_f64, pl, q, ql, s, pix_in);
+  else
+    launch_scatter_k<T, false>(a, tod, w_det, pmap, pmap_f64, pl, q, ql, s, pix_in);
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }
@@ -517,7 +596,15 @@ template furax_status launch_bj_build<double>(const PtArgs<double> &, const doub
                                               int32_t *, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// Closed-form inverse of each pixel's symmetric 3x3 block, 1-norm rcond.
+// Inverse of each pixel's symmetric 3x3 block from its Cholesky factorisation
+// M = L L^T (the blocks are sums of w (1,c,s)^T (1,c,s), w > 0, so positive
+// semi-definite), and its 1-norm reciprocal condition number.  The Cholesky
+// route is backward stable: a block that is singular in exact arithmetic (all
+// of the pixel's samples at one polariser angle, or at two angles pi/2 apart)
+// meets a pivot that is not positive or of rounding size, so its inverse is
+// huge and its rcond tiny, where the adjugate formula's cofactors would all be
+// rounding noise with a ratio of order one.  A non-positive pivot gives
+// inverse 0 and rcond 0.  M^-1 = L^-T L^-1, L^-1 by forward substitution.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_bj_invert(int64_t npix, const double *__restrict__ M6,
                                                       const int32_t *__restrict__ hits,
@@ -531,17 +618,34 @@ __global__ void __launch_bounds__(kBlock) k_bj_invert(int64_t npix, const double
   for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < npix; p += stride) {
     const double a = M6[p], b = M6[npix + p], c = M6[2 * npix + p];
     const double d = M6[3 * npix + p], e = M6[4 * npix + p], f = M6[5 * npix + p];
-    const double A = d * f - e * e, B = c * e - b * f, C = b * e - c * d;
-    const double D = a * f - c * c, E = b * c - a * e, F = a * d - b * b;
-    const double det = a * A + b * B + c * C;
-    const double ia = A / det, ib = B / det, ic = C / det;
-    const double id = D / det, ie = E / det, iff = F / det;
+    const double l11 = sqrt(a);
+    const double l21 = b / l11;
+    const double l31 = c / l11;
+    const double t22 = d - l21 * l21;
+    const double l22 = sqrt(t22);
+    const double l32 = (e - l31 * l21) / l22;
+    const double t33 = f - l31 * l31 - l32 * l32;
+    const double l33 = sqrt(t33);
+    const double i11 = 1.0 / l11, i22 = 1.0 / l22, i33 = 1.0 / l33;
+    const double i21 = -(l21 * i11) * i22;
+    const double i32 = -(l32 * i22) * i33;
+    const double i31 = -(l31 * i11 + l32 * i21) * i33;
+    double ia = i11 * i11 + i21 * i21 + i31 * i31;
+    double ib = i21 * i22 + i31 * i32;
+    double ic = i31 * i33;
+    double id = i22 * i22 + i32 * i32;
+    double ie = i32 * i33;
+    double iff = i33 * i33;
+    const bool fin = ia - ia == 0.0 && ib - ib == 0.0 && ic - ic == 0.0 && id - id == 0.0 &&
+                     ie - ie == 0.0 && iff - iff == 0.0;
+    const bool chol = a > 0.0 && t22 > 0.0 && t33 > 0.0 && fin;
+    if (!chol) ia = ib = ic = id = ie = iff = 0.0;
     const double n1 = fmax(fmax(fabs(a) + fabs(b) + fabs(c), fabs(b) + fabs(d) + fabs(e)),
                            fabs(c) + fabs(e) + fabs(f));
     const double n1i = fmax(fmax(fabs(ia) + fabs(ib) + fabs(ic), fabs(ib) + fabs(id) + fabs(ie)),
                             fabs(ic) + fabs(ie) + fabs(iff));
     double rc = 1.0 / (n1 * n1i);
-    if (!(rc - rc == 0.0) || det == 0.0) rc = 0.0;
+    if (!chol || !(rc - rc == 0.0)) rc = 0.0;
     bool ok;
     if (force_valid) ok = force_valid[p] != 0;
     else ok = (hits[p] >= min_hits) && (rc >= rcond_min);

@@ -103,7 +103,14 @@ __global__ void __launch_bounds__(kBlock) k_nest_plane(PtArgs<T> a, const int32_
   const int64_t S = a.n_det * a.n_samp;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < S; s += stride) {
-    const int32_t p = ang2pix_ring(a.nside, (double)a.theta[s], (double)a.phi[s]);
+    int32_t p;
+    if (a.qb) {
+      const int64_t k = s / a.n_samp, i = s - k * a.n_samp;
+      const QuatDir d = quat_dir(qmul(load_quat(a.qb, i), load_quat(a.qd, k)));
+      p = zphi2pix_ring(a.nside, d.z, d.phi);
+    } else {
+      p = ang2pix_ring(a.nside, (double)a.theta[s], (double)a.phi[s]);
+    }
     plane[s] = p >= 0 ? r2n[p] : -1;
   }
 }
@@ -346,7 +353,7 @@ constexpr int kHwpPeriodMax = 1024;           // tabulated HWP periods
 constexpr int kHwpTable = kHwpPeriodMax + (int)kMaxRun;
 
 struct SpRunLds {
-  int64_t off[kChunkRuns];
+  int32_t det[kChunkRuns], i0[kChunkRuns];    // detector, first sample index
   int32_t pre[kChunkRuns + 1];
   int32_t hwp0[kChunkRuns];                   // (first sample index) mod hwp_den
   double gw[kChunkRuns], dpsi[kChunkRuns];
@@ -377,7 +384,7 @@ __device__ __forceinline__ int32_t run_of(const int32_t *pre, int32_t lo, int32_
   return lo;
 }
 
-template <typename T, int KIND>
+template <typename T, int KIND, bool QUAT>
 __global__ void __launch_bounds__(kSpThreads)
 k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_det,
            const uint16_t *__restrict__ local, const int32_t *__restrict__ nest_plane,
@@ -409,9 +416,10 @@ k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_
     const int64_t off = (int64_t)(w >> 24);
     const int64_t k = off / a.n_samp;
     const int64_t i0 = off - k * a.n_samp;
-    L.run.off[r] = off;
     L.run.pre[r] = (int32_t)(w & 0xffffff);
     L.run.hwp0[r] = table ? (int32_t)(i0 % a.hwp_den) : 0;
+    L.run.det[r] = (int32_t)k;
+    L.run.i0[r] = (int32_t)i0;
     const double g = a.gain ? a.gain[k] : 1.0;
     const double wk = w_det ? w_det[k] : 1.0;
     L.run.gw[r] = KIND == 0 ? g * wk : g * g * wk;
@@ -436,6 +444,7 @@ k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_
     int64_t sidx[kSlotBatch];
     bool in[kSlotBatch];
     T z[kSlotBatch], ps[kSlotBatch];
+    Quat qb[QUAT ? kSlotBatch : 1], qd[QUAT ? kSlotBatch : 1];
 #pragma unroll
     for (int b = 0; b < kSlotBatch; ++b) {
       const int32_t jb = (blk + b) * 64;
@@ -456,29 +465,43 @@ k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_
       const int32_t r = min(run[b], ch.nr - 1);
       run[b] = r;
       tt[b] = jj - L.run.pre[r];                        // offset inside the run
-      sidx[b] = L.run.off[r] + tt[b];
+      sidx[b] = (int64_t)L.run.det[r] * a.n_samp + (L.run.i0[r] + tt[b]);
       lo[b] = local ? (int32_t)local[sidx[b]] : nest_plane[sidx[b]] - base;
       if constexpr (KIND == 0) z[b] = tod[sidx[b]];
-      ps[b] = a.psi[sidx[b]];
+      if constexpr (QUAT) {
+        qb[b] = load_quat(a.qb, L.run.i0[r] + tt[b]);
+        qd[b] = load_quat(a.qd, L.run.det[r]);
+      } else {
+        ps[b] = a.psi[sidx[b]];
+      }
     }
 #pragma unroll
     for (int b = 0; b < kSlotBatch; ++b) {
       if (!in[b] || (uint32_t)lo[b] >= (uint32_t)P) continue;
       const int32_t r = run[b];
       const int32_t t = tt[b];
-      // psi_eff = psi + dpsi_k + 2 alpha_i, in the oracle's order
-      double pe = (double)ps[b];
-      if (a.dpsi) pe = pe + L.run.dpsi[r];
+      // psi_eff = psi + dpsi_k + 2 alpha_i, in the oracle's order (beta: the
+      // part that does not come from the pointing)
+      double two_a = 0.0;
       if (a.hwp) {
         if (table) {
-          pe = pe + L.two_alpha[L.run.hwp0[r] + t];
+          two_a = L.two_alpha[L.run.hwp0[r] + t];
         } else {
-          const int64_t i = sidx[b] - (sidx[b] / a.n_samp) * a.n_samp;
-          pe = pe + 2.0 * hwp_alpha(i, a.hwp_num_mod, a.hwp_den, a.hwp_phase0);
+          const int64_t i = (int64_t)L.run.i0[r] + t;
+          two_a = 2.0 * hwp_alpha(i, a.hwp_num_mod, a.hwp_den, a.hwp_phase0);
         }
       }
       T c, sn;
-      weights(2.0 * pe, c, sn);
+      if constexpr (QUAT) {
+        double beta = a.dpsi ? L.run.dpsi[r] : 0.0;
+        if (a.hwp) beta = beta + two_a;
+        quat_weights(quat_dir(qmul(qb[b], qd[b])), a.dpsi || a.hwp, beta, c, sn);
+      } else {
+        double pe = (double)ps[b];
+        if (a.dpsi) pe = pe + L.run.dpsi[r];
+        if (a.hwp) pe = pe + two_a;
+        weights(2.0 * pe, c, sn);
+      }
       if constexpr (KIND == 0) {
         const T v = (T)L.run.gw[r] * z[b];
         atomicAdd(&L.acc[0][lo[b]], (double)v);
@@ -543,8 +566,14 @@ furax_status sp_transpose(const SpPlan &sp, const PtArgs<T> &a, const T *tod,
                           const double *w_det, const uint16_t *local, const int32_t *nest_plane,
                           double *q, MapLayout ql, hipStream_t s) {
   if (sp.n_chunks > 0) {
-    hipLaunchKernelGGL((k_sp_accum<T, 0>), dim3((unsigned)sp.n_chunks), dim3(kSpThreads), 0, s, a,
-                       tod, w_det, local, nest_plane, sp.runs, sp.chunks, sp.log2P, sp.partial);
+    if (a.qb)
+      hipLaunchKernelGGL((k_sp_accum<T, 0, true>), dim3((unsigned)sp.n_chunks), dim3(kSpThreads),
+                         0, s, a, tod, w_det, local, nest_plane, sp.runs, sp.chunks, sp.log2P,
+                         sp.partial);
+    else
+      hipLaunchKernelGGL((k_sp_accum<T, 0, false>), dim3((unsigned)sp.n_chunks), dim3(kSpThreads),
+                         0, s, a, tod, w_det, local, nest_plane, sp.runs, sp.chunks, sp.log2P,
+                         sp.partial);
     FX_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_sp_reduce, dim3(grid_for(sp.npix, 16384)), dim3(kBlock), 0, s, sp.npix,
@@ -566,9 +595,14 @@ template <typename T>
 furax_status sp_bj_build(const SpPlan &sp, const PtArgs<T> &a, const double *w_det,
                          const int32_t *nest_plane, double *M6, int32_t *hits, hipStream_t s) {
   if (sp.n_chunks > 0) {
-    hipLaunchKernelGGL((k_sp_accum<T, 1>), dim3((unsigned)sp.n_chunks), dim3(kSpThreads), 0, s, a,
-                       (const T *)nullptr, w_det, (const uint16_t *)nullptr, nest_plane, sp.runs,
-                       sp.chunks, sp.log2P, sp.partial);
+    if (a.qb)
+      hipLaunchKernelGGL((k_sp_accum<T, 1, true>), dim3((unsigned)sp.n_chunks), dim3(kSpThreads),
+                         0, s, a, (const T *)nullptr, w_det, (const uint16_t *)nullptr,
+                         nest_plane, sp.runs, sp.chunks, sp.log2P, sp.partial);
+    else
+      hipLaunchKernelGGL((k_sp_accum<T, 1, false>), dim3((unsigned)sp.n_chunks), dim3(kSpThreads),
+                         0, s, a, (const T *)nullptr, w_det, (const uint16_t *)nullptr,
+                         nest_plane, sp.runs, sp.chunks, sp.log2P, sp.partial);
     FX_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_sp_reduce, dim3(grid_for(sp.npix, 16384)), dim3(kBlock), 0, s, sp.npix,

@@ -35,7 +35,7 @@ class _Pointing(C.Structure):
                 ("dtype", C.c_int32), ("theta", C.c_void_p), ("phi", C.c_void_p),
                 ("psi", C.c_void_p), ("gain", C.c_void_p), ("dpsi", C.c_void_p),
                 ("hwp", C.c_int32), ("hwp_num", C.c_int64), ("hwp_den", C.c_int64),
-                ("hwp_phase0", C.c_double)]
+                ("hwp_phase0", C.c_double), ("bore_quat", C.c_void_p), ("det_quat", C.c_void_p)]
 
 
 class _Noise(C.Structure):
@@ -136,6 +136,14 @@ def _dt(t: torch.Tensor) -> int:
     raise TypeError(f"unsupported dtype {t.dtype}")
 
 
+def _dt_of(dtype: torch.dtype) -> int:
+    if dtype == torch.float32:
+        return F32
+    if dtype == torch.float64:
+        return F64
+    raise TypeError(f"unsupported dtype {dtype}")
+
+
 def _dev(t: torch.Tensor, name: str, dtype=None, shape=None) -> torch.Tensor:
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
@@ -196,13 +204,71 @@ class Pointing:
         return _Pointing(self.nside, self.n_det, self.n_samp, _dt(self.theta), _ptr(self.theta),
                          _ptr(self.phi), _ptr(self.psi), _ptr(self.gain), _ptr(self.dpsi),
                          1 if h else 0, int(h[0]) if h else 0, int(h[1]) if h else 1,
-                         float(h[2]) if h else 0.0)
+                         float(h[2]) if h else 0.0, None, None)
 
     def with_(self, **kw) -> "Pointing":
         d = dict(nside=self.nside, theta=self.theta, phi=self.phi, psi=self.psi, gain=self.gain,
                  dpsi=self.dpsi, hwp=self.hwp)
         d.update(kw)
         return Pointing(**d)
+
+
+@dataclass
+class QuatPointing:
+    """Boresight-quaternion pointing (see furax_pointing): the boresight attitude
+    bore_quat [n_samp, 4] and the detector attitudes det_quat [n_det, 4], both
+    float64 (w, x, y, z); `dtype` is the TOD / arithmetic precision."""
+    nside: int
+    bore_quat: torch.Tensor
+    det_quat: torch.Tensor
+    dtype: torch.dtype = torch.float64
+    gain: Optional[torch.Tensor] = None      # [n_det] float64
+    dpsi: Optional[torch.Tensor] = None      # [n_det] float64
+    hwp: Optional[tuple] = None              # (hwp_num, hwp_den, phase0)
+
+    def __post_init__(self):
+        _dev(self.bore_quat, "bore_quat", torch.float64)
+        _dev(self.det_quat, "det_quat", torch.float64)
+        if self.bore_quat.dim() != 2 or self.bore_quat.shape[1] != 4:
+            raise ValueError("bore_quat must be [n_samp, 4]")
+        if self.det_quat.dim() != 2 or self.det_quat.shape[1] != 4:
+            raise ValueError("det_quat must be [n_det, 4]")
+        if self.dtype not in (torch.float32, torch.float64):
+            raise ValueError("dtype must be float32 or float64")
+        if self.gain is not None:
+            _dev(self.gain, "gain", torch.float64, (self.n_det,))
+        if self.dpsi is not None:
+            _dev(self.dpsi, "dpsi", torch.float64, (self.n_det,))
+
+    @property
+    def n_det(self) -> int:
+        return self.det_quat.shape[0]
+
+    @property
+    def n_samp(self) -> int:
+        return self.bore_quat.shape[0]
+
+    @property
+    def npix(self) -> int:
+        return 12 * self.nside * self.nside
+
+    @property
+    def device(self):
+        return self.bore_quat.device
+
+    def c(self) -> _Pointing:
+        h = self.hwp
+        dt = _dt_of(self.dtype)
+        return _Pointing(self.nside, self.n_det, self.n_samp, dt, None, None, None,
+                         _ptr(self.gain), _ptr(self.dpsi), 1 if h else 0, int(h[0]) if h else 0,
+                         int(h[1]) if h else 1, float(h[2]) if h else 0.0,
+                         _ptr(self.bore_quat), _ptr(self.det_quat))
+
+    def with_(self, **kw) -> "QuatPointing":
+        d = dict(nside=self.nside, bore_quat=self.bore_quat, det_quat=self.det_quat,
+                 dtype=self.dtype, gain=self.gain, dpsi=self.dpsi, hwp=self.hwp)
+        d.update(kw)
+        return QuatPointing(**d)
 
 
 @dataclass
@@ -295,7 +361,7 @@ def bj_invert(M6: torch.Tensor, hits: torch.Tensor, rcond_min: float = 1e-3, min
 
 def normal_workspace_bytes(P: Pointing, N: Noise) -> int:
     cp, cn = P.c(), N.c()
-    n = _lib.furax_normal_workspace_bytes(C.byref(cp), C.byref(cn), _dt(P.theta))
+    n = _lib.furax_normal_workspace_bytes(C.byref(cp), C.byref(cn), _dt_of(P.dtype))
     if n < 0:
         raise FuraxError(EINVAL, _lib.furax_last_error().decode())
     return n
@@ -315,7 +381,7 @@ def normal_apply(P: Pointing, N: Noise, p: torch.Tensor, valid: Optional[torch.T
         if work.numel() < normal_workspace_bytes(P, N):
             raise ValueError("workspace too small")
     cp, cn = P.c(), N.c()
-    _check(_lib.furax_normal_apply(C.byref(cp), C.byref(cn), _dt(P.theta), _ptr(p), _ptr(out),
+    _check(_lib.furax_normal_apply(C.byref(cp), C.byref(cn), _dt_of(P.dtype), _ptr(p), _ptr(out),
                                    _ptr(valid), _ptr(work), _stream(P.device)))
     return out
 
@@ -332,7 +398,7 @@ class PcgInfo:
 def _opts(P, max_iter, rtol, rcond_min, min_hits, valid_in, no_early_exit):
     if valid_in is not None:
         _dev(valid_in, "valid_in", torch.uint8, (P.npix,))
-    return _PcgOpts(int(max_iter), float(rtol), _dt(P.theta), float(rcond_min), int(min_hits),
+    return _PcgOpts(int(max_iter), float(rtol), _dt_of(P.dtype), float(rcond_min), int(min_hits),
                     _ptr(valid_in), 1 if no_early_exit else 0)
 
 

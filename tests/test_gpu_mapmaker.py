@@ -173,7 +173,13 @@ def test_pcg_breakdown_and_invalid_args(fx):
     bad = fx.Noise("band", 2, 5000, lags=torch.tensor([-1.0, 0.1], dtype=torch.float64,
                                                        device=dev()))
     d2, _ = _tod(w, prob, P)
-    _, _, info2, st2 = fx.pcg_mapmake(P, bad, torch.from_numpy(d2).to(dev()), max_iter=5)
+    # a negative-definite kernel: no block passes the Cholesky validity test ...
+    _, v0, info0, _ = fx.pcg_mapmake(P, bad, torch.from_numpy(d2).to(dev()), max_iter=5)
+    assert info0.n_valid == 0 and int(v0.sum()) == 0
+    # ... and with every pixel forced valid the first <r, z> is not positive
+    allv = torch.ones(P.npix, dtype=torch.uint8, device=dev())
+    _, _, info2, st2 = fx.pcg_mapmake(P, bad, torch.from_numpy(d2).to(dev()), max_iter=5,
+                                      valid_in=allv)
     assert st2 == fx.EBREAKDOWN
     with pytest.raises(fx.FuraxError) as e:
         fx.pcg_mapmake(P, fx.Noise("diag", 3, 5000, inv_var=torch.ones(3, dtype=torch.float64,

@@ -44,6 +44,48 @@ def test_bj_inverse_and_rcond_vs_numpy():
     assert not v2.any()
 
 
+def test_bj_rank_deficient_blocks_are_invalid():
+    """Blocks singular in exact arithmetic -- every sample at one polariser angle
+    (rank 1), or at two angles pi/2 apart (rank 2) -- must come out invalid with
+    a tiny rcond, as numpy's condition number of the same matrices says."""
+    rng = np.random.default_rng(3)
+    blocks = []
+    for _ in range(300):
+        n = int(rng.integers(3, 9))
+        ang = np.full(n, rng.uniform(0, 2 * np.pi))               # one angle: rank 1
+        if rng.random() < 0.5:                                    # two angles pi/2 apart
+            ang = ang + (np.pi / 2) * rng.integers(0, 2, n)
+        w = rng.uniform(0.5, 2.0, n)
+        v = np.stack([np.ones(n), np.cos(2 * ang), np.sin(2 * ang)], 1)
+        blocks.append(np.einsum("k,ki,kj->ij", w, v, v))
+    Ms = np.array(blocks)
+    M6 = np.stack([Ms[:, 0, 0], Ms[:, 0, 1], Ms[:, 0, 2], Ms[:, 1, 1], Ms[:, 1, 2], Ms[:, 2, 2]])
+    inv, valid, rcond = mm.bj_invert(M6, np.full(len(Ms), 8), 1e-3, 3)
+    assert not valid.any()
+    assert (rcond < 1e-10).all()
+    assert (1.0 / np.linalg.cond(Ms, 1) < 1e-10).all()
+    assert (inv == 0).all()
+
+
+def test_bj_well_conditioned_psd_blocks_match_numpy():
+    """Blocks made the way the method makes them (sums of w (1,c,s)^T (1,c,s))."""
+    rng = np.random.default_rng(4)
+    n = 400
+    k = rng.integers(3, 12, n)
+    Ms = np.zeros((n, 3, 3))
+    for j in range(n):
+        ang = rng.uniform(0, 2 * np.pi, k[j])
+        v = np.stack([np.ones(k[j]), np.cos(2 * ang), np.sin(2 * ang)], 1)
+        Ms[j] = np.einsum("k,ki,kj->ij", rng.uniform(0.5, 2, k[j]), v, v)
+    M6 = np.stack([Ms[:, 0, 0], Ms[:, 0, 1], Ms[:, 0, 2], Ms[:, 1, 1], Ms[:, 1, 2], Ms[:, 2, 2]])
+    inv, valid, rcond = mm.bj_invert(M6, k, 0.0, 3)
+    ref_rc = 1.0 / np.linalg.cond(Ms, 1)
+    good = ref_rc > 1e-6
+    assert good.sum() > 300
+    assert np.allclose(rcond[good], ref_rc[good], rtol=1e-8)
+    assert np.allclose(mm.sym3(inv)[good], np.linalg.inv(Ms[good]), rtol=1e-8, atol=1e-10)
+
+
 def test_diag_noise_converges_in_one_iteration_to_binned_map():
     prob = _problem(nside=4, n_det=4, n_samp=600, kind="diag")
     rng = np.random.default_rng(1)
@@ -135,8 +177,13 @@ def test_breakdown_on_nan_data():
 
 
 def test_indefinite_noise_breaks_down():
+    """A negative-definite kernel makes every block negative definite: no pixel
+    passes the (Cholesky) validity test, and with every pixel forced valid the
+    first <r, z> is not positive, which is a breakdown."""
     prob = _problem(nside=2, n_det=2, n_samp=300, kind="band", b=4)
     prob.lags = np.array([-1.0, 0.1, 0.0, 0.0])       # negative-definite kernel
     d = np.random.default_rng(0).standard_normal(prob.theta.shape)
-    res = mm.pcg_mapmake(prob, d, max_iter=10)
+    M6, hits = mm.bj_build(*prob.geometry(), prob.wdiag(), prob.npix, prob.gain)
+    assert not mm.bj_invert(M6, hits)[1].any()
+    res = mm.pcg_mapmake(prob, d, max_iter=10, valid_in=np.ones(prob.npix, bool))
     assert res.stop_reason == mm.STOP_BREAKDOWN
