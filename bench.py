@@ -8,7 +8,9 @@ seeded and resident in HBM before the timed region.
 Default workload: HEALPix nside 512, 256 detectors x 2^20 samples, FP64
 pointing/TOD, 1/f noise weighted by a band-Toeplitz of 4096 lags, ideal HWP at
 2 Hz.  The FP32 variant of the same workload (FP32 pointing, TOD and FFT,
-FP64 accumulation, dots and preconditioner) is measured beside it.
+FP64 accumulation, dots and preconditioner) is measured beside it, and both
+again with boresight-quaternion pointing (the same scan given as one attitude
+per time sample and one per detector, expanded per sample in the kernels).
 
 Prints one JSON line (rank 0).
 """
@@ -42,9 +44,14 @@ def make_inputs(w, dev):
     from paper_2603_19600_amd import synth
 
     t0 = time.time()
-    pt = synth.pointing(w, device=dev, det_chunk=8)
     hwp = (w.hwp_num, w.hwp_den, 0.0) if w.hwp else None
-    P = fx.Pointing(w.nside, pt.theta, pt.phi, pt.psi, hwp=hwp)
+    if w.pointing == "quat":
+        P = fx.QuatPointing(w.nside, synth.boresight_quaternions(w, device=dev),
+                            synth.detector_quaternions(w, device=dev),
+                            torch.float64 if w.dtype == "f64" else torch.float32, hwp=hwp)
+    else:
+        pt = synth.pointing(w, device=dev, det_chunk=8)
+        P = fx.Pointing(w.nside, pt.theta, pt.phi, pt.psi, hwp=hwp)
     if w.noise == "band":
         lags = torch.from_numpy(synth.toeplitz_lags(w)).to(dev)
         N = fx.Noise("band", w.n_det, w.n_samp, lags=lags)
@@ -68,29 +75,34 @@ def kernel_bytes(w):
     the operator must move as the method defines it, whatever the kernel reads)."""
     e = 8 if w.dtype == "f64" else 4
     S = w.n_det * w.n_samp
+    # pointing stream per phase: theta, phi, psi planes, or (quaternion
+    # pointing) one boresight attitude per time sample and one per detector
+    pt = S * 3 * e if w.pointing != "quat" else 32 * (w.n_samp + w.n_det)
     return {
-        # P: theta, phi, psi in, TOD out, the map read once
-        "apply": S * (3 * e + e) + 3 * w.npix * e,
+        # P: pointing in, TOD out, the map read once
+        "apply": pt + S * e + 3 * w.npix * e,
         # N^-1: TOD in, TOD out
         "noise": S * 2 * e,
-        # P^T: theta, phi, psi and TOD in, the FP64 map written once
-        "transpose": S * (3 * e + e) + 3 * w.npix * 8,
+        # P^T: pointing and TOD in, the FP64 map written once
+        "transpose": pt + S * e + 3 * w.npix * 8,
     }
 
 
 def operator_bytes(w):
     """Algorithmic bytes of a whole PCG iteration: the pointing stream once plus
-    the map-domain vectors (p, q, x, r, z, preconditioner: ~52 FP64 per pixel)."""
+    the map-domain vectors (p, q, x, r, z, preconditioner: ~52 FP64 per pixel).
+    The TOD itself never has to reach HBM when P, N^-1 and P^T are fused."""
     e = 8 if w.dtype == "f64" else 4
-    return w.n_det * w.n_samp * 3 * e + 52 * 8 * w.npix
+    pt = w.n_det * w.n_samp * 3 * e if w.pointing != "quat" else 32 * (w.n_samp + w.n_det)
+    return pt + 52 * 8 * w.npix
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nside512_256x2p20_band4096.txt")
 # kernels making up each phase, by rocprofv3 kernel name ({T}: double or float)
 PHASE_KERNELS = {
-    "apply": ["fx::k_apply<{T}, {T}, true>"],
+    "apply": ["fx::k_apply<{T}, {T}, true, false>"],
     "noise": ["fx::k_overlap_save<{T}, "],
-    "transpose": ["fx::k_sp_accum<{T}, 0>", "fx::k_sp_reduce"],
+    "transpose": ["fx::k_sp_accum<{T}, 0, false>", "fx::k_sp_reduce"],
 }
 
 
@@ -239,6 +251,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=2, help="workload number (2, 3 or 5)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 variant")
+    ap.add_argument("--no-quat", action="store_true",
+                    help="skip the boresight-quaternion pointing variants")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-dets", type=int, default=64)
     args = ap.parse_args()
@@ -267,6 +281,14 @@ def main():
     if not args.no_fp32 and w.dtype == "f64":
         w32 = synth.WORKLOADS[3] if args.config == 2 else w.with_(dtype="f32")
         fp32 = measure(w32, dev, args.steps, args.warmup)
+
+    quat = {}
+    if not args.no_quat:
+        for wq in ([w] + ([synth.WORKLOADS[3]] if fp32 is not None and args.config == 2 else [])):
+            r = measure(wq.with_(pointing="quat"), dev, args.steps, args.warmup)
+            quat[wq.dtype] = {"workload": wq.name + "_quat", "value": r["value"],
+                              "ms_per_step": r["ms_per_step"], "kernels": r["kernels"],
+                              "operator": r["operator"]}
 
     # the dominant operator kernel of the iteration
     name, k = max(((n, v) for n, v in primary["kernels"].items() if "alg_bytes" in v),
@@ -307,6 +329,7 @@ def main():
             "value": fp32["value"], "ms_per_step": fp32["ms_per_step"],
             "kernels": fp32["kernels"], "operator": fp32["operator"],
             "speedup_vs_fp64": fp32["value"] / primary["value"]},
+        "quat": quat or None,
         "host": host_info(),
     }
     print(json.dumps(line), flush=True)

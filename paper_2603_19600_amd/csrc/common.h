@@ -192,16 +192,32 @@ __device__ __forceinline__ void weights(double ang, float &c, float &s) {
 // sin 2 psi follow from (west, north) algebraically in FP64, and the turn by
 // 2 beta (detector angle offset plus twice the HWP angle) is applied with the
 // precision's weights() of that angle.  psi = 0 where west = north = 0.
+__device__ __forceinline__ void quat_c2s2(const QuatDir &g, double &c2, double &s2) {
+#pragma clang fp contract(off)
+  const double ww = g.west * g.west, nn = g.north * g.north, r2 = ww + nn;
+  c2 = 1.0;
+  s2 = 0.0;
+  if (r2 > 0.0) {
+    const double inv = 1.0 / r2;
+    c2 = (nn - ww) * inv;
+    s2 = (2.0 * (g.west * g.north)) * inv;
+  }
+}
+
+// (c, s) = (c2, s2) turned by the angle whose cosine / sine are (cb, sb).
+template <typename T>
+__device__ __forceinline__ void turn_weights(double c2, double s2, T cb, T sb, T &c, T &s) {
+#pragma clang fp contract(off)
+  const T ct = (T)c2, st = (T)s2;
+  c = ct * cb - st * sb;
+  s = st * cb + ct * sb;
+}
+
 template <typename T>
 __device__ __forceinline__ void quat_weights(const QuatDir &g, bool has_beta, double beta, T &c,
                                              T &s) {
-#pragma clang fp contract(off)
-  const double ww = g.west * g.west, nn = g.north * g.north, r2 = ww + nn;
-  double c2 = 1.0, s2 = 0.0;
-  if (r2 > 0.0) {
-    c2 = (nn - ww) / r2;
-    s2 = (2.0 * (g.west * g.north)) / r2;
-  }
+  double c2, s2;
+  quat_c2s2(g, c2, s2);
   if (!has_beta) {
     c = (T)c2;
     s = (T)s2;
@@ -209,9 +225,7 @@ __device__ __forceinline__ void quat_weights(const QuatDir &g, bool has_beta, do
   }
   T cb, sb;
   weights(2.0 * beta, cb, sb);
-  const T ct = (T)c2, st = (T)s2;
-  c = ct * cb - st * sb;
-  s = st * cb + ct * sb;
+  turn_weights(c2, s2, cb, sb, c, s);
 }
 
 // Geometry of one sample: pixel (or -1) and polariser weights.

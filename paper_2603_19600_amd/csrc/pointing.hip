@@ -178,13 +178,32 @@ __device__ __forceinline__ void load_tile_quats(const double *qd, int64_t n_det,
     tq[j] = load_quat(qd, d0 + j < n_det ? d0 + j : 0);
 }
 
+// With a HWP and no angle offsets the turn of the polariser weights is by
+// 4 alpha_i alone: its cosine and sine are tabulated per tile sample in LDS
+// (turn4a), so no sample evaluates a sine or cosine.
+__device__ __forceinline__ void load_tile_turns(const TileConsts &tc, const Tiling &tl,
+                                                double2 *turn4a) {
+  for (int t = threadIdx.x; t < (1 << tl.log2ts); t += blockDim.x) {
+    double sn, cs;
+    sincos(2.0 * tc.two_alpha[t], &sn, &cs);
+    turn4a[t] = make_double2(cs, sn);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void quat_slot(const PtArgs<T> &a, const TileConsts &tc,
-                                          const Slot &sl, const QuatDir &d, int32_t &pix, T &c,
-                                          T &s) {
+                                          const double2 *turn4a, const Slot &sl,
+                                          const QuatDir &d, int32_t &pix, T &c, T &s) {
 #pragma clang fp contract(off)
   pix = zphi2pix_ring(a.nside, d.z, d.phi);
   if (pix >= 0 && a.valid && !a.valid[pix]) pix = -1;
+  if (a.hwp && !a.dpsi) {
+    double c2, s2;
+    quat_c2s2(d, c2, s2);
+    const double2 tn = turn4a[sl.il];
+    turn_weights(c2, s2, (T)tn.x, (T)tn.y, c, s);
+    return;
+  }
   double beta = a.dpsi ? tc.dpsi[sl.kl] : 0.0;
   if (a.hwp) beta = beta + tc.two_alpha[sl.il];
   quat_weights(d, a.dpsi || a.hwp, beta, c, s);
@@ -236,6 +255,7 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *
                                                          int32_t local_mask) {
   __shared__ TileConsts tc;
   __shared__ Quat tq[QUAT ? kMaxTileDets : 1];
+  __shared__ double2 turn4a[QUAT ? kMaxTileSamples : 1];
   const int64_t tile = tile_of_block(blockIdx.x, tl.blocks());
   const int64_t d0 = (tile / tl.n_tb) * tl.dets;
   const int64_t t0 = (tile % tl.n_tb) << tl.log2ts;
@@ -243,6 +263,12 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *
   load_tile_consts(a, nullptr, tl, d0, t0, tc);
   if constexpr (QUAT) load_tile_quats(a.qd, a.n_det, tl, d0, tq);
   __syncthreads();
+  if constexpr (QUAT) {
+    if (a.hwp && !a.dpsi) {
+      load_tile_turns(tc, tl, turn4a);
+      __syncthreads();
+    }
+  }
   for (int32_t s0 = threadIdx.x; s0 < nsamp; s0 += kBatch * kApplyThreads) {
     Slot sl[kBatch];
     int32_t px[kBatch], tag[kBatch];
@@ -256,7 +282,7 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *
       }
 #pragma unroll
       for (int b = 0; b < kBatch; ++b)
-        quat_slot(a, tc, sl[b], quat_dir(qmul(qb[b], tq[sl[b].kl])), px[b], c[b], s[b]);
+        quat_slot(a, tc, turn4a, sl[b], quat_dir(qmul(qb[b], tq[sl[b].kl])), px[b], c[b], s[b]);
     } else {
       T th[kBatch], ph[kBatch], ps[kBatch];
 #pragma unroll
@@ -397,10 +423,14 @@ __global__ void __launch_bounds__(kScatterThreads)
 k_scatter(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_det,
           const MT *__restrict__ pmap, int64_t p_cs, Tiling tl, double *__restrict__ q,
           MapLayout ql, const int32_t *__restrict__ pix_in) {
+  // quaternion samples carry a boresight attitude each: fewer in flight per
+  // thread keeps the 1024-thread workgroup within its register budget
+  constexpr int KB = QUAT ? 2 : kBatch;
   __shared__ int32_t keys[kHashSlots];
   __shared__ double acc[3][kHashSlots];
   __shared__ TileConsts tc;
   __shared__ Quat tq[QUAT ? kMaxTileDets : 1];
+  __shared__ double2 turn4a[QUAT ? kMaxTileSamples : 1];
   for (int h = threadIdx.x; h < kHashSlots; h += kScatterThreads) {
     keys[h] = kEmpty;
     acc[0][h] = 0.0;
@@ -414,31 +444,37 @@ k_scatter(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_d
   load_tile_consts(a, w_det, tl, d0, t0, tc);
   if constexpr (QUAT) load_tile_quats(a.qd, a.n_det, tl, d0, tq);
   __syncthreads();
+  if constexpr (QUAT) {
+    if (a.hwp && !a.dpsi) {
+      load_tile_turns(tc, tl, turn4a);
+      __syncthreads();
+    }
+  }
 
-  for (int32_t s0 = threadIdx.x; s0 < nsamp; s0 += kBatch * kScatterThreads) {
-    Slot sl[kBatch];
-    int32_t px[kBatch];
-    T v[kBatch], c[kBatch], s[kBatch];
+  for (int32_t s0 = threadIdx.x; s0 < nsamp; s0 += KB * kScatterThreads) {
+    Slot sl[KB];
+    int32_t px[KB];
+    T v[KB], c[KB], s[KB];
     if constexpr (QUAT) {
-      Quat qb[kBatch];
+      Quat qb[KB];
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
+      for (int b = 0; b < KB; ++b) {
         sl[b] = slot_of(tl, d0, t0, s0 + b * kScatterThreads, a.n_det, a.n_samp);
         qb[b] = load_quat(a.qb, t0 + sl[b].il < a.n_samp ? t0 + sl[b].il : 0);
         if constexpr (MODE == 2) px[b] = pix_in[sl[b].off];
         if constexpr (MODE != 1) v[b] = tod[sl[b].off];
       }
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
+      for (int b = 0; b < KB; ++b) {
         int32_t pq;
-        quat_slot(a, tc, sl[b], quat_dir(qmul(qb[b], tq[sl[b].kl])), pq, c[b], s[b]);
+        quat_slot(a, tc, turn4a, sl[b], quat_dir(qmul(qb[b], tq[sl[b].kl])), pq, c[b], s[b]);
         if constexpr (MODE != 2) px[b] = pq;
         if (!sl[b].in) px[b] = -1;
       }
     } else {
-      T th[kBatch], ph[kBatch], ps[kBatch];
+      T th[KB], ph[KB], ps[KB];
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
+      for (int b = 0; b < KB; ++b) {
         sl[b] = slot_of(tl, d0, t0, s0 + b * kScatterThreads, a.n_det, a.n_samp);
         ps[b] = a.psi[sl[b].off];
         if constexpr (MODE == 2) {
@@ -450,34 +486,34 @@ k_scatter(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_d
         if constexpr (MODE != 1) v[b] = tod[sl[b].off];
       }
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
+      for (int b = 0; b < KB; ++b) {
         if constexpr (MODE != 2) px[b] = pixel_of(a, th[b], ph[b]);
         if (!sl[b].in) px[b] = -1;
         pol_weights(a, tc, sl[b], ps[b], c[b], s[b]);
       }
     }
     if constexpr (MODE == 1) {
-      MT I[kBatch], Q[kBatch], U[kBatch];
+      MT I[KB], Q[KB], U[KB];
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
+      for (int b = 0; b < KB; ++b) {
         int32_t tag;
         load_iqu<IL>(pmap, p_cs, px[b] >= 0 ? px[b] : 0, I[b], Q[b], U[b], tag);
       }
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
+      for (int b = 0; b < KB; ++b) {
         const T g = (T)tc.gain[sl[b].kl];
         const T y = g * ((T)I[b] + c[b] * (T)Q[b] + s[b] * (T)U[b]);
         v[b] = g * ((T)tc.w[sl[b].kl] * y);
       }
     } else {
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
+      for (int b = 0; b < KB; ++b) {
         v[b] = (T)tc.gain[sl[b].kl] * v[b];
         if (w_det) v[b] = v[b] * (T)tc.w[sl[b].kl];
       }
     }
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b) {
+    for (int b = 0; b < KB; ++b) {
       if (px[b] < 0) continue;
       hash_add(keys, acc, px[b], (double)v[b], (double)(v[b] * c[b]), (double)(v[b] * s[b]), q,
                ql);

@@ -363,14 +363,20 @@ struct SpLds;
 template <>
 struct SpLds<0> {
   double acc[3][kSpPix];
-  double two_alpha[kHwpTable];
+  union {
+    double two_alpha[kHwpTable];
+    double2 turn4a[kHwpPeriodMax];   // quaternion pointing: (cos, sin) 4 alpha for u < den
+  };
   SpRunLds run;
 };
 template <>
 struct SpLds<1> {
   double acc[6][kSpPix];
   int32_t hits[kSpPix];
-  double two_alpha[kHwpTable];
+  union {
+    double two_alpha[kHwpTable];
+    double2 turn4a[kHwpPeriodMax];   // quaternion pointing: (cos, sin) 4 alpha for u < den
+  };
   SpRunLds run;
 };
 
@@ -400,7 +406,19 @@ k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_
     if constexpr (KIND == 1) L.hits[l] = 0;
   }
   const bool table = a.hwp && a.hwp_den <= kHwpPeriodMax;
-  if (table) {
+  // quaternion pointing with a HWP and no angle offsets: the weights' turn is
+  // by 4 alpha alone, tabulated as its cosine and sine over one HWP period
+  const bool qturn = QUAT && table && !a.dpsi;
+  if (qturn) {
+    for (int u = threadIdx.x; u < (int)a.hwp_den; u += kSpThreads) {
+#pragma clang fp contract(off)
+      const int64_t m = (a.hwp_num_mod * u) % a.hwp_den;
+      const double frac = (double)m / (double)a.hwp_den;
+      double sn, cs;
+      sincos(2.0 * (2.0 * ((2.0 * kPi) * frac + a.hwp_phase0)), &sn, &cs);
+      L.turn4a[u] = make_double2(cs, sn);
+    }
+  } else if (table) {
     // two_alpha[u] = 2 alpha for a sample index congruent to u mod den, for
     // u < den + kMaxRun, so that (phase of the run's first sample) + offset
     // inside the run indexes it without a modulo
@@ -483,7 +501,7 @@ k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_
       // psi_eff = psi + dpsi_k + 2 alpha_i, in the oracle's order (beta: the
       // part that does not come from the pointing)
       double two_a = 0.0;
-      if (a.hwp) {
+      if (a.hwp && !qturn) {
         if (table) {
           two_a = L.two_alpha[L.run.hwp0[r] + t];
         } else {
@@ -493,9 +511,17 @@ k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_
       }
       T c, sn;
       if constexpr (QUAT) {
-        double beta = a.dpsi ? L.run.dpsi[r] : 0.0;
-        if (a.hwp) beta = beta + two_a;
-        quat_weights(quat_dir(qmul(qb[b], qd[b])), a.dpsi || a.hwp, beta, c, sn);
+        const QuatDir qdir = quat_dir(qmul(qb[b], qd[b]));
+        if (qturn) {
+          double c2, s2;
+          quat_c2s2(qdir, c2, s2);
+          const double2 tn = L.turn4a[(uint32_t)(L.run.hwp0[r] + t) % (uint32_t)a.hwp_den];
+          turn_weights(c2, s2, (T)tn.x, (T)tn.y, c, sn);
+        } else {
+          double beta = a.dpsi ? L.run.dpsi[r] : 0.0;
+          if (a.hwp) beta = beta + two_a;
+          quat_weights(qdir, a.dpsi || a.hwp, beta, c, sn);
+        }
       } else {
         double pe = (double)ps[b];
         if (a.dpsi) pe = pe + L.run.dpsi[r];

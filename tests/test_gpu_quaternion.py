@@ -96,9 +96,10 @@ def test_quaternion_pixels_bitexact_fp32_path(fx):
     _check_pixels(256, got, prob.bore_quat, prob.det_quat)
 
 
+@pytest.mark.parametrize("dpsi", [True, False])   # False: the tabulated HWP turn
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-6)])
-def test_quaternion_P_and_PT(fx, dtype, tol):
-    w, P, N, prob = _qcase(fx, 32, 5, 30001, dtype=dtype, kind="diag")
+def test_quaternion_P_and_PT(fx, dtype, tol, dpsi):
+    w, P, N, prob = _qcase(fx, 32, 5, 30001, dtype=dtype, kind="diag", dpsi=dpsi)
     m = synth.sky_map(w).numpy()
     pix, c, s = prob.geometry()
     y_ref = opt.apply_pix(pix, c, s, m, prob.gain)
@@ -111,10 +112,11 @@ def test_quaternion_P_and_PT(fx, dtype, tol):
     assert rel_err(q.cpu().numpy(), q_ref) <= tol
 
 
+@pytest.mark.parametrize("dpsi", [True, False])
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-6)])
-def test_quaternion_normal_operator_band(fx, dtype, tol):
+def test_quaternion_normal_operator_band(fx, dtype, tol, dpsi):
     """Band N with a power-of-two nside: the superpixel transpose path."""
-    w, P, N, prob = _qcase(fx, 64, 6, 40000, dtype=dtype, kind="band", b=129)
+    w, P, N, prob = _qcase(fx, 64, 6, 40000, dtype=dtype, kind="band", b=129, dpsi=dpsi)
     g = torch.Generator(device=dev()).manual_seed(3)
     x = torch.randn(3, P.npix, dtype=torch.float64, device=dev(), generator=g)
     got = fx.normal_apply(P, N, x).cpu().numpy()
@@ -132,9 +134,9 @@ def test_quaternion_bj_blocks(fx):
     assert rel_err(M6.cpu().numpy(), M_ref) <= 1e-12
 
 
-@pytest.mark.parametrize("kind", ["diag", "band"])
-def test_quaternion_pcg_matches_oracle(fx, kind):
-    w, P, N, prob = _qcase(fx, 32, 4, 40000, kind=kind, b=65)
+@pytest.mark.parametrize("kind,dpsi", [("diag", True), ("band", True), ("band", False)])
+def test_quaternion_pcg_matches_oracle(fx, kind, dpsi):
+    w, P, N, prob = _qcase(fx, 32, 4, 40000, kind=kind, b=65, dpsi=dpsi)
     m = synth.sky_map(w).numpy()
     n = synth.noise(w.with_(noise="diag")).numpy()
     pix, c, s = prob.geometry()
