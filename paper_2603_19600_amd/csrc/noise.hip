@@ -350,6 +350,313 @@ __global__ void __launch_bounds__(NT) k_overlap_save(const T *__restrict__ in, T
   }
 }
 
+// v[r] *= w1^r for r = 1..15, w1 = narrow(W1).  w2, w4, w8 are squared in
+// FP64; the other powers are products in T (w3 = w1 w2, w5 = w1 w4, w6 = w2 w4,
+// w7 = w3 w4, w(r+8) = w(r) w8), each applied as soon as it is formed so that
+// only w1, w2, w4, w8 stay live.
+template <typename T, bool INV>
+__device__ __forceinline__ void twiddle16(C2<T> (&v)[16], C2<double> W1) {
+  const C2<double> W2 = cmul(W1, W1), W4 = cmul(W2, W2), W8 = cmul(W4, W4);
+  const C2<T> w1 = narrow<T>(W1), w2 = narrow<T>(W2), w4 = narrow<T>(W4), w8 = narrow<T>(W8);
+  v[8] = twiddle<T, INV>(v[8], w8);
+  C2<T> w3 = cmul(w1, w2);
+#pragma unroll
+  for (int r = 1; r < 8; ++r) {
+    C2<T> w;
+    switch (r) {
+      case 1: w = w1; break;
+      case 2: w = w2; break;
+      case 3: w = w3; break;
+      case 4: w = w4; break;
+      case 5: w = cmul(w1, w4); break;
+      case 6: w = cmul(w2, w4); break;
+      default: w = cmul(w3, w4); break;
+    }
+    v[r] = twiddle<T, INV>(v[r], w);
+    v[r + 8] = twiddle<T, INV>(v[r + 8], cmul(w, w8));
+  }
+}
+
+// Output k of the real-spectrum split, kernel multiply and re-pack, from the
+// packed forward transform Z (za = Z[k], zb = Z[M - k]): with E and O the
+// spectra of the even and odd samples, X[k] = E + W^k O and X[k + M] =
+// E - W^k O (W = exp(-2 pi i / L)); multiplying by the real, symmetric kernel
+// spectrum H and re-packing gives E' + i O' with
+//   E' = E hp + W^k O hm,  O' = conj(W^k) E hm + O hp,
+// hp = (H[k] + H[M-k]) / 2, hm = (H[k] - H[M-k]) / 2 (H already divided by M).
+template <typename T>
+__device__ __forceinline__ C2<T> split_mul(C2<T> za, C2<T> zb, T Hk, T Hm, C2<T> Wk) {
+  const C2<T> zc = {zb.x, -zb.y};             // conj(Z[M - k])
+  const C2<T> E = cscale(cadd(za, zc), (T)0.5);
+  const C2<T> Dh = cscale(csub(za, zc), (T)0.5);
+  const C2<T> O = {Dh.y, -Dh.x};              // (Z[k] - conj Z[M-k]) / (2i)
+  const T hp = (Hk + Hm) * (T)0.5, hm = (Hk - Hm) * (T)0.5;
+  const C2<T> A = cadd(cscale(E, hp), cscale(cmul(Wk, O), hm));
+  const C2<T> B = cadd(cscale(cmulc(E, Wk), hm), cscale(O, hp));
+  return {A.x - B.y, A.y + B.x};              // A + i B
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident overlap-save for the long blocks, M = 4096 RL (RL = 2 or
+// 4: FP64 M = 8192, FP32 M = 16384 or 8192).
+//
+// 256 threads hold the whole packed block in registers (M / 256 = 32 or 64
+// complex values each) and use LDS only to exchange data between passes,
+// through a buffer of HALF the block (64 KB), in two rounds: so two
+// workgroups fit one CU and one's HBM traffic overlaps the other's FFT.
+//   forward  : radix 16, 16, 16, RL   (spans Ns = 1, 16, 256, 4096)
+//   inverse  : radix RL, 16, 16, 16   (spans Ns = 1, RL, 16 RL, 256 RL)
+// The last forward pass gives thread t the butterflies j and 4096 - j
+// (j = t + 256 i), whose outputs Z[j + 4096 r] and Z[4096 - j + 4096 r'] are
+// exactly the pairs (k, M - k) that the real-spectrum split needs, and the
+// split's outputs are exactly the inputs of those two butterflies in the
+// first inverse pass (radix RL, span 1): split, kernel multiply and that pass
+// run in registers with no exchange.  The first forward pass reads its inputs
+// from HBM and the last inverse pass writes its outputs there.  Every
+// exchange is static in which half a value travels: a radix-16 butterfly's
+// outputs lie in the lower half iff j < M/32, and a radix-16 pass's inputs
+// j + r M/16 iff r < 8.  Twiddles come from the FP64 table tw[j] =
+// exp(-2 pi i j / L) (L2-resident), one lookup per butterfly and pass.
+// ---------------------------------------------------------------------------
+constexpr int kOsRegThreads = 256;
+
+// Radix-16 butterfly q (j = tid + q NT) of a pass of span Ns, on v[16 q ..]:
+// twiddles for k = j mod Ns, then the 16-point DFT (result in dft16 order).
+template <typename T, int M, bool INV>
+__device__ __forceinline__ void reg_r16(C2<T> *v, int j, int Ns, const C2<double> *tw) {
+  constexpr int L = 2 * M;
+  const int k = j & (Ns - 1);
+  if (Ns > 1) twiddle16<T, INV>(*reinterpret_cast<C2<T>(*)[16]>(v), tw[k * (L / (16 * Ns))]);
+  dft16<T, INV>(*reinterpret_cast<C2<T>(*)[16]>(v));
+}
+
+// Exchange after a radix-16 pass of span Ns (Ns divides M/32) into the layout
+// of the next radix-16 pass: v[16 q + r] = element j + r M/16.
+template <typename T, int M, int NT>
+__device__ __forceinline__ void reg_xchg16(C2<T> *s, C2<T> (&v)[M / NT], int tid, int Ns) {
+  constexpr int NB16 = M / 16, B16 = NB16 / NT, HALF = M / 2;
+  C2<T> tmp[M / NT / 2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int q = h * B16 / 2; q < (h + 1) * B16 / 2; ++q) {
+      const int j = tid + q * NT, k = j & (Ns - 1);
+      const int d = (j - k) * 16 + k - h * HALF;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s[pad16(d + r * Ns)] = v[16 * q + 4 * (r & 3) + (r >> 2)];
+    }
+    lds_barrier();
+#pragma unroll
+    for (int q = 0; q < B16; ++q) {
+      const int j = tid + q * NT;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const C2<T> e = s[pad16(j + (8 * h + r) * NB16 - h * HALF)];
+        if (h == 0) tmp[8 * q + r] = e;
+        else v[16 * q + 8 + r] = e;
+      }
+    }
+    lds_barrier();
+  }
+#pragma unroll
+  for (int q = 0; q < B16; ++q)
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[16 * q + r] = tmp[8 * q + r];
+}
+
+template <typename T, int M>
+__global__ void __launch_bounds__(kOsRegThreads, 2)
+k_os_reg(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, int64_t nblk,
+         const T *__restrict__ spec, int64_t spec_stride, const C2<double> *__restrict__ tw) {
+  constexpr int NT = kOsRegThreads;
+  constexpr int RL = M / 4096;
+  static_assert(RL == 2 || RL == 4, "M = 8192 or 16384");
+  constexpr int L = 2 * M, HALF = M / 2, NB16 = M / 16, B16 = NB16 / NT, NPT = M / NT;
+  static_assert(NPT == 16 * RL, "8 butterfly pairs of the last forward pass per thread");
+  __shared__ C2<T> s[HALF + HALF / 16];
+  const int tid = threadIdx.x;
+  const int64_t det = (int64_t)blockIdx.x / nblk, blk = (int64_t)blockIdx.x - det * nblk;
+  const int V = L - 2 * (b - 1);
+  // sample offsets within a detector's stream are 32-bit (the launcher checks
+  // n + L < 2^31), so each access is a uniform base plus one 32-bit offset
+  const int32_t s0 = (int32_t)(blk * V) - (b - 1);
+  const int32_t n32 = (int32_t)n;
+  C2<T> v[NPT];
+
+  // ---- forward pass 0 (radix 16, span 1) straight from HBM
+  {
+    const T *x = in + det * n;
+#pragma unroll
+    for (int q = 0; q < B16; ++q)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        // unconditional loads from clamped offsets, zeroed outside the stream
+        const int32_t g = s0 + 2 * (tid + q * NT + r * NB16);
+        const T a = x[g < 0 ? 0 : (g < n32 ? g : n32 - 1)];
+        const T c = x[g + 1 < 0 ? 0 : (g + 1 < n32 ? g + 1 : n32 - 1)];
+        v[16 * q + r].x = (g >= 0 && g < n32) ? a : (T)0;
+        v[16 * q + r].y = (g + 1 >= 0 && g + 1 < n32) ? c : (T)0;
+      }
+#pragma unroll
+    for (int q = 0; q < B16; ++q) reg_r16<T, M, false>(v + 16 * q, tid + q * NT, 1, tw);
+  }
+  reg_xchg16<T, M, NT>(s, v, tid, 1);
+  // ---- forward pass 1 (span 16), exchange
+#pragma unroll
+  for (int q = 0; q < B16; ++q) reg_r16<T, M, false>(v + 16 * q, tid + q * NT, 16, tw);
+  reg_xchg16<T, M, NT>(s, v, tid, 16);
+  // ---- forward pass 2 (span 256), exchange into the paired layout of pass 3:
+  // v[(2 i + h) RL + r] = element jh_i + 4096 r, j0 = tid + 256 i, j1 = 4096 - j0
+  // (2048 for j0 = 0)
+#pragma unroll
+  for (int q = 0; q < B16; ++q) reg_r16<T, M, false>(v + 16 * q, tid + q * NT, 256, tw);
+  {
+    C2<T> tmp[NPT / 2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int q = h * B16 / 2; q < (h + 1) * B16 / 2; ++q) {
+        const int j = tid + q * NT, k = j & 255;
+        const int d = (j - k) * 16 + k - h * HALF;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) s[pad16(d + r * 256)] = v[16 * q + 4 * (r & 3) + (r >> 2)];
+      }
+      lds_barrier();
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int j0 = tid + 256 * i;
+        const int j1 = j0 == 0 ? 2048 : 4096 - j0;
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+#pragma unroll
+          for (int r = h * RL / 2; r < (h + 1) * RL / 2; ++r) {
+            const C2<T> val = s[pad16((e ? j1 : j0) + 4096 * r - h * HALF)];
+            if (h == 0) tmp[(2 * i + e) * (RL / 2) + r] = val;
+            else v[(2 * i + e) * RL + r] = val;
+          }
+      }
+      lds_barrier();
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int r = 0; r < RL / 2; ++r) v[(2 * i + e) * RL + r] = tmp[(2 * i + e) * (RL / 2) + r];
+  }
+  // ---- forward pass 3 (radix RL, span 4096), split + kernel multiply, inverse
+  // pass 0 (radix RL, span 1), all in registers
+  const T *H = spec + det * spec_stride;   // H[0..M], already divided by M
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int j0 = tid + 256 * i;
+    const int j1 = j0 == 0 ? 2048 : 4096 - j0;
+    C2<T> Z[2][RL];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      C2<T> *w = v + (2 * i + e) * RL;
+      const C2<double> W1 = tw[2 * (e ? j1 : j0)];   // exp(-2 pi i j / M)
+      if constexpr (RL == 2) {
+        const C2<T> b1 = twiddle<T, false>(w[1], narrow<T>(W1));
+        Z[e][0] = cadd(w[0], b1);
+        Z[e][1] = csub(w[0], b1);
+      } else {
+        const C2<double> W2 = cmul(W1, W1), W3 = cmul(W1, W2);
+        C2<T> a0 = w[0], a1 = twiddle<T, false>(w[1], narrow<T>(W1));
+        C2<T> a2 = twiddle<T, false>(w[2], narrow<T>(W2)), a3 = twiddle<T, false>(w[3], narrow<T>(W3));
+        dft4<T, false>(a0, a1, a2, a3);
+        Z[e][0] = a0;
+        Z[e][1] = a1;
+        Z[e][2] = a2;
+        Z[e][3] = a3;
+      }
+    }
+    // element index of Z[e][r] is (e ? j1 : j0) + 4096 r; its partner M - that
+    // sits at Z[1 - e][RL - 1 - r], except in the pair j0 = 0, j1 = 2048,
+    // where Z[0][r] pairs with Z[0][(RL - r) % RL] and Z[1][r] with Z[1][RL - 1 - r]
+    const bool z0 = j0 == 0;
+    C2<T> X[2][RL];
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int a = (e ? j1 : j0) + 4096 * r;
+        const C2<T> zb = (z0 && e == 0) ? Z[0][(RL - r) % RL] : Z[1 - e][RL - 1 - r];
+        const C2<T> zb0 = (z0 && e == 1) ? Z[1][RL - 1 - r] : zb;
+        X[e][r] = split_mul<T>(Z[e][r], zb0, H[a], H[M - a], narrow<T>(tw[a]));
+      }
+    // inverse pass 0: radix RL, span 1 (no twiddles), in place
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      C2<T> *w = v + (2 * i + e) * RL;
+      if constexpr (RL == 2) {
+        w[0] = cadd(X[e][0], X[e][1]);
+        w[1] = csub(X[e][0], X[e][1]);
+      } else {
+        C2<T> a0 = X[e][0], a1 = X[e][1], a2 = X[e][2], a3 = X[e][3];
+        dft4<T, true>(a0, a1, a2, a3);
+        w[0] = a0;
+        w[1] = a1;
+        w[2] = a2;
+        w[3] = a3;
+      }
+    }
+  }
+  // ---- exchange: inverse pass 0 outputs (butterfly j at RL j + r; j0 < 2048
+  // in the lower half, j1 >= 2048 in the upper) -> radix-16 layout
+  {
+    C2<T> tmp[NPT / 2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int j0 = tid + 256 * i;
+        const int j = h == 0 ? j0 : (j0 == 0 ? 2048 : 4096 - j0);
+#pragma unroll
+        for (int r = 0; r < RL; ++r) s[pad16(RL * j + r - h * HALF)] = v[(2 * i + h) * RL + r];
+      }
+      lds_barrier();
+#pragma unroll
+      for (int q = 0; q < B16; ++q) {
+        const int j = tid + q * NT;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const C2<T> e = s[pad16(j + (8 * h + r) * NB16 - h * HALF)];
+          if (h == 0) tmp[8 * q + r] = e;
+          else v[16 * q + 8 + r] = e;
+        }
+      }
+      lds_barrier();
+    }
+#pragma unroll
+    for (int q = 0; q < B16; ++q)
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[16 * q + r] = tmp[8 * q + r];
+  }
+  // ---- inverse passes 1 (span RL) and 2 (span 16 RL)
+#pragma unroll
+  for (int q = 0; q < B16; ++q) reg_r16<T, M, true>(v + 16 * q, tid + q * NT, RL, tw);
+  reg_xchg16<T, M, NT>(s, v, tid, RL);
+#pragma unroll
+  for (int q = 0; q < B16; ++q) reg_r16<T, M, true>(v + 16 * q, tid + q * NT, 16 * RL, tw);
+  reg_xchg16<T, M, NT>(s, v, tid, 16 * RL);
+  // ---- inverse pass 3 (span M/16): outputs j + r M/16, straight to HBM
+  T *z = out + det * n;
+  const int lo = b - 1, hi = b - 1 + V;
+#pragma unroll
+  for (int q = 0; q < B16; ++q) {
+    const int j = tid + q * NT;
+    reg_r16<T, M, true>(v + 16 * q, j, NB16, tw);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const C2<T> w = v[16 * q + 4 * (r & 3) + (r >> 2)];
+      const int e = 2 * (j + r * NB16);
+      if (e >= lo && e < hi && s0 + e < n32) z[s0 + e] = w.x;
+      if (e + 1 >= lo && e + 1 < hi && s0 + e + 1 < n32) z[s0 + e + 1] = w.y;
+    }
+  }
+}
+
 // Spectrum of the symmetric circular kernel of length L = 2M, divided by M:
 // H[k] = (t0 + 2 sum_{tau=1}^{b-1} t[tau] cos(2 pi k tau / L)) / M, k = 0..M.
 // One wave per frequency k: the lanes split the lags, cos(2 pi k tau / L) is
@@ -438,12 +745,16 @@ void release_twiddles() {
   g_tw.clear();
 }
 
-// FFT half-length M used for a band of b lags in precision T.
+// FFT half-length M used for a band of b lags in precision T: the smallest
+// power of two with M >= 4 (b - 1) (at most a quarter of each block is
+// halo), capped at 8192, the register-resident kernel's length -- for b up to
+// 4096 its two blocks per CU beat a longer block with fewer wasted outputs,
+// also in FP32 (measured).  Wider FP32 bands take one 16384-point block per CU.
 template <typename T>
 int os_half_length(int64_t b) {
-  const int64_t mmax = sizeof(T) == 4 ? 16384 : 8192;
   int64_t m = 512;
-  while (m < 4 * (b - 1) && m < mmax) m *= 2;
+  while (m < 4 * (b - 1) && m < 8192) m *= 2;
+  if (sizeof(T) == 4 && b > 4096) m = 16384;
   return (int)m;
 }
 
@@ -497,6 +808,22 @@ static furax_status launch_os(const furax_noise *N, const T *in, T *out, const T
   return FURAX_OK;
 }
 
+template <typename T, int M>
+static furax_status launch_os_reg(const furax_noise *N, const T *in, T *out, const T *spec,
+                                  const C2<double> *tw, hipStream_t s) {
+  const int b = (int)N->bandwidth;
+  const int64_t V = 2 * M - 2 * (int64_t)(b - 1);
+  const int64_t nblk = (N->n_samp + V - 1) / V;
+  const int64_t ntask = N->n_det * nblk;
+  const int64_t spec_stride = N->toeplitz_stride ? (M + 1) : 0;
+  if (N->n_samp + 4 * (int64_t)M >= ((int64_t)1 << 31))   // 32-bit offsets inside the kernel
+    return launch_os<T, M, M / 16>(N, in, out, spec, tw, s);
+  hipLaunchKernelGGL((k_os_reg<T, M>), dim3((unsigned)ntask), dim3(kOsRegThreads), 0, s, in, out,
+                     N->n_samp, b, nblk, spec, spec_stride, tw);
+  FX_HIP(hipGetLastError());
+  return FURAX_OK;
+}
+
 // Apply N^-1 given a prepared spectrum (kind 1) or the diagonal weights (kind 0).
 template <typename T>
 furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *spec,
@@ -520,7 +847,7 @@ furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *sp
     case 1024: return launch_os<T, 1024, 64>(N, in, out, sp, t, s);
     case 2048: return launch_os<T, 2048, 128>(N, in, out, sp, t, s);
     case 4096: return launch_os<T, 4096, 256>(N, in, out, sp, t, s);
-    case 8192: return launch_os<T, 8192, 512>(N, in, out, sp, t, s);
+    case 8192: return launch_os_reg<T, 8192>(N, in, out, sp, t, s);
     case 16384:
       if constexpr (sizeof(T) == 4) return launch_os<T, 16384, 1024>(N, in, out, sp, t, s);
       break;

@@ -173,7 +173,8 @@ def test_hits_bitexact_and_sum(fx):
 
 # ---------------------------------------------------------------- N^-1
 @pytest.mark.parametrize("n_samp,b", [(1, 1), (100, 1), (5000, 7), (40000, 129), (70001, 4096),
-                                      (16384, 4096), (200_000, 1000)])
+                                      (16384, 4096), (200_000, 1000), (50_001, 2500),
+                                      (8194, 4096)])
 def test_band_noise_f64(fx, n_samp, b):
     rng = np.random.default_rng(n_samp + b)
     y = rng.standard_normal((2, n_samp))
@@ -184,7 +185,8 @@ def test_band_noise_f64(fx, n_samp, b):
     assert rel_err(got, ref) <= 1e-12
 
 
-@pytest.mark.parametrize("n_samp,b", [(5000, 7), (70001, 4096), (100_000, 8192), (3, 2)])
+@pytest.mark.parametrize("n_samp,b", [(5000, 7), (70001, 4096), (100_000, 8192), (3, 2),
+                                      (50_001, 2500)])
 def test_band_noise_f32(fx, n_samp, b):
     rng = np.random.default_rng(n_samp + b)
     y = rng.standard_normal((3, n_samp)).astype(np.float32)
@@ -193,6 +195,20 @@ def test_band_noise_f32(fx, n_samp, b):
     N = fx.Noise("band", 3, n_samp, lags=torch.from_numpy(t).to(dev()))
     got = fx.noise_apply(N, torch.from_numpy(y).to(dev())).cpu().numpy()
     assert rel_err(got, ref) <= 2e-6
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-12), (np.float32, 2e-6)])
+def test_band_noise_per_detector_long_kernels(fx, dtype, tol):
+    """Per-detector lags wide enough for the register-resident 8192-point blocks."""
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal((3, 30001)).astype(dtype)
+    base = synth.toeplitz_lags(synth.WORKLOADS[2], 3000)
+    t = np.stack([base, 0.5 * base, 2.0 * base]) + 1e-3 * rng.standard_normal((3, 3000))
+    t[:, 0] = np.abs(t[:, 0]) + 1.0
+    ref = onz.band_apply(y.astype(np.float64), t, "fft")
+    N = fx.Noise("band", 3, 30001, lags=torch.from_numpy(t).to(dev()))
+    got = fx.noise_apply(N, torch.from_numpy(y).to(dev())).cpu().numpy()
+    assert rel_err(got, ref) <= tol
 
 
 def test_band_noise_per_detector_kernels(fx):
