@@ -101,7 +101,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nside512_256x2p20_band409
 # kernels making up each phase, by rocprofv3 kernel name ({T}: double or float)
 PHASE_KERNELS = {
     "apply": ["fx::k_apply<{T}, {T}, true, false>"],
-    "noise": ["fx::k_overlap_save<{T}, "],
+    "noise": ["fx::k_os_reg<{T}, ", "fx::k_overlap_save<{T}, "],
     "transpose": ["fx::k_sp_accum<{T}, 0, false>", "fx::k_sp_reduce"],
 }
 
@@ -244,6 +244,115 @@ def host_info():
     return info
 
 
+# ---------------------------------------------------------------------------
+# Profile records (run on the rocprofv3 output of this script; nothing below
+# is used by the measurement itself).
+# ---------------------------------------------------------------------------
+def _rocpd_dbs(d):
+    import glob
+
+    return sorted(glob.glob(os.path.join(d, "**", "*.db"), recursive=True))
+
+
+def _short_kernel(name):
+    import re
+
+    return re.sub(r"\(.*", "", name).replace("void ", "")
+
+
+def summarize_trace(db_dir, out, command, title):
+    """Markdown table of a rocprofv3 --kernel-trace run: per-kernel calls and
+    durations with the launch resources, the library's kernels only."""
+    import sqlite3
+
+    rows = []
+    for db in _rocpd_dbs(db_dir):
+        con = sqlite3.connect(db)
+        rows += list(con.execute(
+            "select name, count(*), avg(duration), sum(duration), min(duration), max(duration), "
+            "max(vgpr_count), max(accum_vgpr_count), max(sgpr_count), max(lds_size), "
+            "max(scratch_size), max(workgroup_x), max(grid_x) from kernels group by name"))
+    rows = sorted((r for r in rows if "fx::" in r[0]), key=lambda r: -r[3])
+    lines = [f"# {title}", "", "Command (run from the repository root on one MI355X):", "",
+             "```", command, "```", "", "Durations in microseconds (rocprofv3 kernel trace).", "",
+             "| kernel | calls | avg us | total us | min us | max us | VGPR | AGPR | SGPR | LDS B "
+             "| scratch B | wg | grid |", "|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| `{_short_kernel(r[0])}` | {r[1]} | {r[2] / 1000:.1f} | {r[3] / 1000:.1f} | "
+                     f"{r[4] / 1000:.1f} | {r[5] / 1000:.1f} | {r[6]} | {r[7]} | {r[8]} | {r[9]} | "
+                     f"{r[10]} | {r[11]} | {r[12]} |")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def traffic_record(fetch_dir, write_dir, out, commands):
+    """The FETCH_SIZE / WRITE_SIZE record measured_traffic() reads: KiB per
+    dispatch of every library kernel, the 1 GiB calibration copy's counts, and
+    the fingerprint of the sources they were taken on."""
+    import collections
+    import sqlite3
+
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    calib = {}
+    for d in (fetch_dir, write_dir):
+        for db in _rocpd_dbs(d):
+            con = sqlite3.connect(db)
+            for name, cname, v, grid in con.execute(
+                    "select kernel_name, counter_name, value, grid_size from counters_collection "
+                    "order by dispatch_id"):
+                if "copy" in name and grid == (1 << 26) and cname not in calib:
+                    calib[cname] = v
+                if "fx::" in name:
+                    vals[_short_kernel(name)][cname].append(v)
+    rec = {"calibration_copy_bytes": 1 << 30, "calibration_kib": calib, "commands": commands,
+           "source_sha256": source_fingerprint(), "kernels": {}}
+    for k, d in vals.items():
+        rec["kernels"][k] = {c: sum(v) / len(v) for c, v in d.items()}
+        rec["kernels"][k]["dispatches"] = len(d.get("FETCH_SIZE", []))
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1, sort_keys=True)
+
+
+def counter_summary(dirs, out, commands, title):
+    """Markdown table of rocprofv3 --pmc runs: per library kernel, dispatches,
+    mean duration and the mean of each counter per dispatch; with
+    SQ_INSTS_VALU, the VALU busy fraction (a wave64 VALU instruction occupies
+    a 16-lane SIMD for 4 cycles; 1024 SIMDs at 2.4 GHz)."""
+    import collections
+    import sqlite3
+
+    rows = collections.defaultdict(lambda: collections.defaultdict(list))
+    for d in dirs:
+        for db in _rocpd_dbs(d):
+            con = sqlite3.connect(db)
+            for name, cname, v, dur in con.execute(
+                    "select kernel_name, counter_name, value, duration from counters_collection"):
+                if "fx::" in name:
+                    r = rows[_short_kernel(name)]
+                    r[cname].append(v)
+                    r["_dur"].append(dur / 1000.0)
+    cnames = sorted({c for r in rows.values() for c in r if c != "_dur"})
+    busy = "SQ_INSTS_VALU" in cnames
+    head = ["kernel", "dispatches", "mean us"] + cnames + (["VALU busy"] if busy else [])
+    lines = [f"# {title}", "", "Commands (run from the repository root on one MI355X, one "
+             "counter group per run):", "", "```"] + commands + ["```", "",
+             "Counter values are means per dispatch over the profiled run (set-up and "
+             "iterations); FETCH_SIZE / WRITE_SIZE in KiB.", "",
+             "| " + " | ".join(head) + " |", "|" + "---|" * len(head)]
+    for k in sorted(rows, key=lambda k: -sum(rows[k]["_dur"])):
+        r = rows[k]
+        dur = sum(r["_dur"]) / len(r["_dur"])
+        cells = [f"`{k}`", str(max(len(v) for c, v in r.items() if c != "_dur")), f"{dur:.1f}"]
+        for c in cnames:
+            cells.append(f"{sum(r[c]) / len(r[c]):.4g}" if r.get(c) else "")
+        if busy:
+            v = r.get("SQ_INSTS_VALU")
+            cells.append(f"{100 * (sum(v) / len(v)) * 4 / (1024 * 2400.0) / dur:.0f} %" if v else "")
+        lines.append("| " + " | ".join(cells) + " |")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,7 +364,27 @@ def main():
                     help="skip the boresight-quaternion pointing variants")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-dets", type=int, default=64)
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="write the kernel-trace summary of a rocprofv3 output directory to --out")
+    ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the FETCH_SIZE / WRITE_SIZE record of two rocprofv3 --pmc runs "
+                         "to --out")
+    ap.add_argument("--counter-summary", nargs="+", metavar="DIR",
+                    help="write the per-kernel counter table of rocprofv3 --pmc outputs to --out")
+    ap.add_argument("--out")
+    ap.add_argument("--command", action="append", default=[],
+                    help="the profiling command(s) to record in the summary")
+    ap.add_argument("--title", default="rocprofv3 kernel summary")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.out, "\n".join(args.command), args.title)
+        return
+    if args.counter_summary:
+        counter_summary(args.counter_summary, args.out, args.command, args.title)
+        return
+    if args.traffic_record:
+        traffic_record(args.traffic_record[0], args.traffic_record[1], args.out, args.command)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the map-making path is built and measured on a single "
