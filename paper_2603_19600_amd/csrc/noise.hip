@@ -418,7 +418,6 @@ __device__ __forceinline__ C2<T> split_mul(C2<T> za, C2<T> zb, T Hk, T Hm, C2<T>
 // j + r M/16 iff r < 8.  Twiddles come from the FP64 table tw[j] =
 // exp(-2 pi i j / L) (L2-resident), one lookup per butterfly and pass.
 // ---------------------------------------------------------------------------
-constexpr int kOsRegThreads = 256;
 
 // Radix-16 butterfly q (j = tid + q NT) of a pass of span Ns, on v[16 q ..]:
 // twiddles for k = j mod Ns, then the 16-point DFT (result in dft16 order).
@@ -433,18 +432,32 @@ __device__ __forceinline__ void reg_r16(C2<T> *v, int j, int Ns, const C2<double
 // Exchange after a radix-16 pass of span Ns (Ns divides M/32) into the layout
 // of the next radix-16 pass: v[16 q + r] = element j + r M/16.
 template <typename T, int M, int NT>
+__device__ __forceinline__ void reg_write16(C2<T> *s, const C2<T> (&v)[M / NT], int tid, int Ns,
+                                            int h) {
+  constexpr int B16 = M / 16 / NT, HALF = M / 2;
+  // butterflies j < M/32 (q < B16/2, or with one butterfly per thread the
+  // threads below NT/2) have all 16 outputs in the lower half
+#pragma unroll
+  for (int q = 0; q < B16; ++q) {
+    if constexpr (B16 >= 2) {
+      if ((q < B16 / 2) != (h == 0)) continue;
+    } else {
+      if ((tid < NT / 2) != (h == 0)) continue;
+    }
+    const int j = tid + q * NT, k = j & (Ns - 1);
+    const int d = (j - k) * 16 + k - h * HALF;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s[pad16(d + r * Ns)] = v[16 * q + 4 * (r & 3) + (r >> 2)];
+  }
+}
+
+template <typename T, int M, int NT>
 __device__ __forceinline__ void reg_xchg16(C2<T> *s, C2<T> (&v)[M / NT], int tid, int Ns) {
   constexpr int NB16 = M / 16, B16 = NB16 / NT, HALF = M / 2;
   C2<T> tmp[M / NT / 2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-#pragma unroll
-    for (int q = h * B16 / 2; q < (h + 1) * B16 / 2; ++q) {
-      const int j = tid + q * NT, k = j & (Ns - 1);
-      const int d = (j - k) * 16 + k - h * HALF;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) s[pad16(d + r * Ns)] = v[16 * q + 4 * (r & 3) + (r >> 2)];
-    }
+    reg_write16<T, M, NT>(s, v, tid, Ns, h);
     lds_barrier();
 #pragma unroll
     for (int q = 0; q < B16; ++q) {
@@ -464,15 +477,17 @@ __device__ __forceinline__ void reg_xchg16(C2<T> *s, C2<T> (&v)[M / NT], int tid
     for (int r = 0; r < 8; ++r) v[16 * q + r] = tmp[8 * q + r];
 }
 
-template <typename T, int M>
-__global__ void __launch_bounds__(kOsRegThreads, 2)
+// (the second launch bound is waves per SIMD: with 256 threads, two
+// workgroups per CU; 512-thread workgroups measured slower in both precisions)
+template <typename T, int M, int NT>
+__global__ void __launch_bounds__(NT, NT / 128)
 k_os_reg(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, int64_t nblk,
          const T *__restrict__ spec, int64_t spec_stride, const C2<double> *__restrict__ tw) {
-  constexpr int NT = kOsRegThreads;
   constexpr int RL = M / 4096;
   static_assert(RL == 2 || RL == 4, "M = 8192 or 16384");
   constexpr int L = 2 * M, HALF = M / 2, NB16 = M / 16, B16 = NB16 / NT, NPT = M / NT;
-  static_assert(NPT == 16 * RL, "8 butterfly pairs of the last forward pass per thread");
+  constexpr int NP = 2048 / NT;   // butterfly pairs of the last forward pass per thread
+  static_assert(B16 >= 1 && NPT == 2 * NP * RL, "whole butterflies per thread");
   __shared__ C2<T> s[HALF + HALF / 16];
   const int tid = threadIdx.x;
   const int64_t det = (int64_t)blockIdx.x / nblk, blk = (int64_t)blockIdx.x - det * nblk;
@@ -514,17 +529,11 @@ k_os_reg(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
     C2<T> tmp[NPT / 2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-#pragma unroll
-      for (int q = h * B16 / 2; q < (h + 1) * B16 / 2; ++q) {
-        const int j = tid + q * NT, k = j & 255;
-        const int d = (j - k) * 16 + k - h * HALF;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) s[pad16(d + r * 256)] = v[16 * q + 4 * (r & 3) + (r >> 2)];
-      }
+      reg_write16<T, M, NT>(s, v, tid, 256, h);
       lds_barrier();
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int j0 = tid + 256 * i;
+      for (int i = 0; i < NP; ++i) {
+        const int j0 = tid + NT * i;
         const int j1 = j0 == 0 ? 2048 : 4096 - j0;
 #pragma unroll
         for (int e = 0; e < 2; ++e)
@@ -538,7 +547,7 @@ k_os_reg(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
       lds_barrier();
     }
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < NP; ++i)
 #pragma unroll
       for (int e = 0; e < 2; ++e)
 #pragma unroll
@@ -548,8 +557,8 @@ k_os_reg(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
   // pass 0 (radix RL, span 1), all in registers
   const T *H = spec + det * spec_stride;   // H[0..M], already divided by M
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int j0 = tid + 256 * i;
+  for (int i = 0; i < NP; ++i) {
+    const int j0 = tid + NT * i;
     const int j1 = j0 == 0 ? 2048 : 4096 - j0;
     C2<T> Z[2][RL];
 #pragma unroll
@@ -609,8 +618,8 @@ k_os_reg(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int j0 = tid + 256 * i;
+      for (int i = 0; i < NP; ++i) {
+        const int j0 = tid + NT * i;
         const int j = h == 0 ? j0 : (j0 == 0 ? 2048 : 4096 - j0);
 #pragma unroll
         for (int r = 0; r < RL; ++r) s[pad16(RL * j + r - h * HALF)] = v[(2 * i + h) * RL + r];
@@ -808,7 +817,7 @@ static furax_status launch_os(const furax_noise *N, const T *in, T *out, const T
   return FURAX_OK;
 }
 
-template <typename T, int M>
+template <typename T, int M, int NT>
 static furax_status launch_os_reg(const furax_noise *N, const T *in, T *out, const T *spec,
                                   const C2<double> *tw, hipStream_t s) {
   const int b = (int)N->bandwidth;
@@ -818,7 +827,7 @@ static furax_status launch_os_reg(const furax_noise *N, const T *in, T *out, con
   const int64_t spec_stride = N->toeplitz_stride ? (M + 1) : 0;
   if (N->n_samp + 4 * (int64_t)M >= ((int64_t)1 << 31))   // 32-bit offsets inside the kernel
     return launch_os<T, M, M / 16>(N, in, out, spec, tw, s);
-  hipLaunchKernelGGL((k_os_reg<T, M>), dim3((unsigned)ntask), dim3(kOsRegThreads), 0, s, in, out,
+  hipLaunchKernelGGL((k_os_reg<T, M, NT>), dim3((unsigned)ntask), dim3(NT), 0, s, in, out,
                      N->n_samp, b, nblk, spec, spec_stride, tw);
   FX_HIP(hipGetLastError());
   return FURAX_OK;
@@ -847,7 +856,7 @@ furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *sp
     case 1024: return launch_os<T, 1024, 64>(N, in, out, sp, t, s);
     case 2048: return launch_os<T, 2048, 128>(N, in, out, sp, t, s);
     case 4096: return launch_os<T, 4096, 256>(N, in, out, sp, t, s);
-    case 8192: return launch_os_reg<T, 8192>(N, in, out, sp, t, s);
+    case 8192: return launch_os_reg<T, 8192, 256>(N, in, out, sp, t, s);
     case 16384:
       if constexpr (sizeof(T) == 4) return launch_os<T, 16384, 1024>(N, in, out, sp, t, s);
       break;
