@@ -154,7 +154,7 @@ class Problem:
     theta: np.ndarray
     phi: np.ndarray
     psi: np.ndarray
-    noise_kind: str                     # "diag" or "band"
+    noise_kind: str                     # "diag", "band" or "deproj" (templates)
     inv_var: np.ndarray | None = None   # [n_det] for "diag"
     lags: np.ndarray | None = None      # [b] or [n_det, b] for "band"
     gain: np.ndarray | None = None
@@ -162,6 +162,7 @@ class Problem:
     hwp: tuple | None = None            # (num, den, phase0)
     bore_quat: np.ndarray | None = None # [n_samp, 4]: quaternion pointing (theta/phi/psi None)
     det_quat: np.ndarray | None = None  # [n_det, 4]
+    tmpl: tuple | None = None           # (seg_len, order) for noise_kind "deproj" (Eq. (3))
 
     @property
     def npix(self):
@@ -182,7 +183,7 @@ class Problem:
         return pix, c, s
 
     def ninv(self, y):
-        return _noise.noise_apply(self.noise_kind, y, self.inv_var, self.lags)
+        return _noise.noise_apply(self.noise_kind, y, self.inv_var, self.lags, tmpl=self.tmpl)
 
     def wdiag(self):
         return _noise.diag_of_inverse(self.noise_kind, self.n_det, self.inv_var, self.lags)

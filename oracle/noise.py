@@ -83,17 +83,24 @@ def band_apply(tod, t, method: str = "auto") -> np.ndarray:
     return out
 
 
-def noise_apply(kind: str, tod, inv_var=None, t=None, method: str = "auto") -> np.ndarray:
+def noise_apply(kind: str, tod, inv_var=None, t=None, method: str = "auto",
+                tmpl=None) -> np.ndarray:
+    """The weight of the estimator: N^-1 ("diag", "band") or, with templates,
+    F_T of Eq. (3) with W = diag(inv_var) ("deproj", tmpl = (seg_len, order))."""
     if kind == "diag":
         return diag_apply(tod, inv_var)
     if kind == "band":
         return band_apply(tod, t, method)
+    if kind == "deproj":
+        from .templates import deproject_apply
+        return deproject_apply(tod, inv_var, tmpl[0], tmpl[1])
     raise ValueError(kind)
 
 
 def diag_of_inverse(kind: str, n_det: int, inv_var=None, t=None) -> np.ndarray:
-    """Per-detector diagonal of N^-1 (w_k, or t_k[0] for the band case)."""
-    if kind == "diag":
+    """Per-detector diagonal of the weight without templates (w_k, or t_k[0]
+    for the band case); the block-Jacobi preconditioner uses it."""
+    if kind in ("diag", "deproj"):
         return np.asarray(inv_var, dtype=np.float64)
     t = np.asarray(t, dtype=np.float64)
     return np.full(n_det, t[0]) if t.ndim == 1 else t[:, 0].copy()
