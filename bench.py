@@ -10,7 +10,10 @@ pointing/TOD, 1/f noise weighted by a band-Toeplitz of 4096 lags, ideal HWP at
 2 Hz.  The FP32 variant of the same workload (FP32 pointing, TOD and FFT,
 FP64 accumulation, dots and preconditioner) is measured beside it, and both
 again with boresight-quaternion pointing (the same scan given as one attitude
-per time sample and one per detector, expanded per sample in the kernels).
+per time sample and one per detector, expanded per sample in the kernels) and
+with template deprojection (the weight F_T of Eq. (3): white weights with
+Legendre baselines of degree 0..3 removed from every 4096-sample segment) in
+place of the band-Toeplitz N^-1.
 
 Prints one JSON line (rank 0).
 """
@@ -55,6 +58,11 @@ def make_inputs(w, dev):
     if w.noise == "band":
         lags = torch.from_numpy(synth.toeplitz_lags(w)).to(dev)
         N = fx.Noise("band", w.n_det, w.n_samp, lags=lags)
+    elif w.noise == "deproj":
+        N = fx.Noise("deproj", w.n_det, w.n_samp,
+                     inv_var=torch.full((w.n_det,), 1.0 / w.sigma ** 2, dtype=torch.float64,
+                                        device=dev),
+                     seg_len=w.tmpl_seg_len, order=w.tmpl_order)
     else:
         N = fx.Noise("diag", w.n_det, w.n_samp,
                      inv_var=torch.full((w.n_det,), 1.0 / w.sigma ** 2, dtype=torch.float64,
@@ -362,6 +370,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 variant")
     ap.add_argument("--no-quat", action="store_true",
                     help="skip the boresight-quaternion pointing variants")
+    ap.add_argument("--no-deproj", action="store_true",
+                    help="skip the template-deprojection variants")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-dets", type=int, default=64)
     ap.add_argument("--summarize-trace", metavar="DIR",
@@ -419,6 +429,15 @@ def main():
                               "ms_per_step": r["ms_per_step"], "kernels": r["kernels"],
                               "operator": r["operator"]}
 
+    deproj = {}
+    if not args.no_deproj:
+        for wd in ([w] + ([synth.WORKLOADS[3]] if fp32 is not None and args.config == 2 else [])):
+            r = measure(wd.with_(noise="deproj"), dev, args.steps, args.warmup)
+            deproj[wd.dtype] = {"workload": wd.name.replace(f"band{wd.bandwidth}",
+                                                            f"deproj{wd.tmpl_seg_len}o{wd.tmpl_order}"),
+                                "value": r["value"], "ms_per_step": r["ms_per_step"],
+                                "kernels": r["kernels"], "operator": r["operator"]}
+
     # the dominant operator kernel of the iteration
     name, k = max(((n, v) for n, v in primary["kernels"].items() if "alg_bytes" in v),
                   key=lambda kv: kv[1]["ms"])
@@ -459,6 +478,7 @@ def main():
             "kernels": fp32["kernels"], "operator": fp32["operator"],
             "speedup_vs_fp64": fp32["value"] / primary["value"]},
         "quat": quat or None,
+        "deproj": deproj or None,
         "host": host_info(),
     }
     print(json.dumps(line), flush=True)

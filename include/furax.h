@@ -109,20 +109,34 @@ typedef struct {
   const double *det_quat;  /* [n_det][4] (with bore_quat): detector attitudes        */
 } furax_pointing;
 
-/* N^-1, block-diagonal over detectors (BlockDiagonalOperator of Table 2).
+/* The weight of the estimator, block-diagonal over detectors
+ * (BlockDiagonalOperator of Table 2): N^-1, or with templates the weighting
+ * and deprojection operator F_T of Eq. (3).
  *  kind 0 (HomothetyOperator / DiagonalOperator): z[k,i] = inv_var[k] y[k,i].
  *  kind 1 (SymmetricBandToeplitzOperator): truncated linear convolution of each
  *     detector's stream with its symmetric band of lags t[0..b-1],
  *         z[k,i] = sum_{|tau| <= b-1, 0 <= i+tau < n_samp} t_k[|tau|] y[k,i+tau],
  *     applied by overlap-save blocks with a real FFT (the paper's overlap-save
- *     method).  FP32 streams support b <= 8192, FP64 streams b <= 4096. */
+ *     method).  FP32 streams support b <= 8192, FP64 streams b <= 4096.
+ *  kind 2 (template deprojection, Eq. (3) with TemplateOperator templates):
+ *         z = F_T y,  F_T = W - W T (T^T W T)^-1 T^T W,  W = diag(inv_var[k]),
+ *     where T holds, per detector and per segment of tmpl_seg_len samples
+ *     (the last segment running to the end of the stream, so segments have
+ *     tmpl_seg_len to 2 tmpl_seg_len - 1 samples, or the whole stream when it
+ *     is shorter), the Legendre polynomials P_0 .. P_tmpl_order of
+ *     x = (2 (i - i0) + 1) / len - 1.  F_T removes every baseline of that form
+ *     from each segment: z = w_k (y - T_s (T_s^T T_s)^-1 T_s^T y).  Needs
+ *     0 <= tmpl_order <= 7, tmpl_seg_len > tmpl_order and n_samp > tmpl_order.
+ *     The projections are accumulated in FP64 in both precisions. */
 typedef struct {
-  int32_t kind;            /* 0 = diagonal, 1 = symmetric band-Toeplitz              */
+  int32_t kind;            /* 0 diagonal, 1 symmetric band-Toeplitz, 2 template deprojection */
   int64_t n_det, n_samp;   /* must equal the pointing's when used together           */
-  const double *inv_var;   /* kind 0: [n_det]                                        */
+  const double *inv_var;   /* kinds 0 and 2: [n_det]                                 */
   int64_t bandwidth;       /* kind 1: b >= 1 lags                                    */
   const double *toeplitz;  /* kind 1: [1][b] (stride 0) or [n_det][b] (stride b)     */
   int64_t toeplitz_stride; /* 0: one kernel shared by all detectors; b: per detector */
+  int64_t tmpl_seg_len;    /* kind 2: samples per template segment                   */
+  int32_t tmpl_order;      /* kind 2: highest Legendre degree of the baselines       */
 } furax_noise;
 
 /* HEALPix ring-scheme pixel of each direction (Landscape types, section
@@ -156,7 +170,8 @@ furax_status furax_noise_apply(const furax_noise *N, int32_t dt, const void *tod
 
 /* Block-Jacobi preconditioner ("BJPreconditioner", "Map-making classes"):
  * per-pixel 3x3 blocks of P^T diag(N^-1) P, where diag(N^-1) is inv_var[k]
- * (kind 0) or t_k[0] (kind 1).
+ * (kinds 0 and 2: the weight without its template projection) or t_k[0]
+ * (kind 1).
  *   M6:   [6][npix] FP64 out: entries II, IQ, IU, QQ, QU, UU.
  *   hits: [npix] int32 out: unflagged samples per pixel (exact).
  * furax_bj_invert then writes Minv6 [6][npix] and valid [npix] (1 iff

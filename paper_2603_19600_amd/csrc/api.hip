@@ -76,7 +76,19 @@ furax_status check_noise(const furax_noise *N, int64_t n_det, int64_t n_samp, in
     if (!N->inv_var) return set_error(FURAX_EINVAL, "diagonal noise needs inv_var");
     return FURAX_OK;
   }
-  if (N->kind != 1) return set_error(FURAX_EINVAL, "noise kind must be 0 or 1");
+  if (N->kind == 2) {
+    if (!N->inv_var) return set_error(FURAX_EINVAL, "template deprojection needs inv_var");
+    if (N->tmpl_order < 0 || N->tmpl_order > kMaxTmplOrder)
+      return set_error(FURAX_EINVAL, "tmpl_order must be in [0, 7]");
+    if (N->tmpl_seg_len <= N->tmpl_order)
+      return set_error(FURAX_EINVAL, "tmpl_seg_len must exceed tmpl_order");
+    if (N->n_samp > 0 && N->n_samp <= N->tmpl_order)
+      return set_error(FURAX_EINVAL, "a stream needs more samples than tmpl_order");
+    if (N->n_det * std::max<int64_t>(1, N->n_samp / N->tmpl_seg_len) > 0x7fffffffLL)
+      return set_error(FURAX_EINVAL, "too many template segments for one launch");
+    return FURAX_OK;
+  }
+  if (N->kind != 1) return set_error(FURAX_EINVAL, "noise kind must be 0, 1 or 2");
   if (!N->toeplitz) return set_error(FURAX_EINVAL, "band noise needs toeplitz lags");
   if (N->bandwidth < 1) return set_error(FURAX_EINVAL, "bandwidth must be >= 1");
   if (N->bandwidth > n_samp && n_samp > 0)

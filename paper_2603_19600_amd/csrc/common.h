@@ -12,6 +12,7 @@ namespace fx {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kMaxNside = 8192;
+constexpr int kMaxTmplOrder = 7;   // highest Legendre degree of the deprojected baselines
 
 // ---------------------------------------------------------------------------
 // Host-side status plumbing.

@@ -244,7 +244,7 @@ static NormalLayout normal_layout(const furax_pointing *P, const furax_noise *N)
   const size_t tod = (size_t)P->n_det * P->n_samp * sizeof(T);
   const int64_t npix = npix_of(P->nside);
   L.wdet = off; off += align256(sizeof(double) * P->n_det);
-  if (N->kind == 1) {
+  if (N->kind != 0) {   // band N^-1 or F_T: P, the weight and P^T as separate kernels
     L.spec = off; off += align256(noise_workspace_bytes<T>(N));
     L.y = off; off += align256(tod);
     L.z = off; off += align256(tod);
@@ -279,7 +279,7 @@ static furax_status normal_prepare(NormalPlan<T> &pl, hipStream_t s) {
   const furax_noise *N = pl.N;
   double *w = reinterpret_cast<double *>(pl.work + pl.L.wdet);
   hipLaunchKernelGGL(k_diag_weights, dim3((unsigned)((pl.P->n_det + 255) / 256)), dim3(256), 0, s,
-                     pl.P->n_det, N->kind == 0 ? N->inv_var : nullptr,
+                     pl.P->n_det, N->kind != 1 ? N->inv_var : nullptr,
                      N->kind == 1 ? N->toeplitz : nullptr, N->toeplitz_stride, w);
   FX_HIP(hipGetLastError());
   if (N->kind == 1) FX_TRY(noise_prepare<T>(N, pl.work + pl.L.spec, s));
@@ -399,7 +399,7 @@ furax_status normal_apply_impl(const furax_pointing *P, const furax_noise *N, co
   pl.a = pt_args<T>(P, nullptr);
   pl.L = normal_layout<T>(P, N);
   pl.npix = npix_of(P->nside);
-  pl.use_sp = N->kind == 1 && pl.L.local != 0;
+  pl.use_sp = N->kind != 0 && pl.L.local != 0;
   DevBuf own;
   if (!work) {
     FX_TRY(own.alloc(pl.L.total, s));
@@ -440,7 +440,7 @@ furax_status bj_build_impl(const furax_pointing *P, const furax_noise *N, double
   FX_TRY(wbuf.alloc(sizeof(double) * P->n_det, s));
   double *w = static_cast<double *>(wbuf.ptr);
   hipLaunchKernelGGL(k_diag_weights, dim3((unsigned)((P->n_det + 255) / 256)), dim3(256), 0, s,
-                     P->n_det, N->kind == 0 ? N->inv_var : nullptr,
+                     P->n_det, N->kind != 1 ? N->inv_var : nullptr,
                      N->kind == 1 ? N->toeplitz : nullptr, N->toeplitz_stride, w);
   FX_HIP(hipGetLastError());
   FX_TRY(zero_async(M6, sizeof(double) * 6 * npix, s));
@@ -541,7 +541,7 @@ static furax_status pcg_setup(furax_pcg_state *h, const void *tod) {
   if (pl.use_sp) {
     // superpixel plan (kept for the iterations) and the blocks on the way
     FX_TRY(sp_prepare<T>(pl, w, M6, hits, &nest_plane, s));
-    pl.use_sp = h->N.kind == 1 && pl.L.local != 0;
+    pl.use_sp = h->N.kind != 0 && pl.L.local != 0;
   } else {
     FX_TRY(zero_async(M6, sizeof(double) * 6 * npix, s));
     FX_TRY(zero_async(hits, sizeof(int32_t) * npix, s));
@@ -558,7 +558,7 @@ static furax_status pcg_setup(furax_pcg_state *h, const void *tod) {
   const T *d = static_cast<const T *>(tod);
   const T *zt = d;
   const double *wd = w;
-  if (h->N.kind == 1) {
+  if (h->N.kind != 0) {
     T *zbuf = reinterpret_cast<T *>(pl.work + pl.L.z);
     FX_TRY(noise_run<T>(&h->N, d, zbuf, pl.work + pl.L.spec, s));
     zt = zbuf;

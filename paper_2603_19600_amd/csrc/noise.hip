@@ -833,7 +833,169 @@ static furax_status launch_os_reg(const furax_noise *N, const T *in, T *out, con
   return FURAX_OK;
 }
 
-// Apply N^-1 given a prepared spectrum (kind 1) or the diagonal weights (kind 0).
+// ---------------------------------------------------------------------------
+// Template deprojection F_T = W - W T (T^T W T)^-1 T^T W (Eq. (3)) with
+// W = w_k I and T the Legendre baselines P_0 .. P_{NP-1} of each segment:
+//   z = w_k (y - T_s G^-1 T_s^T y),  G = T_s^T T_s.
+// One workgroup per (detector, segment).  Pass 1 accumulates, in FP64, the
+// projections T_s^T y and the Gram matrix G (upper triangle) over the
+// segment's samples; the partial sums are combined in a fixed order (wave
+// shuffles, then the waves in order), and one thread solves G c = T_s^T y by
+// Cholesky.  Pass 2 re-reads the segment (L2-resident) and writes
+// w_k (y - sum_j c_j P_j).  The Gram sums are recomputed per segment: they cost
+// arithmetic only, the kernel is bound by its two TOD streams.
+// ---------------------------------------------------------------------------
+constexpr int kDeprojThreads = 256;
+
+template <int NP>
+__device__ __forceinline__ void legendre_at(double x, double (&P)[NP]) {
+#pragma clang fp contract(off)
+  P[0] = 1.0;
+  if constexpr (NP > 1) P[1] = x;
+#pragma unroll
+  for (int j = 1; j + 1 < NP; ++j)
+    P[j + 1] = ((double)(2 * j + 1) * x * P[j] - (double)j * P[j - 1]) / (double)(j + 1);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+template <typename T, int NP>
+__global__ void __launch_bounds__(kDeprojThreads) k_deproject(const T *__restrict__ in,
+                                                              T *__restrict__ out, int64_t n,
+                                                              int64_t seg_len, int64_t nseg,
+                                                              const double *__restrict__ w) {
+#pragma clang fp contract(off)
+  constexpr int NG = NP * (NP + 1) / 2;
+  constexpr int NV = NP + NG;
+  constexpr int NW = kDeprojThreads / 64;
+  __shared__ double part[NW][NV];
+  __shared__ double coef[NP];
+  const int64_t det = (int64_t)blockIdx.x / nseg, seg = (int64_t)blockIdx.x - det * nseg;
+  const int64_t i0 = seg * seg_len;
+  const int64_t len = seg + 1 < nseg ? seg_len : n - i0;
+  const T *y = in + det * n + i0;
+  T *z = out + det * n + i0;
+  const double dlen = (double)len;
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  for (int64_t i = threadIdx.x; i < len; i += kDeprojThreads) {
+    double P[NP];
+    legendre_at<NP>((2.0 * (double)i + 1.0) / dlen - 1.0, P);
+    const double yi = (double)y[i];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) acc[j] += P[j] * yi;
+    int g = NP;
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int l = j; l < NP; ++l) acc[g++] += P[j] * P[l];
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double t = wave_sum(acc[v]);
+    if (lane == 0) part[wave][v] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      r[v] = part[0][v];
+#pragma unroll
+      for (int q = 1; q < NW; ++q) r[v] += part[q][v];
+    }
+    // G = L L^T (G[j][l] = r[NP + idx(j, l)], upper triangle by rows), then
+    // forward and back substitution for c
+    double Lm[NP][NP];
+    int g = NP;
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int l = j; l < NP; ++l) {
+        Lm[l][j] = r[g];   // lower triangle holds G
+        ++g;
+      }
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      double d = Lm[j][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) d -= Lm[j][k] * Lm[j][k];
+      d = sqrt(d);
+      Lm[j][j] = d;
+#pragma unroll
+      for (int l = j + 1; l < NP; ++l) {
+        double v = Lm[l][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) v -= Lm[l][k] * Lm[j][k];
+        Lm[l][j] = v / d;
+      }
+    }
+    double c[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      double v = r[j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= Lm[j][k] * c[k];
+      c[j] = v / Lm[j][j];
+    }
+#pragma unroll
+    for (int j = NP - 1; j >= 0; --j) {
+      double v = c[j];
+#pragma unroll
+      for (int k = j + 1; k < NP; ++k) v -= Lm[k][j] * c[k];
+      c[j] = v / Lm[j][j];
+    }
+#pragma unroll
+    for (int j = 0; j < NP; ++j) coef[j] = c[j];
+  }
+  __syncthreads();
+  double c[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) c[j] = coef[j];
+  const double wk = w[det];
+  for (int64_t i = threadIdx.x; i < len; i += kDeprojThreads) {
+    double P[NP];
+    legendre_at<NP>((2.0 * (double)i + 1.0) / dlen - 1.0, P);
+    double fit = 0.0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) fit += c[j] * P[j];
+    z[i] = (T)(wk * ((double)y[i] - fit));
+  }
+}
+
+template <typename T, int NP>
+static furax_status launch_deproject_np(const furax_noise *N, const T *in, T *out, hipStream_t s) {
+  const int64_t nseg = std::max<int64_t>(1, N->n_samp / N->tmpl_seg_len);
+  hipLaunchKernelGGL((k_deproject<T, NP>), dim3((unsigned)(N->n_det * nseg)),
+                     dim3(kDeprojThreads), 0, s, in, out, N->n_samp, N->tmpl_seg_len, nseg,
+                     N->inv_var);
+  FX_HIP(hipGetLastError());
+  return FURAX_OK;
+}
+
+template <typename T>
+static furax_status launch_deproject(const furax_noise *N, const T *in, T *out, hipStream_t s) {
+  switch (N->tmpl_order) {
+    case 0: return launch_deproject_np<T, 1>(N, in, out, s);
+    case 1: return launch_deproject_np<T, 2>(N, in, out, s);
+    case 2: return launch_deproject_np<T, 3>(N, in, out, s);
+    case 3: return launch_deproject_np<T, 4>(N, in, out, s);
+    case 4: return launch_deproject_np<T, 5>(N, in, out, s);
+    case 5: return launch_deproject_np<T, 6>(N, in, out, s);
+    case 6: return launch_deproject_np<T, 7>(N, in, out, s);
+    case 7: return launch_deproject_np<T, 8>(N, in, out, s);
+  }
+  return set_error(FURAX_EINVAL, "tmpl_order must be in [0, 7]");
+}
+
+// Apply the weight: N^-1 given a prepared spectrum (kind 1) or the diagonal
+// weights (kind 0), or the template deprojection F_T (kind 2).
 template <typename T>
 furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *spec,
                        hipStream_t s) {
@@ -846,6 +1008,7 @@ furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *sp
     FX_HIP(hipGetLastError());
     return FURAX_OK;
   }
+  if (N->kind == 2) return launch_deproject<T>(N, in, out, s);
   const int M = os_half_length<T>(N->bandwidth);
   TwTables tw;
   FX_TRY(get_twiddles(2 * M, s, tw));

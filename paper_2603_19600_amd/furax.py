@@ -41,7 +41,8 @@ class _Pointing(C.Structure):
 class _Noise(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_det", C.c_int64), ("n_samp", C.c_int64),
                 ("inv_var", C.c_void_p), ("bandwidth", C.c_int64), ("toeplitz", C.c_void_p),
-                ("toeplitz_stride", C.c_int64)]
+                ("toeplitz_stride", C.c_int64), ("tmpl_seg_len", C.c_int64),
+                ("tmpl_order", C.c_int32)]
 
 
 class _PcgOpts(C.Structure):
@@ -273,24 +274,32 @@ class QuatPointing:
 
 @dataclass
 class Noise:
-    """N^-1: kind "diag" with inv_var [n_det], or "band" with lags [b] or [n_det, b]."""
+    """The estimator's weight (see furax_noise): kind "diag" with inv_var [n_det];
+    "band" with lags [b] or [n_det, b]; "deproj" (template deprojection F_T of
+    Eq. (3)) with inv_var [n_det], seg_len and order of the Legendre baselines."""
     kind: str
     n_det: int
     n_samp: int
     inv_var: Optional[torch.Tensor] = None
     lags: Optional[torch.Tensor] = None
+    seg_len: int = 0
+    order: int = 0
 
     def c(self) -> _Noise:
         if self.kind == "diag":
             _dev(self.inv_var, "inv_var", torch.float64, (self.n_det,))
-            return _Noise(0, self.n_det, self.n_samp, _ptr(self.inv_var), 0, None, 0)
+            return _Noise(0, self.n_det, self.n_samp, _ptr(self.inv_var), 0, None, 0, 0, 0)
         if self.kind == "band":
             _dev(self.lags, "lags", torch.float64)
             b = self.lags.shape[-1]
             stride = 0 if self.lags.dim() == 1 else b
             if self.lags.dim() == 2 and self.lags.shape[0] != self.n_det:
                 raise ValueError("per-detector lags must be [n_det, b]")
-            return _Noise(1, self.n_det, self.n_samp, None, b, _ptr(self.lags), stride)
+            return _Noise(1, self.n_det, self.n_samp, None, b, _ptr(self.lags), stride, 0, 0)
+        if self.kind == "deproj":
+            _dev(self.inv_var, "inv_var", torch.float64, (self.n_det,))
+            return _Noise(2, self.n_det, self.n_samp, _ptr(self.inv_var), 0, None, 0,
+                          int(self.seg_len), int(self.order))
         raise ValueError(f"unknown noise kind {self.kind!r}")
 
 

@@ -105,11 +105,14 @@ class Workload:
     nside: int
     n_det: int
     n_samp: int
-    noise: str                    # "diag" (white) or "band" (1/f, band-Toeplitz inverse)
+    noise: str                    # "diag" (white), "band" (1/f, band-Toeplitz inverse) or
+                                  # "deproj" (white weights with template deprojection)
     bandwidth: int = 1            # number of Toeplitz lags t[0..b-1]
     hwp: bool = False
     dtype: str = "f64"            # canonical pointing / TOD dtype: "f64" or "f32"
     pointing: str = "angles"      # "angles": theta/phi/psi planes; "quat": boresight quaternions
+    tmpl_seg_len: int = 4096      # noise "deproj": baseline segments of ~82 s at 50 Hz
+    tmpl_order: int = 3           # noise "deproj": Legendre degrees 0..3 per segment
     iters: int = 20
     offsets_deg: float = 1.0      # detector offsets uniform in +-offsets_deg (0: boresight)
     fs: float = 50.0              # sampling rate [Hz]

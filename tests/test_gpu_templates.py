@@ -1,0 +1,119 @@
+"""GPU parity of template deprojection (the weight F_T of Eq. (3), noise kind 2)
+against the FP64 oracle: the operator itself (ragged last segments, a stream
+shorter than one segment, every supported order, in place), the normal
+operator P^T F_T P on both transpose paths, PCG, and the recovery of a map
+from noiseless data that carries template signals."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mapmaker as omm
+from oracle import pointing as opt
+from oracle import templates as otp
+from paper_2603_19600_amd import synth
+from tests.gpu_util import case, dev, rel_err, to_pointing
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fx():
+    from paper_2603_19600_amd import furax
+    return furax
+
+
+@pytest.mark.parametrize("n_det,n_samp,seg_len,order", [
+    (3, 5000, 1000, 3), (2, 4097, 1000, 0), (2, 300, 1000, 2), (2, 70001, 16384, 7),
+    (4, 13, 5, 3), (1, 20000, 333, 5)])
+@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-12), (np.float32, 2e-6)])
+def test_deprojection_operator(fx, n_det, n_samp, seg_len, order, dtype, tol):
+    rng = np.random.default_rng(n_samp + order)
+    y = rng.standard_normal((n_det, n_samp)).astype(dtype)
+    w = rng.uniform(0.5, 2.0, n_det)
+    ref = otp.deproject_apply(y.astype(np.float64), w, seg_len, order)
+    N = fx.Noise("deproj", n_det, n_samp, inv_var=torch.from_numpy(w).to(dev()), seg_len=seg_len,
+                 order=order)
+    got = fx.noise_apply(N, torch.from_numpy(y).to(dev())).cpu().numpy()
+    assert rel_err(got, ref) <= tol
+
+
+def test_deprojection_in_place_and_annihilates_templates(fx):
+    n_det, n_samp, seg_len, order = 3, 50_000, 4096, 4
+    w = np.array([1.0, 0.5, 2.0])
+    amp = np.random.default_rng(2).standard_normal((n_det, n_samp // seg_len, order + 1))
+    Tt = otp.template_signal(amp, n_samp, seg_len, order)
+    N = fx.Noise("deproj", n_det, n_samp, inv_var=torch.from_numpy(w).to(dev()), seg_len=seg_len,
+                 order=order)
+    t = torch.from_numpy(Tt).to(dev())
+    out = fx.noise_apply(N, t)
+    assert float(out.abs().max()) < 1e-10 * float(t.abs().max())
+    y = torch.randn(n_det, n_samp, dtype=torch.float64, device=dev())
+    ref = fx.noise_apply(N, y)
+    st = fx._lib.furax_noise_apply(fx.C.byref(N.c()), fx.F64, fx._ptr(y), fx._ptr(y), None)
+    assert st == fx.OK
+    torch.cuda.synchronize()
+    assert torch.equal(y, ref)
+
+
+def _problem(fx, nside, nd, ns, seg_len, order, dtype="f64", seed=7, sphere=False):
+    w, h, t = case(nside, nd, ns, dtype=dtype, seed=seed, sphere=sphere)
+    P = to_pointing(nside, t)
+    iv = np.linspace(0.5, 2.0, nd)
+    N = fx.Noise("deproj", nd, ns, inv_var=torch.from_numpy(iv).to(dev()), seg_len=seg_len,
+                 order=order)
+    prob = omm.Problem(nside, h["theta"], h["phi"], h["psi"], "deproj", inv_var=iv,
+                       gain=h["gain"], dpsi=h["dpsi"], hwp=h["hwp"], tmpl=(seg_len, order))
+    return w, P, N, prob
+
+
+@pytest.mark.parametrize("nside", [64, 7])       # superpixel and LDS-hash transposes
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_normal_operator_with_deprojection(fx, nside, dtype, tol):
+    w, P, N, prob = _problem(fx, nside, 5, 40_000, 3000, 3, dtype=dtype)
+    g = torch.Generator(device=dev()).manual_seed(4)
+    x = torch.randn(3, P.npix, dtype=torch.float64, device=dev(), generator=g)
+    got = fx.normal_apply(P, N, x).cpu().numpy()
+    pix, c, s = prob.geometry()
+    ref = omm.normal_apply(prob, pix, c, s, x.cpu().numpy())
+    assert rel_err(got, ref) <= tol
+
+
+def test_pcg_with_deprojection_matches_oracle(fx):
+    w, P, N, prob = _problem(fx, 16, 4, 30_000, 2000, 2)
+    pix, c, s = prob.geometry()
+    d = opt.apply_pix(pix, c, s, synth.sky_map(w).numpy(), prob.gain) + \
+        synth.noise(w.with_(noise="diag")).numpy()
+    ref = omm.pcg_mapmake(prob, d, max_iter=12, rtol=0.0)
+    x, valid, info, _ = fx.pcg_mapmake(P, N, torch.from_numpy(d).to(dev()), max_iter=12,
+                                       rtol=0.0, valid_in=torch.from_numpy(
+                                           ref.valid.astype(np.uint8)).to(dev()))
+    assert info.iters == ref.iters
+    assert rel_err(x.cpu().numpy(), ref.x) <= 1e-10
+
+
+def test_map_recovered_from_data_with_template_signals(fx):
+    """d = P m + T t with large baselines: the deprojected solve returns m up to
+    the I monopole (which offsets cannot distinguish from the sky)."""
+    w, P, N, prob = _problem(fx, 8, 6, 60_000, 5000, 3, sphere=True)
+    pix, c, s = prob.geometry()
+    rng = np.random.default_rng(8)
+    m = synth.sky_map(w).numpy()
+    amp = 20.0 * rng.standard_normal((6, 12, 4))
+    d = opt.apply_pix(pix, c, s, m, prob.gain) + otp.template_signal(amp, 60_000, 5000, 3)
+    x, valid, info, _ = fx.pcg_mapmake(P, N, torch.from_numpy(d).to(dev()), max_iter=300,
+                                       rtol=1e-12)
+    v = valid.cpu().numpy().astype(bool)
+    assert v.mean() > 0.95
+    err = x.cpu().numpy()[:, v] - m[:, v]
+    assert np.abs(err[0] - err[0].mean()).max() < 1e-7
+    assert np.abs(err[1:]).max() < 1e-7
+
+
+def test_deprojection_argument_errors(fx):
+    iv = torch.ones(2, dtype=torch.float64, device=dev())
+    y = torch.zeros(2, 100, dtype=torch.float64, device=dev())
+    for seg_len, order, n in ((100, 8, 100), (3, 3, 100), (100, 3, 3)):
+        N = fx.Noise("deproj", 2, n, inv_var=iv, seg_len=seg_len, order=order)
+        with pytest.raises(fx.FuraxError) as e:
+            fx.noise_apply(N, y[:, :n].contiguous())
+        assert e.value.status == fx.EINVAL
