@@ -298,6 +298,14 @@ furax_status furax_pointing_vjp(const furax_pointing *P, int32_t map_dt, const v
                                 const void *tod_cot, double *grad_map, double *grad_gain,
                                 double *grad_dpsi, hipStream_t stream);
 
+/* Template fit of a noise model of kind 2 (TemplateOperator, Eq. (1)/(3)):
+ * the amplitudes t = (T^T W T)^-1 T^T W y of every detector's and segment's
+ * Legendre baselines, e.g. of the residual d - P m after a solve.
+ *   tod: [n_det][n_samp] of dtype dt.  amp: [n_det][n_seg][tmpl_order + 1]
+ *   FP64 out, n_seg = max(1, n_samp / tmpl_seg_len) (segments as for F_T). */
+furax_status furax_template_fit(const furax_noise *N, int32_t dt, const void *tod, double *amp,
+                                hipStream_t stream);
+
 /* Thread-local description of the last non-OK status (never NULL). */
 const char *furax_last_error(void);
 /* Frees the library's per-device FFT twiddle tables (rebuilt on demand). */

@@ -200,6 +200,18 @@ furax_status furax_pointing_transpose(const furax_pointing *P, int32_t tod_dt, c
                                 planar_layout(npix_of(P->nside)), stream);
 }
 
+furax_status furax_template_fit(const furax_noise *N, int32_t dt, const void *tod, double *amp,
+                                hipStream_t stream) {
+  if (!N) return set_error(FURAX_EINVAL, "noise descriptor is NULL");
+  if (!dtype_ok(dt)) return set_error(FURAX_EINVAL, "bad dtype");
+  FX_TRY(check_noise(N, N->n_det, N->n_samp, dt));
+  if (N->kind != 2) return set_error(FURAX_EINVAL, "template fit needs a noise model of kind 2");
+  if (N->n_samp > 0 && (!tod || !amp)) return set_error(FURAX_EINVAL, "NULL tod or amp");
+  if (dt == FURAX_F32)
+    return launch_deproject<float>(N, static_cast<const float *>(tod), nullptr, amp, stream);
+  return launch_deproject<double>(N, static_cast<const double *>(tod), nullptr, amp, stream);
+}
+
 furax_status furax_noise_apply(const furax_noise *N, int32_t dt, const void *tod_in,
                                void *tod_out, hipStream_t stream) {
   if (!N) return set_error(FURAX_EINVAL, "noise descriptor is NULL");

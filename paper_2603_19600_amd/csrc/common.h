@@ -411,6 +411,9 @@ furax_status launch_noise(const furax_noise *N, const T *in, T *out, void *work,
                           size_t work_bytes, hipStream_t s);
 template <typename T>
 size_t noise_workspace_bytes(const furax_noise *N);
+template <typename T>
+furax_status launch_deproject(const furax_noise *N, const T *in, T *out, double *amp,
+                              hipStream_t s);
 
 furax_status zero_async(void *ptr, size_t bytes, hipStream_t s);
 

@@ -867,7 +867,8 @@ template <typename T, int NP>
 __global__ void __launch_bounds__(kDeprojThreads) k_deproject(const T *__restrict__ in,
                                                               T *__restrict__ out, int64_t n,
                                                               int64_t seg_len, int64_t nseg,
-                                                              const double *__restrict__ w) {
+                                                              const double *__restrict__ w,
+                                                              double *__restrict__ amp) {
 #pragma clang fp contract(off)
   constexpr int NG = NP * (NP + 1) / 2;
   constexpr int NV = NP + NG;
@@ -953,7 +954,12 @@ __global__ void __launch_bounds__(kDeprojThreads) k_deproject(const T *__restric
     }
 #pragma unroll
     for (int j = 0; j < NP; ++j) coef[j] = c[j];
+    if (amp) {   // the template fit (T^T W T)^-1 T^T W y of this segment (w cancels)
+#pragma unroll
+      for (int j = 0; j < NP; ++j) amp[(int64_t)blockIdx.x * NP + j] = c[j];
+    }
   }
+  if (!out) return;   // amplitudes only (uniform over the workgroup)
   __syncthreads();
   double c[NP];
 #pragma unroll
@@ -970,29 +976,38 @@ __global__ void __launch_bounds__(kDeprojThreads) k_deproject(const T *__restric
 }
 
 template <typename T, int NP>
-static furax_status launch_deproject_np(const furax_noise *N, const T *in, T *out, hipStream_t s) {
+static furax_status launch_deproject_np(const furax_noise *N, const T *in, T *out, double *amp,
+                                        hipStream_t s) {
   const int64_t nseg = std::max<int64_t>(1, N->n_samp / N->tmpl_seg_len);
   hipLaunchKernelGGL((k_deproject<T, NP>), dim3((unsigned)(N->n_det * nseg)),
                      dim3(kDeprojThreads), 0, s, in, out, N->n_samp, N->tmpl_seg_len, nseg,
-                     N->inv_var);
+                     N->inv_var, amp);
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }
 
+// out = F_T in (out may be null: amplitudes only); amp [n_det][n_seg][order + 1]
+// receives the template fit of each segment when not null.
 template <typename T>
-static furax_status launch_deproject(const furax_noise *N, const T *in, T *out, hipStream_t s) {
+furax_status launch_deproject(const furax_noise *N, const T *in, T *out, double *amp,
+                              hipStream_t s) {
+  if (N->n_samp == 0) return FURAX_OK;
   switch (N->tmpl_order) {
-    case 0: return launch_deproject_np<T, 1>(N, in, out, s);
-    case 1: return launch_deproject_np<T, 2>(N, in, out, s);
-    case 2: return launch_deproject_np<T, 3>(N, in, out, s);
-    case 3: return launch_deproject_np<T, 4>(N, in, out, s);
-    case 4: return launch_deproject_np<T, 5>(N, in, out, s);
-    case 5: return launch_deproject_np<T, 6>(N, in, out, s);
-    case 6: return launch_deproject_np<T, 7>(N, in, out, s);
-    case 7: return launch_deproject_np<T, 8>(N, in, out, s);
+    case 0: return launch_deproject_np<T, 1>(N, in, out, amp, s);
+    case 1: return launch_deproject_np<T, 2>(N, in, out, amp, s);
+    case 2: return launch_deproject_np<T, 3>(N, in, out, amp, s);
+    case 3: return launch_deproject_np<T, 4>(N, in, out, amp, s);
+    case 4: return launch_deproject_np<T, 5>(N, in, out, amp, s);
+    case 5: return launch_deproject_np<T, 6>(N, in, out, amp, s);
+    case 6: return launch_deproject_np<T, 7>(N, in, out, amp, s);
+    case 7: return launch_deproject_np<T, 8>(N, in, out, amp, s);
   }
   return set_error(FURAX_EINVAL, "tmpl_order must be in [0, 7]");
 }
+template furax_status launch_deproject<float>(const furax_noise *, const float *, float *, double *,
+                                              hipStream_t);
+template furax_status launch_deproject<double>(const furax_noise *, const double *, double *,
+                                               double *, hipStream_t);
 
 // Apply the weight: N^-1 given a prepared spectrum (kind 1) or the diagonal
 // weights (kind 0), or the template deprojection F_T (kind 2).
@@ -1008,7 +1023,7 @@ furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *sp
     FX_HIP(hipGetLastError());
     return FURAX_OK;
   }
-  if (N->kind == 2) return launch_deproject<T>(N, in, out, s);
+  if (N->kind == 2) return launch_deproject<T>(N, in, out, nullptr, s);
   const int M = os_half_length<T>(N->bandwidth);
   TwTables tw;
   FX_TRY(get_twiddles(2 * M, s, tw));

@@ -73,6 +73,7 @@ def _load() -> C.CDLL:
         "furax_pointing_apply": [P, i32, vp, i32, vp, vp],
         "furax_pointing_transpose": [P, i32, vp, vp, i32, vp],
         "furax_noise_apply": [N, i32, vp, vp, vp],
+        "furax_template_fit": [N, i32, vp, vp, vp],
         "furax_bj_build": [P, N, vp, vp, vp],
         "furax_bj_invert": [i64, vp, vp, dbl, i32, vp, vp, vp, vp],
         "furax_normal_workspace_bytes": [P, N, i32],
@@ -104,7 +105,7 @@ _lib = _load()
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = ("furax_ang2pix", "furax_pointing_apply", "furax_pointing_transpose",
-           "furax_noise_apply", "furax_bj_build", "furax_bj_invert",
+           "furax_noise_apply", "furax_template_fit", "furax_bj_build", "furax_bj_invert",
            "furax_normal_workspace_bytes", "furax_normal_apply", "furax_pcg_mapmake",
            "furax_pcg_create", "furax_pcg_iterate", "furax_pcg_finish", "furax_pcg_destroy",
            "furax_pcg_set_timing", "furax_pcg_read_timing",
@@ -345,6 +346,18 @@ def noise_apply(N: Noise, tod: torch.Tensor, out: Optional[torch.Tensor] = None)
     _check(_lib.furax_noise_apply(C.byref(c), _dt(tod), _ptr(tod), _ptr(out),
                                   _stream(tod.device)))
     return out
+
+
+def template_fit(N: Noise, tod: torch.Tensor) -> torch.Tensor:
+    """Template amplitudes (T^T W T)^-1 T^T W y of a "deproj" noise model's
+    baselines: [n_det, n_seg, order + 1] float64."""
+    _dev(tod, "tod", None, (N.n_det, N.n_samp))
+    nseg = max(1, N.n_samp // N.seg_len) if N.seg_len > 0 else 1
+    amp = torch.empty(N.n_det, nseg, N.order + 1, dtype=torch.float64, device=tod.device)
+    c = N.c()
+    _check(_lib.furax_template_fit(C.byref(c), _dt(tod), _ptr(tod), _ptr(amp),
+                                   _stream(tod.device)))
+    return amp
 
 
 def bj_build(P: Pointing, N: Noise):

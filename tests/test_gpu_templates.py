@@ -117,3 +117,20 @@ def test_deprojection_argument_errors(fx):
         with pytest.raises(fx.FuraxError) as e:
             fx.noise_apply(N, y[:, :n].contiguous())
         assert e.value.status == fx.EINVAL
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-12), (np.float32, 2e-6)])
+def test_template_fit(fx, dtype, tol):
+    rng = np.random.default_rng(9)
+    n_det, n_samp, seg_len, order = 3, 30_001, 4000, 4
+    amp = rng.standard_normal((n_det, n_samp // seg_len, order + 1))
+    y = (otp.template_signal(amp, n_samp, seg_len, order)
+         + 0.1 * rng.standard_normal((n_det, n_samp))).astype(dtype)
+    w = np.array([1.0, 0.3, 3.0])
+    N = fx.Noise("deproj", n_det, n_samp, inv_var=torch.from_numpy(w).to(dev()), seg_len=seg_len,
+                 order=order)
+    got = fx.template_fit(N, torch.from_numpy(y).to(dev())).cpu().numpy()
+    ref = otp.template_amplitudes(y.astype(np.float64), w, seg_len, order)
+    assert got.shape == ref.shape
+    assert rel_err(got, ref) <= tol
+    assert np.abs(got - amp).max() < 0.05          # the fit finds the planted baselines
