@@ -69,6 +69,7 @@ SUB_PSI = 0
 SUB_OFFSET = 1
 SUB_NOISE = 2
 SUB_GAIN = 3
+SUB_GAPS = 4
 
 
 def stream_key(seed: int, stream: int, sub: int = 0) -> int:
@@ -347,6 +348,41 @@ def toeplitz_lags(w: Workload, b: Optional[int] = None) -> np.ndarray:
     p[0] = p[1]
     t = np.fft.irfft(1.0 / p, n=L)
     return np.ascontiguousarray(t[:b])
+
+
+def covariance_lags(w: Workload, b: Optional[int] = None) -> np.ndarray:
+    """Noise autocorrelation lags c[0..b-1] (float64) of the PSD, for gap filling.
+
+    The PSD sampled on the frequency grid j*fs/L (L = psd_len, zero frequency
+    set to the first non-zero bin) is transformed to lags with an inverse real
+    FFT and the first b kept with a triangular taper (1 - tau/b): the taper
+    makes the band's symbol the PSD smoothed by a non-negative (Fejer) kernel,
+    so the band-Toeplitz covariance stays positive definite."""
+    b = w.bandwidth if b is None else b
+    L = w.psd_len
+    f = np.arange(L // 2 + 1) * (w.fs / L)
+    p = psd(w, f)
+    p[0] = p[1]
+    c = np.fft.irfft(p, n=L)[:b]
+    return np.ascontiguousarray(c * (1.0 - np.arange(b) / b))
+
+
+def gap_mask(w: Workload, det0: int = 0, n_det: Optional[int] = None, frac: float = 0.01,
+             mean_len: int = 200) -> np.ndarray:
+    """Missing-sample mask [n_det, n_samp] (bool): gaps of random length (1 to
+    2 mean_len - 1 samples) at random positions, covering about `frac` of each
+    detector's stream, seeded per detector."""
+    n_det = w.n_det - det0 if n_det is None else n_det
+    out = np.zeros((n_det, w.n_samp), dtype=bool)
+    n_gaps = max(1, int(round(frac * w.n_samp / mean_len)))
+    for j in range(n_det):
+        key = stream_key(w.seed, 2 + det0 + j, SUB_GAPS)
+        u = uniform(key, torch.arange(2 * n_gaps)).numpy()
+        starts = (u[:n_gaps] * w.n_samp).astype(np.int64)
+        lens = 1 + (u[n_gaps:] * (2 * mean_len - 1)).astype(np.int64)
+        for s0, ln in zip(starts, lens):
+            out[j, s0:s0 + ln] = True
+    return out
 
 
 def white_lags(w: Workload) -> np.ndarray:
