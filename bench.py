@@ -206,6 +206,38 @@ def measure(w, dev, steps, warmup):
     return res
 
 
+def measure_gapfill(w, dev, frac=0.01, rtol=1e-10):
+    """Constrained-realisation gap filling of the workload's streams (1 % of the
+    samples missing in gaps of 1-399 samples, band-Toeplitz covariance of the
+    workload's bandwidth): wall time of the whole call (CG to rtol on every
+    detector, set-up and output), its CG iterations, and samples/s per CG
+    iteration."""
+    import numpy as np
+    import torch
+
+    from paper_2603_19600_amd import furax as fx
+    from paper_2603_19600_amd import synth
+
+    C = fx.Noise("band", w.n_det, w.n_samp,
+                 lags=torch.from_numpy(synth.covariance_lags(w)).to(dev))
+    d = synth.noise(w, device=dev, shape_1f=True)
+    nr = synth.noise(w.with_(seed=w.seed + 1), device=dev, shape_1f=True)
+    gaps = torch.from_numpy(synth.gap_mask(w, frac=frac).astype(np.uint8)).to(dev)
+    fx.gap_fill(C, gaps, d, nr, max_iter=2, rtol=0.0)       # warm-up (plans, caches)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out, iters, rel, st = fx.gap_fill(C, gaps, d, nr, max_iter=500, rtol=rtol)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    S = w.n_det * w.n_samp
+    log(f"gap fill: {iters} CG iterations in {dt * 1e3:.1f} ms ({dt * 1e3 / max(iters, 1):.3f} ms "
+        f"per iteration), worst |r|/|b| {rel:.2e}")
+    return {"workload": w.name.replace(f"band{w.bandwidth}", f"gapfill{w.bandwidth}"),
+            "missing_fraction": float(gaps.double().mean()), "cg_iters": iters,
+            "rel_resid": rel, "ms_total": dt * 1e3, "ms_per_cg_iter": dt * 1e3 / max(iters, 1),
+            "samples_per_s_per_cg_iter": S / (dt / max(iters, 1))}
+
+
 def cpu_baseline(w, n_det):
     """The FP64 NumPy oracle's P^T N^-1 P on a detector prefix of the same workload,
     on one host core (BLAS/OpenMP pools limited to one thread)."""
@@ -372,6 +404,8 @@ def main():
                     help="skip the boresight-quaternion pointing variants")
     ap.add_argument("--no-deproj", action="store_true",
                     help="skip the template-deprojection variants")
+    ap.add_argument("--no-gapfill", action="store_true",
+                    help="skip the gap-filling measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-dets", type=int, default=64)
     ap.add_argument("--summarize-trace", metavar="DIR",
@@ -438,6 +472,10 @@ def main():
                                 "value": r["value"], "ms_per_step": r["ms_per_step"],
                                 "kernels": r["kernels"], "operator": r["operator"]}
 
+    gapfill = None
+    if not args.no_gapfill and w.dtype == "f64" and w.bandwidth <= 4096:
+        gapfill = measure_gapfill(w, dev)
+
     # the dominant operator kernel of the iteration
     name, k = max(((n, v) for n, v in primary["kernels"].items() if "alg_bytes" in v),
                   key=lambda kv: kv[1]["ms"])
@@ -479,6 +517,7 @@ def main():
             "speedup_vs_fp64": fp32["value"] / primary["value"]},
         "quat": quat or None,
         "deproj": deproj or None,
+        "gapfill": gapfill,
         "host": host_info(),
     }
     print(json.dumps(line), flush=True)

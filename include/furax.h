@@ -306,6 +306,34 @@ furax_status furax_pointing_vjp(const furax_pointing *P, int32_t map_dt, const v
 furax_status furax_template_fit(const furax_noise *N, int32_t dt, const void *tod, double *amp,
                                 hipStream_t stream);
 
+/* Gap filling by constrained Gaussian realisations (the band-Toeplitz
+ * operator's use named after Table 2).  For every detector with missing
+ * samples G and valid samples V:
+ *     out_G = n_G + N_GV N_VV^-1 (d_V - n_V),    out_V = d_V,
+ * where N is the noise COVARIANCE described by C (kind 1: band-Toeplitz
+ * autocorrelation lags c[0..b-1], b <= 4096, truncated at the stream's ends;
+ * kind 0: white, then out_G = n_G) and n is an unconstrained realisation of
+ * it drawn by the caller.  N_VV^-1 is applied by conjugate gradients on all
+ * detectors at once (each with its own scalars), preconditioned by 1/c_k[0],
+ * in FP64 whatever dt is, until every detector's |r|/|b| <= rtol or max_iter.
+ *   gaps: [n_det][n_samp] uint8, nonzero = missing.  tod, noise_real, out:
+ *   [n_det][n_samp] of dtype dt (out may alias tod or noise_real).
+ * Allocates 4 FP64 TOD-sized vectors stream-ordered; synchronous on return.
+ * Returns FURAX_ENOTCONV when max_iter is reached with rtol > 0 (out is
+ * still written) and FURAX_EBREAKDOWN on a non-finite residual. */
+typedef struct {
+  int32_t max_iter;        /* >= 0                                                   */
+  double rtol;             /* >= 0                                                   */
+} furax_gapfill_opts;
+typedef struct {
+  int32_t iters;           /* CG iterations performed                                */
+  double rel_resid;        /* largest |r_k| / |b_k| over the detectors at exit       */
+} furax_gapfill_info;
+furax_status furax_gap_fill(const furax_noise *C, int32_t dt, const uint8_t *gaps,
+                            const void *tod, const void *noise_real, void *out,
+                            const furax_gapfill_opts *opt, furax_gapfill_info *info,
+                            hipStream_t stream);
+
 /* Thread-local description of the last non-OK status (never NULL). */
 const char *furax_last_error(void);
 /* Frees the library's per-device FFT twiddle tables (rebuilt on demand). */

@@ -18,7 +18,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfurax.so")
-SOURCES = ["api.hip", "pointing.hip", "noise.hip", "mapmaker.hip", "superpix.hip", "vjp.hip"]
+SOURCES = ["api.hip", "pointing.hip", "noise.hip", "mapmaker.hip", "superpix.hip", "vjp.hip",
+           "gapfill.hip"]
 
 ARCH = os.environ.get("FURAX_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

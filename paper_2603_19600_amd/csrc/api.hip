@@ -200,6 +200,30 @@ furax_status furax_pointing_transpose(const furax_pointing *P, int32_t tod_dt, c
                                 planar_layout(npix_of(P->nside)), stream);
 }
 
+furax_status furax_gap_fill(const furax_noise *C, int32_t dt, const uint8_t *gaps,
+                            const void *tod, const void *noise_real, void *out,
+                            const furax_gapfill_opts *opt, furax_gapfill_info *info,
+                            hipStream_t stream) {
+  if (!C) return set_error(FURAX_EINVAL, "covariance descriptor is NULL");
+  if (!dtype_ok(dt)) return set_error(FURAX_EINVAL, "bad dtype");
+  if (C->kind != 0 && C->kind != 1)
+    return set_error(FURAX_EINVAL, "gap filling needs a white (0) or band (1) covariance");
+  FX_TRY(check_noise(C, C->n_det, C->n_samp, FURAX_F64));   // the solve runs in FP64
+  if (C->kind == 0 && !C->inv_var) return set_error(FURAX_EINVAL, "white covariance needs inv_var");
+  if (!opt) return set_error(FURAX_EINVAL, "NULL options");
+  if (opt->max_iter < 0 || !(opt->rtol >= 0.0) || !(opt->rtol - opt->rtol == 0.0))
+    return set_error(FURAX_EINVAL, "max_iter must be >= 0 and rtol finite and >= 0");
+  if (C->n_samp > 0 && (!gaps || !tod || !noise_real || !out))
+    return set_error(FURAX_EINVAL, "NULL gaps, tod, noise_real or out");
+  if (dt == FURAX_F32)
+    return gap_fill_impl<float>(C, gaps, static_cast<const float *>(tod),
+                                static_cast<const float *>(noise_real), static_cast<float *>(out),
+                                opt, info, stream);
+  return gap_fill_impl<double>(C, gaps, static_cast<const double *>(tod),
+                               static_cast<const double *>(noise_real), static_cast<double *>(out),
+                               opt, info, stream);
+}
+
 furax_status furax_template_fit(const furax_noise *N, int32_t dt, const void *tod, double *amp,
                                 hipStream_t stream) {
   if (!N) return set_error(FURAX_EINVAL, "noise descriptor is NULL");

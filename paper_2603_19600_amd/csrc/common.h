@@ -414,6 +414,17 @@ size_t noise_workspace_bytes(const furax_noise *N);
 template <typename T>
 furax_status launch_deproject(const furax_noise *N, const T *in, T *out, double *amp,
                               hipStream_t s);
+// Kernel spectrum of a band model (noise_workspace_bytes<T> bytes at spec),
+// then the weight (or, for a covariance, N itself) applied to [n_det][n_samp].
+template <typename T>
+furax_status noise_prepare(const furax_noise *N, void *spec, hipStream_t s);
+template <typename T>
+furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *spec,
+                       hipStream_t s);
+template <typename T>
+furax_status gap_fill_impl(const furax_noise *C, const uint8_t *gaps, const T *d, const T *nr,
+                           T *out, const furax_gapfill_opts *opt, furax_gapfill_info *info,
+                           hipStream_t s);
 
 furax_status zero_async(void *ptr, size_t bytes, hipStream_t s);
 

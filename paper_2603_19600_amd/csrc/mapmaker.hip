@@ -17,11 +17,6 @@
 namespace fx {
 
 template <typename T>
-furax_status noise_prepare(const furax_noise *N, void *spec, hipStream_t s);
-template <typename T>
-furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *spec,
-                       hipStream_t s);
-template <typename T>
 furax_status launch_bj_build(const PtArgs<T> &a, const double *w_det, double *M6, int32_t *hits,
                              hipStream_t s);
 furax_status launch_bj_invert(int64_t npix, const double *M6, const int32_t *hits,

@@ -51,6 +51,14 @@ class _PcgOpts(C.Structure):
                 ("no_early_exit", C.c_int32)]
 
 
+class _GapOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("rtol", C.c_double)]
+
+
+class _GapInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("rel_resid", C.c_double)]
+
+
 class _PcgTiming(C.Structure):
     _fields_ = [("iters", C.c_int32), ("ms_apply", C.c_double), ("ms_noise", C.c_double),
                 ("ms_transpose", C.c_double), ("ms_update", C.c_double)]
@@ -74,6 +82,7 @@ def _load() -> C.CDLL:
         "furax_pointing_transpose": [P, i32, vp, vp, i32, vp],
         "furax_noise_apply": [N, i32, vp, vp, vp],
         "furax_template_fit": [N, i32, vp, vp, vp],
+        "furax_gap_fill": [N, i32, vp, vp, vp, vp, C.POINTER(_GapOpts), C.POINTER(_GapInfo), vp],
         "furax_bj_build": [P, N, vp, vp, vp],
         "furax_bj_invert": [i64, vp, vp, dbl, i32, vp, vp, vp, vp],
         "furax_normal_workspace_bytes": [P, N, i32],
@@ -105,7 +114,8 @@ _lib = _load()
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = ("furax_ang2pix", "furax_pointing_apply", "furax_pointing_transpose",
-           "furax_noise_apply", "furax_template_fit", "furax_bj_build", "furax_bj_invert",
+           "furax_noise_apply", "furax_template_fit", "furax_gap_fill", "furax_bj_build",
+           "furax_bj_invert",
            "furax_normal_workspace_bytes", "furax_normal_apply", "furax_pcg_mapmake",
            "furax_pcg_create", "furax_pcg_iterate", "furax_pcg_finish", "furax_pcg_destroy",
            "furax_pcg_set_timing", "furax_pcg_read_timing",
@@ -358,6 +368,28 @@ def template_fit(N: Noise, tod: torch.Tensor) -> torch.Tensor:
     _check(_lib.furax_template_fit(C.byref(c), _dt(tod), _ptr(tod), _ptr(amp),
                                    _stream(tod.device)))
     return amp
+
+
+def gap_fill(cov: Noise, gaps: torch.Tensor, tod: torch.Tensor, noise_real: torch.Tensor,
+             max_iter: int = 200, rtol: float = 1e-10, out: Optional[torch.Tensor] = None,
+             raise_on: Sequence[int] = (EINVAL, ENOMEM, EHIP, EUNSUPPORTED)):
+    """Constrained Gaussian realisation of the missing samples (see furax_gap_fill):
+    cov describes the noise covariance ("band": autocorrelation lags).  Returns
+    (out, iters, rel_resid, status)."""
+    _dev(tod, "tod", None, (cov.n_det, cov.n_samp))
+    _dev(noise_real, "noise_real", tod.dtype, tod.shape)
+    _dev(gaps, "gaps", torch.uint8, tod.shape)
+    if out is None:
+        out = torch.empty_like(tod)
+    _dev(out, "out", tod.dtype, tod.shape)
+    c = cov.c()
+    opt = _GapOpts(int(max_iter), float(rtol))
+    info = _GapInfo(0, 0.0)
+    st = _lib.furax_gap_fill(C.byref(c), _dt(tod), _ptr(gaps), _ptr(tod), _ptr(noise_real),
+                             _ptr(out), C.byref(opt), C.byref(info), _stream(tod.device))
+    if st in raise_on:
+        _check(st)
+    return out, info.iters, info.rel_resid, st
 
 
 def bj_build(P: Pointing, N: Noise):
