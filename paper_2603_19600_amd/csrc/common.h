@@ -260,6 +260,14 @@ __device__ __forceinline__ T gain_of(const PtArgs<T> &a, int64_t k) {
   return a.gain ? (T)a.gain[k] : (T)1;
 }
 
+// Streams read or written once per sample (pointing planes, TOD, label
+// planes) go through the non-temporal path, so they do not evict the map
+// lines that the gathers of neighbouring samples reuse from L1 and L2.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ __forceinline__ void st_stream(T *p, T v) { __builtin_nontemporal_store(v, p); }
+
 // ---------------------------------------------------------------------------
 // Launch helpers.
 // ---------------------------------------------------------------------------

@@ -54,6 +54,29 @@ __device__ __forceinline__ C2<T> cscale(C2<T> a, T s) { return {a.x * s, a.y * s
 // 16 (pad16) so that the stride-16 accesses of the first pass do not pile onto
 // a few banks.  tw[j] = exp(-2 pi i j / L), L = 2M, so W_M^x = tw[2x].  INV
 // selects the (unnormalised) inverse transform.
+// Output k of the real-spectrum split, kernel multiply and re-pack, from the
+// packed forward transform Z (za = Z[k], zb = Z[M - k]).  With E and O the
+// spectra of the even and odd samples, E = (Z[k] + conj Z[M-k]) / 2,
+// O = (Z[k] - conj Z[M-k]) / 2i, the full spectrum is X[k] = E + W^k O and
+// X[k + M] = E - W^k O (W = exp(-2 pi i / L)).  Multiplying by the real,
+// symmetric kernel spectrum H and re-packing gives E' + i O' with
+//   E' = hp E + hm W^k O,  O' = hm conj(W^k) E + hp O,
+// hp = (H[k] + H[M-k]) / 2, hm = (H[k] - H[M-k]) / 2 (H already divided by
+// M).  Substituting E and O, every term but two cancels:
+//   Re out = alpha_k Re Z[k] + beta_k Im Z[M-k],
+//   Im out = alpha_k Im Z[k] + beta_k Re Z[M-k],
+// alpha_k = hp + Im(W^k) hm, beta_k = Re(W^k) hm, tabulated per k by
+// k_spectrum (ab = (alpha_k, beta_k)).
+template <typename T>
+__device__ __forceinline__ C2<T> split_mul(C2<T> za, C2<T> zb, C2<T> ab) {
+  return {ab.x * za.x + ab.y * zb.y, ab.x * za.y + ab.y * zb.x};
+}
+
+// Per-kernel layout of the spectrum workspace: H[0..M] (padded to M + 2
+// entries) then the split coefficients (alpha_k, beta_k), k = 0..M-1.
+__host__ __device__ constexpr int64_t spec_block(int M) { return 3 * (int64_t)M + 2; }
+__host__ __device__ constexpr int64_t spec_coef_off(int M) { return (int64_t)M + 2; }
+
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int pad16(int e) { return e + (e >> 4); }
 
@@ -279,7 +302,6 @@ __global__ void __launch_bounds__(NT) k_overlap_save(const T *__restrict__ in, T
     for (int i = tid; i < nl; i += NT) tab[o + i] = tw[st * i];
     for (int i = tid; i < Pl::nhi(t); i += NT) tab[o + nl + i] = tw[st * 128 * i];
   }
-  const TwStage W = stage_of<M>(tab, Pl::nstage - 1);   // the split's twiddles
 
   const int64_t t_beg = PREFETCH ? ntask * blockIdx.x / gridDim.x
                                  : xcd_remap(blockIdx.x, (int64_t)gridDim.x);
@@ -310,28 +332,12 @@ __global__ void __launch_bounds__(NT) k_overlap_save(const T *__restrict__ in, T
     fft_lds<T, M, NT, false>(s, tab);
 
     const int64_t det = t / nblk, blk = t - det * nblk;
-    const T *H = spec + det * spec_stride;   // H[0..M], already divided by M
+    const C2<T> *AB = reinterpret_cast<const C2<T> *>(spec + det * spec_stride + spec_coef_off(M));
     for (int k = tid; k <= M / 2; k += NT) {
       const int k2 = (M - k) & (M - 1);
       const C2<T> z1 = s[pad16(k)], z2 = s[pad16(k2)];
-      C2<T> r1, r2;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int kk = h ? k2 : k;
-        const C2<T> za = h ? z2 : z1;
-        const C2<T> zb = h ? z1 : z2;               // Z[M - kk]
-        const C2<T> zc = {zb.x, -zb.y};             // conj(Z[M - kk])
-        const C2<T> E = cscale(cadd(za, zc), (T)0.5);
-        const C2<T> Dh = cscale(csub(za, zc), (T)0.5);
-        const C2<T> O = {Dh.y, -Dh.x};              // (Z[k] - conj Z[M-k]) / (2i)
-        const T Hk = H[kk], Hm = H[M - kk];
-        const T hp = (Hk + Hm) * (T)0.5, hm = (Hk - Hm) * (T)0.5;
-        const C2<T> Wk = narrow<T>(W(kk));          // exp(-2 pi i kk / L)
-        const C2<T> A = cadd(cscale(E, hp), cscale(cmul(Wk, O), hm));
-        const C2<T> B = cadd(cscale(cmulc(E, Wk), hm), cscale(O, hp));
-        const C2<T> r = {A.x - B.y, A.y + B.x};     // A + i B
-        if (h) r2 = r; else r1 = r;
-      }
+      const C2<T> r1 = split_mul<T>(z1, z2, AB[k]);
+      const C2<T> r2 = split_mul<T>(z2, z1, AB[k2]);
       s[pad16(k)] = r1;
       if (k2 != k) s[pad16(k2)] = r2;
     }
@@ -375,25 +381,6 @@ __device__ __forceinline__ void twiddle16(C2<T> (&v)[16], C2<double> W1) {
     v[r] = twiddle<T, INV>(v[r], w);
     v[r + 8] = twiddle<T, INV>(v[r + 8], cmul(w, w8));
   }
-}
-
-// Output k of the real-spectrum split, kernel multiply and re-pack, from the
-// packed forward transform Z (za = Z[k], zb = Z[M - k]): with E and O the
-// spectra of the even and odd samples, X[k] = E + W^k O and X[k + M] =
-// E - W^k O (W = exp(-2 pi i / L)); multiplying by the real, symmetric kernel
-// spectrum H and re-packing gives E' + i O' with
-//   E' = E hp + W^k O hm,  O' = conj(W^k) E hm + O hp,
-// hp = (H[k] + H[M-k]) / 2, hm = (H[k] - H[M-k]) / 2 (H already divided by M).
-template <typename T>
-__device__ __forceinline__ C2<T> split_mul(C2<T> za, C2<T> zb, T Hk, T Hm, C2<T> Wk) {
-  const C2<T> zc = {zb.x, -zb.y};             // conj(Z[M - k])
-  const C2<T> E = cscale(cadd(za, zc), (T)0.5);
-  const C2<T> Dh = cscale(csub(za, zc), (T)0.5);
-  const C2<T> O = {Dh.y, -Dh.x};              // (Z[k] - conj Z[M-k]) / (2i)
-  const T hp = (Hk + Hm) * (T)0.5, hm = (Hk - Hm) * (T)0.5;
-  const C2<T> A = cadd(cscale(E, hp), cscale(cmul(Wk, O), hm));
-  const C2<T> B = cadd(cscale(cmulc(E, Wk), hm), cscale(O, hp));
-  return {A.x - B.y, A.y + B.x};              // A + i B
 }
 
 // ---------------------------------------------------------------------------
@@ -555,7 +542,7 @@ k_os_reg(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
   }
   // ---- forward pass 3 (radix RL, span 4096), split + kernel multiply, inverse
   // pass 0 (radix RL, span 1), all in registers
-  const T *H = spec + det * spec_stride;   // H[0..M], already divided by M
+  const C2<T> *AB = reinterpret_cast<const C2<T> *>(spec + det * spec_stride + spec_coef_off(M));
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
     const int j0 = tid + NT * i;
@@ -592,7 +579,7 @@ k_os_reg(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
         const int a = (e ? j1 : j0) + 4096 * r;
         const C2<T> zb = (z0 && e == 0) ? Z[0][(RL - r) % RL] : Z[1 - e][RL - 1 - r];
         const C2<T> zb0 = (z0 && e == 1) ? Z[1][RL - 1 - r] : zb;
-        X[e][r] = split_mul<T>(Z[e][r], zb0, H[a], H[M - a], narrow<T>(tw[a]));
+        X[e][r] = split_mul<T>(Z[e][r], zb0, AB[a]);
       }
     // inverse pass 0: radix RL, span 1 (no twiddles), in place
 #pragma unroll
@@ -666,30 +653,49 @@ k_os_reg(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
   }
 }
 
-// Spectrum of the symmetric circular kernel of length L = 2M, divided by M:
-// H[k] = (t0 + 2 sum_{tau=1}^{b-1} t[tau] cos(2 pi k tau / L)) / M, k = 0..M.
-// One wave per frequency k: the lanes split the lags, cos(2 pi k tau / L) is
-// read from the FP64 table at the exact integer phase (k tau) mod L, and the
-// lanes' partial sums are combined in a fixed order.
+// Spectrum of the symmetric circular kernel of length L = 2M, divided by M,
+// and the split coefficients of split_mul.  One wave per pair (k, M - k),
+// k = 0..M/2: since cos(2 pi (M - k) tau / L) = (-1)^tau cos(2 pi k tau / L),
+//   H[k]     = (t0 + 2 (S_even + S_odd)) / M,
+//   H[M - k] = (t0 + 2 (S_even - S_odd)) / M,
+// with S_even / S_odd the sums of t[tau] cos(2 pi k tau / L) over even / odd
+// tau >= 1; then alpha and beta of k and M - k, all in FP64, stored as T.
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_spectrum(const double *__restrict__ lags, int32_t b,
                                                      int64_t lag_stride, int32_t M,
                                                      const C2<double> *__restrict__ tw64,
-                                                     double *__restrict__ spec64,
-                                                     float *__restrict__ spec32) {
+                                                     T *__restrict__ spec) {
   const int64_t kern = blockIdx.y;
   const int k = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (k > M) return;
+  if (k > M / 2) return;
   const double *t = lags + kern * lag_stride;
   const int64_t Lmask = 2 * M - 1;
-  double acc = 0.0;
-  for (int tau = 1 + lane; tau < b; tau += 64) acc += t[tau] * tw64[((int64_t)k * tau) & Lmask].x;
+  double se = 0.0, so = 0.0;
+  for (int tau = 1 + lane; tau < b; tau += 64) {
+    const double v = t[tau] * tw64[((int64_t)k * tau) & Lmask].x;
+    if (tau & 1) so += v;
+    else se += v;
+  }
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) {
-    const double h = (t[0] + 2.0 * acc) / (double)M;
-    if (spec64) spec64[kern * (int64_t)(M + 1) + k] = h;
-    if (spec32) spec32[kern * (int64_t)(M + 1) + k] = (float)h;
+  for (int off = 32; off >= 1; off >>= 1) {
+    se += __shfl_down(se, off, 64);
+    so += __shfl_down(so, off, 64);
+  }
+  if (lane != 0) return;
+  T *H = spec + kern * spec_block(M);
+  C2<T> *AB = reinterpret_cast<C2<T> *>(H + spec_coef_off(M));
+  const int k2 = M - k;
+  const double hk = (t[0] + 2.0 * (se + so)) / (double)M;
+  const double hk2 = (t[0] + 2.0 * (se - so)) / (double)M;
+  H[k] = (T)hk;
+  if (k2 != k) H[k2] = (T)hk2;
+  const double hp = 0.5 * (hk + hk2), hm = 0.5 * (hk - hk2);
+  const C2<double> w = tw64[k];
+  AB[k] = {(T)(hp + w.y * hm), (T)(w.x * hm)};
+  if (k2 < M && k2 != k) {
+    const C2<double> w2 = tw64[k2];
+    AB[k2] = {(T)(hp - w2.y * hm), (T)(-w2.x * hm)};
   }
 }
 
@@ -778,7 +784,7 @@ size_t noise_workspace_bytes(const furax_noise *N) {
   if (N->kind != 1) return 0;
   const int M = os_half_length<T>(N->bandwidth);
   const int64_t nk = N->toeplitz_stride ? N->n_det : 1;
-  return (size_t)nk * (M + 1) * sizeof(T);
+  return (size_t)nk * spec_block(M) * sizeof(T);
 }
 template size_t noise_workspace_bytes<float>(const furax_noise *);
 template size_t noise_workspace_bytes<double>(const furax_noise *);
@@ -792,11 +798,9 @@ furax_status noise_prepare(const furax_noise *N, void *spec, hipStream_t s) {
   FX_TRY(get_twiddles(2 * M, s, tw));
   const int64_t nk = N->toeplitz_stride ? N->n_det : 1;
   constexpr int per_block = kBlock / 64;
-  dim3 grid((M + 1 + per_block - 1) / per_block, (unsigned)nk);
-  hipLaunchKernelGGL(k_spectrum, grid, dim3(kBlock), 0, s, N->toeplitz, (int32_t)N->bandwidth,
-                     N->toeplitz_stride, M, tw.tw64,
-                     sizeof(T) == 8 ? static_cast<double *>(spec) : nullptr,
-                     sizeof(T) == 4 ? static_cast<float *>(spec) : nullptr);
+  dim3 grid((M / 2 + 1 + per_block - 1) / per_block, (unsigned)nk);
+  hipLaunchKernelGGL(k_spectrum<T>, grid, dim3(kBlock), 0, s, N->toeplitz, (int32_t)N->bandwidth,
+                     N->toeplitz_stride, M, tw.tw64, static_cast<T *>(spec));
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }
@@ -810,7 +814,7 @@ static furax_status launch_os(const furax_noise *N, const T *in, T *out, const T
   const int64_t V = 2 * M - 2 * (int64_t)(b - 1);
   const int64_t nblk = (N->n_samp + V - 1) / V;
   const int64_t ntask = N->n_det * nblk;
-  const int64_t spec_stride = N->toeplitz_stride ? (M + 1) : 0;
+  const int64_t spec_stride = N->toeplitz_stride ? spec_block(M) : 0;
   hipLaunchKernelGGL((k_overlap_save<T, M, NT, false>), dim3((unsigned)ntask), dim3(NT), 0, s, in,
                      out, N->n_samp, b, nblk, ntask, spec, spec_stride, tw);
   FX_HIP(hipGetLastError());
@@ -824,7 +828,7 @@ static furax_status launch_os_reg(const furax_noise *N, const T *in, T *out, con
   const int64_t V = 2 * M - 2 * (int64_t)(b - 1);
   const int64_t nblk = (N->n_samp + V - 1) / V;
   const int64_t ntask = N->n_det * nblk;
-  const int64_t spec_stride = N->toeplitz_stride ? (M + 1) : 0;
+  const int64_t spec_stride = N->toeplitz_stride ? spec_block(M) : 0;
   if (N->n_samp + 4 * (int64_t)M >= ((int64_t)1 << 31))   // 32-bit offsets inside the kernel
     return launch_os<T, M, M / 16>(N, in, out, spec, tw, s);
   hipLaunchKernelGGL((k_os_reg<T, M, NT>), dim3((unsigned)ntask), dim3(NT), 0, s, in, out,

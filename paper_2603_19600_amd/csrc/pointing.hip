@@ -288,9 +288,9 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *
 #pragma unroll
       for (int b = 0; b < kBatch; ++b) {
         sl[b] = slot_of(tl, d0, t0, s0 + b * kApplyThreads, a.n_det, a.n_samp);
-        th[b] = a.theta[sl[b].off];
-        ph[b] = a.phi[sl[b].off];
-        ps[b] = a.psi[sl[b].off];
+        th[b] = ld_stream(a.theta + sl[b].off);
+        ph[b] = ld_stream(a.phi + sl[b].off);
+        ps[b] = ld_stream(a.psi + sl[b].off);
       }
 #pragma unroll
       for (int b = 0; b < kBatch; ++b) {
@@ -306,9 +306,11 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *
     for (int b = 0; b < kBatch; ++b) {
       if (!sl[b].in) continue;
       const T y = (T)I[b] + c[b] * (T)Q[b] + s[b] * (T)U[b];
-      tod[sl[b].off] = px[b] >= 0 ? (T)tc.gain[sl[b].kl] * y : (T)0;
-      if (pix_out) pix_out[sl[b].off] = px[b];
-      if (local_out) local_out[sl[b].off] = px[b] >= 0 ? (uint16_t)(tag[b] & local_mask) : 0xffff;
+      st_stream(tod + sl[b].off, px[b] >= 0 ? (T)tc.gain[sl[b].kl] * y : (T)0);
+      if (pix_out) st_stream(pix_out + sl[b].off, px[b]);
+      if (local_out)
+        st_stream(local_out + sl[b].off,
+                  (uint16_t)(px[b] >= 0 ? (uint16_t)(tag[b] & local_mask) : 0xffff));
     }
   }
 }
@@ -462,7 +464,7 @@ k_scatter(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_d
         sl[b] = slot_of(tl, d0, t0, s0 + b * kScatterThreads, a.n_det, a.n_samp);
         qb[b] = load_quat(a.qb, t0 + sl[b].il < a.n_samp ? t0 + sl[b].il : 0);
         if constexpr (MODE == 2) px[b] = pix_in[sl[b].off];
-        if constexpr (MODE != 1) v[b] = tod[sl[b].off];
+        if constexpr (MODE != 1) v[b] = ld_stream(tod + sl[b].off);
       }
 #pragma unroll
       for (int b = 0; b < KB; ++b) {
@@ -476,14 +478,14 @@ k_scatter(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_d
 #pragma unroll
       for (int b = 0; b < KB; ++b) {
         sl[b] = slot_of(tl, d0, t0, s0 + b * kScatterThreads, a.n_det, a.n_samp);
-        ps[b] = a.psi[sl[b].off];
+        ps[b] = ld_stream(a.psi + sl[b].off);
         if constexpr (MODE == 2) {
           px[b] = pix_in[sl[b].off];
         } else {
-          th[b] = a.theta[sl[b].off];
-          ph[b] = a.phi[sl[b].off];
+          th[b] = ld_stream(a.theta + sl[b].off);
+          ph[b] = ld_stream(a.phi + sl[b].off);
         }
-        if constexpr (MODE != 1) v[b] = tod[sl[b].off];
+        if constexpr (MODE != 1) v[b] = ld_stream(tod + sl[b].off);
       }
 #pragma unroll
       for (int b = 0; b < KB; ++b) {
