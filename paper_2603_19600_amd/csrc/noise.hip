@@ -42,18 +42,6 @@ __device__ __forceinline__ C2<T> cmulc(C2<T> a, C2<T> b) {  // a * conj(b)
 template <typename T>
 __device__ __forceinline__ C2<T> cscale(C2<T> a, T s) { return {a.x * s, a.y * s}; }
 
-// ---------------------------------------------------------------------------
-// Stockham autosort FFT of length M = 2^m in LDS, radix 16 in registers.
-//
-// Each pass loads every butterfly's R inputs (stride M/R) into registers,
-// synchronises, multiplies by the twiddles W_M^(r k M/(R Ns)), performs the
-// R-point DFT in registers and writes the R outputs at stride Ns, so one LDS
-// buffer suffices.  M = 16^a * f with f in {1, 2, 4, 8}: a radix-16 passes
-// then one or two radix-4 / radix-2 passes (16384 = 16^3 * 4 takes 4 passes
-// instead of 7 radix-4 ones).  The LDS index is padded by one element every
-// 16 (pad16) so that the stride-16 accesses of the first pass do not pile onto
-// a few banks.  tw[j] = exp(-2 pi i j / L), L = 2M, so W_M^x = tw[2x].  INV
-// selects the (unnormalised) inverse transform.
 // Output k of the real-spectrum split, kernel multiply and re-pack, from the
 // packed forward transform Z (za = Z[k], zb = Z[M - k]).  With E and O the
 // spectra of the even and odd samples, E = (Z[k] + conj Z[M-k]) / 2,
@@ -78,6 +66,17 @@ __host__ __device__ constexpr int64_t spec_block(int M) { return 3 * (int64_t)M 
 __host__ __device__ constexpr int64_t spec_coef_off(int M) { return (int64_t)M + 2; }
 
 // ---------------------------------------------------------------------------
+// Stockham autosort FFT of length M = 2^m in LDS, radix 16 in registers.
+//
+// Each pass loads every butterfly's R inputs (stride M/R) into registers,
+// synchronises, multiplies by the twiddles W_M^(r k M/(R Ns)), performs the
+// R-point DFT in registers and writes the R outputs at stride Ns, so one LDS
+// buffer suffices.  M = 16^a * f with f in {1, 2, 4, 8}: a radix-16 passes
+// then one or two radix-4 / radix-2 passes (16384 = 16^3 * 4 takes 4 passes
+// instead of 7 radix-4 ones).  The LDS index is padded by one element every
+// 16 (pad16) so that the stride-16 accesses of the first pass do not pile onto
+// a few banks.  tw[j] = exp(-2 pi i j / L), L = 2M, so W_M^x = tw[2x].  INV
+// selects the (unnormalised) inverse transform.
 __device__ __forceinline__ int pad16(int e) { return e + (e >> 4); }
 
 template <typename T, bool INV>
