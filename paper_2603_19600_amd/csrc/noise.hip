@@ -138,6 +138,53 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Raw buffer over a row of n values (n sizeof(T) < 2^31 bytes, checked by the
+// launcher): a load whose byte offset is at or past the end returns zero and
+// a store there is dropped.  Offsets are unsigned and must not wrap: an access
+// that belongs before the row's start takes kDropOffset instead.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_buffer(T *p, int64_t n) {
+  // dword 3: 32-bit data format, no swizzle, untyped access
+  return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)(n * (int64_t)sizeof(T)), 0x00020000);
+}
+constexpr uint32_t kDropOffset = 0x80000000u;   // past every row the launcher admits
+
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+}
+
+// The thread index as a value the compiler cannot move across this point:
+// LDS and store addresses derived from it are then computed where they are
+// used instead of being hoisted to the kernel's start and held in registers
+// for its whole length.
+__device__ __forceinline__ int fresh_tid(int tid) {
+  int t;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"(tid));
+  return t;
+}
+// Used by the FP32 register FFT, where the registers it frees raise the
+// occupancy (four waves per SIMD); the FP64 kernel is held to two by its data
+// and runs faster with the hoisted addresses.
+template <typename T>
+__device__ __forceinline__ int pinned_tid(int tid) {
+  if constexpr (sizeof(T) == 4) return fresh_tid(tid);
+  else return tid;
+}
+
 // Passes of the length-M FFT: radix 16 while it divides, then 4 and/or 2.
 // Pass p has radix R(p) and span Ns(p) = product of the earlier radices.
 template <int M>
@@ -438,8 +485,9 @@ __device__ __forceinline__ void reg_write16(C2<T> *s, const C2<T> (&v)[M / NT], 
 }
 
 template <typename T, int M, int NT>
-__device__ __forceinline__ void reg_xchg16(C2<T> *s, C2<T> (&v)[M / NT], int tid, int Ns) {
+__device__ __forceinline__ void reg_xchg16(C2<T> *s, C2<T> (&v)[M / NT], int tid_, int Ns) {
   constexpr int NB16 = M / 16, B16 = NB16 / NT, HALF = M / 2;
+  const int tid = pinned_tid<T>(tid_);
   C2<T> tmp[M / NT / 2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -475,43 +523,44 @@ k_os_reg(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
   constexpr int NP = 2048 / NT;   // butterfly pairs of the last forward pass per thread
   static_assert(B16 >= 1 && NPT == 2 * NP * RL, "whole butterflies per thread");
   __shared__ C2<T> s[HALF + HALF / 16];
-  const int tid = threadIdx.x;
+  const int tid0 = threadIdx.x, tid = tid0;
   const int64_t det = (int64_t)blockIdx.x / nblk, blk = (int64_t)blockIdx.x - det * nblk;
   const int V = L - 2 * (b - 1);
   // sample offsets within a detector's stream are 32-bit (the launcher checks
   // n + L < 2^31), so each access is a uniform base plus one 32-bit offset
   const int32_t s0 = (int32_t)(blk * V) - (b - 1);
-  const int32_t n32 = (int32_t)n;
   C2<T> v[NPT];
 
   // ---- forward pass 0 (radix 16, span 1) straight from HBM
   {
-    const T *x = in + det * n;
+    // the detector's input row as a buffer: reads past its end, and the reads
+    // before its start (given kDropOffset), return zero, which is the zero
+    // padding of the first and last blocks
+    const __amdgpu_buffer_rsrc_t xr = row_buffer(const_cast<T *>(in) + det * n, n);
 #pragma unroll
     for (int q = 0; q < B16; ++q)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        // unconditional loads from clamped offsets, zeroed outside the stream
         const int32_t g = s0 + 2 * (tid + q * NT + r * NB16);
-        const T a = x[g < 0 ? 0 : (g < n32 ? g : n32 - 1)];
-        const T c = x[g + 1 < 0 ? 0 : (g + 1 < n32 ? g + 1 : n32 - 1)];
-        v[16 * q + r].x = (g >= 0 && g < n32) ? a : (T)0;
-        v[16 * q + r].y = (g + 1 >= 0 && g + 1 < n32) ? c : (T)0;
+        v[16 * q + r].x = buf_load<T>(xr, g >= 0 ? (uint32_t)g * (uint32_t)sizeof(T) : kDropOffset);
+        v[16 * q + r].y =
+            buf_load<T>(xr, g + 1 >= 0 ? (uint32_t)(g + 1) * (uint32_t)sizeof(T) : kDropOffset);
       }
 #pragma unroll
-    for (int q = 0; q < B16; ++q) reg_r16<T, M, false>(v + 16 * q, tid + q * NT, 1, tw);
+    for (int q = 0; q < B16; ++q) reg_r16<T, M, false>(v + 16 * q, pinned_tid<T>(tid0) + q * NT, 1, tw);
   }
   reg_xchg16<T, M, NT>(s, v, tid, 1);
   // ---- forward pass 1 (span 16), exchange
 #pragma unroll
-  for (int q = 0; q < B16; ++q) reg_r16<T, M, false>(v + 16 * q, tid + q * NT, 16, tw);
+  for (int q = 0; q < B16; ++q) reg_r16<T, M, false>(v + 16 * q, pinned_tid<T>(tid0) + q * NT, 16, tw);
   reg_xchg16<T, M, NT>(s, v, tid, 16);
   // ---- forward pass 2 (span 256), exchange into the paired layout of pass 3:
   // v[(2 i + h) RL + r] = element jh_i + 4096 r, j0 = tid + 256 i, j1 = 4096 - j0
   // (2048 for j0 = 0)
 #pragma unroll
-  for (int q = 0; q < B16; ++q) reg_r16<T, M, false>(v + 16 * q, tid + q * NT, 256, tw);
+  for (int q = 0; q < B16; ++q) reg_r16<T, M, false>(v + 16 * q, pinned_tid<T>(tid0) + q * NT, 256, tw);
   {
+    const int tid = pinned_tid<T>(tid0);
     C2<T> tmp[NPT / 2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -600,6 +649,7 @@ k_os_reg(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
   // ---- exchange: inverse pass 0 outputs (butterfly j at RL j + r; j0 < 2048
   // in the lower half, j1 >= 2048 in the upper) -> radix-16 layout
   {
+    const int tid = pinned_tid<T>(tid0);
     C2<T> tmp[NPT / 2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -630,24 +680,28 @@ k_os_reg(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
   }
   // ---- inverse passes 1 (span RL) and 2 (span 16 RL)
 #pragma unroll
-  for (int q = 0; q < B16; ++q) reg_r16<T, M, true>(v + 16 * q, tid + q * NT, RL, tw);
+  for (int q = 0; q < B16; ++q) reg_r16<T, M, true>(v + 16 * q, pinned_tid<T>(tid0) + q * NT, RL, tw);
   reg_xchg16<T, M, NT>(s, v, tid, RL);
 #pragma unroll
-  for (int q = 0; q < B16; ++q) reg_r16<T, M, true>(v + 16 * q, tid + q * NT, 16 * RL, tw);
+  for (int q = 0; q < B16; ++q) reg_r16<T, M, true>(v + 16 * q, pinned_tid<T>(tid0) + q * NT, 16 * RL, tw);
   reg_xchg16<T, M, NT>(s, v, tid, 16 * RL);
   // ---- inverse pass 3 (span M/16): outputs j + r M/16, straight to HBM
-  T *z = out + det * n;
+  // the detector's output row as a buffer of n values: stores past its end and
+  // the overlap outputs (given kDropOffset) are dropped by the hardware, so
+  // the stores need no branches
+  const __amdgpu_buffer_rsrc_t zr = row_buffer(out + det * n, n);
   const int lo = b - 1, hi = b - 1 + V;
 #pragma unroll
   for (int q = 0; q < B16; ++q) {
-    const int j = tid + q * NT;
+    const int j = pinned_tid<T>(tid0) + q * NT;
     reg_r16<T, M, true>(v + 16 * q, j, NB16, tw);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const C2<T> w = v[16 * q + 4 * (r & 3) + (r >> 2)];
       const int e = 2 * (j + r * NB16);
-      if (e >= lo && e < hi && s0 + e < n32) z[s0 + e] = w.x;
-      if (e + 1 >= lo && e + 1 < hi && s0 + e + 1 < n32) z[s0 + e + 1] = w.y;
+      buf_store(zr, e >= lo && e < hi ? (uint32_t)(s0 + e) * (uint32_t)sizeof(T) : kDropOffset, w.x);
+      buf_store(zr, e + 1 >= lo && e + 1 < hi ? (uint32_t)(s0 + e + 1) * (uint32_t)sizeof(T)
+                                              : kDropOffset, w.y);
     }
   }
 }
@@ -820,6 +874,10 @@ static furax_status launch_os(const furax_noise *N, const T *in, T *out, const T
   return FURAX_OK;
 }
 
+// Threads per workgroup of the register-resident overlap-save, per precision.
+constexpr int kOsThreads64 = 256;
+constexpr int kOsThreads32 = 256;
+
 template <typename T, int M, int NT>
 static furax_status launch_os_reg(const furax_noise *N, const T *in, T *out, const T *spec,
                                   const C2<double> *tw, hipStream_t s) {
@@ -828,7 +886,10 @@ static furax_status launch_os_reg(const furax_noise *N, const T *in, T *out, con
   const int64_t nblk = (N->n_samp + V - 1) / V;
   const int64_t ntask = N->n_det * nblk;
   const int64_t spec_stride = N->toeplitz_stride ? spec_block(M) : 0;
-  if (N->n_samp + 4 * (int64_t)M >= ((int64_t)1 << 31))   // 32-bit offsets inside the kernel
+  // 32-bit sample offsets inside the kernel, and output rows addressed as
+  // buffers of fewer than 2^31 bytes
+  if (N->n_samp + 4 * (int64_t)M >= ((int64_t)1 << 31) ||
+      N->n_samp * (int64_t)sizeof(T) >= ((int64_t)1 << 31))
     return launch_os<T, M, M / 16>(N, in, out, spec, tw, s);
   hipLaunchKernelGGL((k_os_reg<T, M, NT>), dim3((unsigned)ntask), dim3(NT), 0, s, in, out,
                      N->n_samp, b, nblk, spec, spec_stride, tw);
@@ -1037,7 +1098,9 @@ furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *sp
     case 1024: return launch_os<T, 1024, 64>(N, in, out, sp, t, s);
     case 2048: return launch_os<T, 2048, 128>(N, in, out, sp, t, s);
     case 4096: return launch_os<T, 4096, 256>(N, in, out, sp, t, s);
-    case 8192: return launch_os_reg<T, 8192, 256>(N, in, out, sp, t, s);
+    case 8192:
+      if constexpr (sizeof(T) == 8) return launch_os_reg<T, 8192, kOsThreads64>(N, in, out, sp, t, s);
+      else return launch_os_reg<T, 8192, kOsThreads32>(N, in, out, sp, t, s);
     case 16384:
       if constexpr (sizeof(T) == 4) return launch_os<T, 16384, 1024>(N, in, out, sp, t, s);
       break;
