@@ -8,9 +8,12 @@
 // operator is v -> mask_V(N mask_V(v)) with N applied by the same overlap-save
 // kernels as the weights, the preconditioner is 1 / c_k[0], and every
 // detector has its own scalars (alpha_k, beta_k), so the detectors' solves are
-// independent.  Vectors are FP64 in both TOD precisions.  Per-detector sums are
-// taken in two fixed-order stages (chunk partials, then one pass over them),
-// so results do not depend on scheduling.
+// independent.  The iterate x itself is never formed: the fill needs only
+// N_GV x = sum_i alpha_i (N p_i)_G, and N p_i is the product each iteration
+// computes anyway, so y_G accumulates alpha_i q_i on the missing samples and
+// no final product is needed.  Vectors are FP64 in both TOD precisions.
+// Per-detector sums are taken in two fixed-order stages (chunk partials, then
+// one pass over them), so results do not depend on scheduling.
 #include <algorithm>
 
 #include "common.h"
@@ -29,14 +32,14 @@ __device__ __forceinline__ void chunk_range(int64_t n, int64_t c, int64_t &i0, i
   i1 = n * (c + 1) / kGapChunks;
 }
 
-// r = b = valid (d - n), x = 0, p = z = r / c0; partials of r z, b b and of
+// r = b = valid (d - n), y = 0, p = z = r / c0; partials of r z, b b and of
 // the number of missing samples.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_gap_init(const T *__restrict__ d,
                                                      const T *__restrict__ nr,
                                                      const uint8_t *__restrict__ gaps, int64_t n,
                                                      const GapDet *__restrict__ det,
-                                                     double *__restrict__ x, double *__restrict__ r,
+                                                     double *__restrict__ y, double *__restrict__ r,
                                                      double *__restrict__ p,
                                                      double *__restrict__ part) {
   const int64_t k = blockIdx.y;
@@ -49,7 +52,7 @@ __global__ void __launch_bounds__(kBlock) k_gap_init(const T *__restrict__ d,
     const bool g = gaps[o] != 0;
     const double v = g ? 0.0 : (double)d[o] - (double)nr[o];
     const double z = v * ic;
-    x[o] = 0.0;
+    y[o] = 0.0;
     r[o] = v;
     p[o] = z;
     acc[0] += v * z;
@@ -59,9 +62,10 @@ __global__ void __launch_bounds__(kBlock) k_gap_init(const T *__restrict__ d,
   block_sum<3>(acc, part + (k * kGapChunks + blockIdx.x) * 3, 1);
 }
 
-// q = mask_V q (in place) and partials of p q.
+// Partials of p (mask_V q) (q = N p is left unmasked: its missing samples
+// feed the fill).
 __global__ void __launch_bounds__(kBlock) k_gap_pq(const double *__restrict__ p,
-                                                   double *__restrict__ q,
+                                                   const double *__restrict__ q,
                                                    const uint8_t *__restrict__ gaps, int64_t n,
                                                    double *__restrict__ part) {
   const int64_t k = blockIdx.y;
@@ -70,9 +74,7 @@ __global__ void __launch_bounds__(kBlock) k_gap_pq(const double *__restrict__ p,
   double acc[1] = {0.0};
   for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
     const int64_t o = k * n + i;
-    const double qv = gaps[o] ? 0.0 : q[o];
-    q[o] = qv;
-    acc[0] += p[o] * qv;
+    acc[0] += p[o] * (gaps[o] ? 0.0 : q[o]);
   }
   block_sum<1>(acc, part + (k * kGapChunks + blockIdx.x), 1);
 }
@@ -130,11 +132,12 @@ __global__ void __launch_bounds__(kBlock) k_gap_scalars(int64_t n_det, int32_t s
   if (threadIdx.x == 0 && rel_out) *rel_out = red[0];
 }
 
-// x += alpha p, r -= alpha q; partials of r z (z = r / c0) and r r.
-__global__ void __launch_bounds__(kBlock) k_gap_step(double *__restrict__ x,
+// On valid samples r -= alpha q, on missing ones y += alpha q (the fill's
+// N_GV x, accumulated); partials of r z (z = r / c0) and r r.
+__global__ void __launch_bounds__(kBlock) k_gap_step(double *__restrict__ y,
                                                      double *__restrict__ r,
-                                                     const double *__restrict__ p,
-                                                     const double *__restrict__ q, int64_t n,
+                                                     const double *__restrict__ q,
+                                                     const uint8_t *__restrict__ gaps, int64_t n,
                                                      const GapDet *__restrict__ det,
                                                      double *__restrict__ part) {
   const int64_t k = blockIdx.y;
@@ -144,11 +147,15 @@ __global__ void __launch_bounds__(kBlock) k_gap_step(double *__restrict__ x,
   double acc[2] = {0.0, 0.0};
   for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
     const int64_t o = k * n + i;
-    x[o] += a * p[o];
-    const double rv = r[o] - a * q[o];
-    r[o] = rv;
-    acc[0] += rv * (rv * ic);
-    acc[1] += rv * rv;
+    const double qv = q[o];
+    if (gaps[o]) {
+      y[o] += a * qv;
+    } else {
+      const double rv = r[o] - a * qv;
+      r[o] = rv;
+      acc[0] += rv * (rv * ic);
+      acc[1] += rv * rv;
+    }
   }
   block_sum<2>(acc, part + (k * kGapChunks + blockIdx.x) * 2, 1);
 }
@@ -176,7 +183,8 @@ __global__ void __launch_bounds__(kBlock) k_gap_inv_c0(int64_t n_det, const doub
   det[k] = g;
 }
 
-// out = d on valid samples, n + y on missing ones (y = N x, or 0 for white noise).
+// out = d on valid samples, n + y on missing ones (y = N_GV x, or 0 for white
+// noise).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_gap_out(const T *__restrict__ d,
                                                     const T *__restrict__ nr,
@@ -205,7 +213,7 @@ furax_status gap_fill_impl(const furax_noise *C, const uint8_t *gaps, const T *d
     FX_HIP(hipGetLastError());
     return FURAX_OK;
   }
-  // x, r, p, q [S] FP64; spectrum; per-detector scalars and chunk partials
+  // y, r, p, q [S] FP64; spectrum; per-detector scalars and chunk partials
   const size_t vb = sizeof(double) * (size_t)S;
   const size_t spec_b = noise_workspace_bytes<double>(C);
   const size_t part_b = sizeof(double) * 3 * kGapChunks * nd;
@@ -213,7 +221,7 @@ furax_status gap_fill_impl(const furax_noise *C, const uint8_t *gaps, const T *d
   DevBuf mem;
   FX_TRY(mem.alloc(4 * al(vb) + al(spec_b) + al(part_b) + al(sizeof(GapDet) * nd) + 256, s));
   char *base = static_cast<char *>(mem.ptr);
-  double *x = reinterpret_cast<double *>(base);
+  double *y = reinterpret_cast<double *>(base);
   double *r = reinterpret_cast<double *>(base + al(vb));
   double *p = reinterpret_cast<double *>(base + 2 * al(vb));
   double *q = reinterpret_cast<double *>(base + 3 * al(vb));
@@ -225,7 +233,7 @@ furax_status gap_fill_impl(const furax_noise *C, const uint8_t *gaps, const T *d
   hipLaunchKernelGGL(k_gap_inv_c0, dim3((unsigned)((nd + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                      s, nd, C->toeplitz, C->toeplitz_stride, det);
   const dim3 grid(kGapChunks, (unsigned)nd);
-  hipLaunchKernelGGL(k_gap_init<T>, grid, dim3(kBlock), 0, s, d, nr, gaps, n, det, x, r, p, part);
+  hipLaunchKernelGGL(k_gap_init<T>, grid, dim3(kBlock), 0, s, d, nr, gaps, n, det, y, r, p, part);
   hipLaunchKernelGGL(k_gap_scalars, dim3(1), dim3(kBlock), 0, s, nd, 0, part, det, rel);
   FX_HIP(hipGetLastError());
   double worst = 0.0;
@@ -236,7 +244,7 @@ furax_status gap_fill_impl(const furax_noise *C, const uint8_t *gaps, const T *d
     FX_TRY(noise_run<double>(C, p, q, spec, s));
     hipLaunchKernelGGL(k_gap_pq, grid, dim3(kBlock), 0, s, p, q, gaps, n, part);
     hipLaunchKernelGGL(k_gap_scalars, dim3(1), dim3(kBlock), 0, s, nd, 1, part, det, rel);
-    hipLaunchKernelGGL(k_gap_step, grid, dim3(kBlock), 0, s, x, r, p, q, n, det, part);
+    hipLaunchKernelGGL(k_gap_step, grid, dim3(kBlock), 0, s, y, r, q, gaps, n, det, part);
     hipLaunchKernelGGL(k_gap_scalars, dim3(1), dim3(kBlock), 0, s, nd, 2, part, det, rel);
     hipLaunchKernelGGL(k_gap_dir, grid, dim3(kBlock), 0, s, p, r, n, det);
     FX_HIP(hipGetLastError());
@@ -245,9 +253,8 @@ furax_status gap_fill_impl(const furax_noise *C, const uint8_t *gaps, const T *d
     FX_HIP(hipStreamSynchronize(s));
     if (!(worst - worst == 0.0)) break;   // non-finite: stop, report it
   }
-  // y = N x (x is zero on the gaps), then the constrained realisation
-  FX_TRY(noise_run<double>(C, x, q, spec, s));
-  hipLaunchKernelGGL(k_gap_out<T>, dim3(ob), dim3(kBlock), 0, s, d, nr, gaps, q, S, out);
+  // the constrained realisation from the accumulated y_G = N_GV x
+  hipLaunchKernelGGL(k_gap_out<T>, dim3(ob), dim3(kBlock), 0, s, d, nr, gaps, y, S, out);
   FX_HIP(hipGetLastError());
   FX_HIP(hipStreamSynchronize(s));
   if (info) {
