@@ -117,7 +117,8 @@ typedef struct {
  *     detector's stream with its symmetric band of lags t[0..b-1],
  *         z[k,i] = sum_{|tau| <= b-1, 0 <= i+tau < n_samp} t_k[|tau|] y[k,i+tau],
  *     applied by overlap-save blocks with a real FFT (the paper's overlap-save
- *     method).  FP32 streams support b <= 8192, FP64 streams b <= 4096.
+ *     method).  Both precisions support b <= 8192 (FP64 with b > 4096 also needs
+ *     n_samp < 2^28, else FURAX_EUNSUPPORTED).
  *  kind 2 (template deprojection, Eq. (3) with TemplateOperator templates):
  *         z = F_T y,  F_T = W - W T (T^T W T)^-1 T^T W,  W = diag(inv_var[k]),
  *     where T holds, per detector and per segment of tmpl_seg_len samples
@@ -311,7 +312,7 @@ furax_status furax_template_fit(const furax_noise *N, int32_t dt, const void *to
  * samples G and valid samples V:
  *     out_G = n_G + N_GV N_VV^-1 (d_V - n_V),    out_V = d_V,
  * where N is the noise COVARIANCE described by C (kind 1: band-Toeplitz
- * autocorrelation lags c[0..b-1], b <= 4096, truncated at the stream's ends;
+ * autocorrelation lags c[0..b-1], b <= 8192, truncated at the stream's ends;
  * kind 0: white, then out_G = n_G) and n is an unconstrained realisation of
  * it drawn by the caller.  N_VV^-1 is applied by conjugate gradients on all
  * detectors at once (each with its own scalars), preconditioned by 1/c_k[0],

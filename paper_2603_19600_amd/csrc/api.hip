@@ -97,8 +97,7 @@ furax_status check_noise(const furax_noise *N, int64_t n_det, int64_t n_samp, in
     return set_error(FURAX_EINVAL, "toeplitz_stride must be 0 or bandwidth");
   const int64_t bmax = dt == FURAX_F32 ? os_max_band<float>() : os_max_band<double>();
   if (N->bandwidth > bmax)
-    return set_error(FURAX_EUNSUPPORTED, dt == FURAX_F32 ? "FP32 band-Toeplitz supports b <= 8192"
-                                                         : "FP64 band-Toeplitz supports b <= 4096");
+    return set_error(FURAX_EUNSUPPORTED, "band-Toeplitz supports b <= 8192");
   return FURAX_OK;
 }
 

@@ -431,12 +431,13 @@ __device__ __forceinline__ void twiddle16(C2<T> (&v)[16], C2<double> W1) {
 
 // ---------------------------------------------------------------------------
 // Register-resident overlap-save for the long blocks, M = 4096 RL (RL = 2 or
-// 4: FP64 M = 8192, FP32 M = 16384 or 8192).
+// 4: M = 8192 for b <= 4096, M = 16384 for 4096 < b <= 8192).
 //
-// 256 threads hold the whole packed block in registers (M / 256 = 32 or 64
-// complex values each) and use LDS only to exchange data between passes,
-// through a buffer of HALF the block (64 KB), in two rounds: so two
-// workgroups fit one CU and one's HBM traffic overlaps the other's FFT.
+// NT threads (256 for M = 8192, 512 for M = 16384) hold the whole packed
+// block in registers (32 complex values each) and use LDS only to exchange
+// data between passes, through a buffer of HALF the block (64 KB in FP64, 32
+// or 64 KB in FP32), in two rounds: so two or more workgroups fit one CU and
+// one's HBM traffic overlaps another's FFT.
 //   forward  : radix 16, 16, 16, RL   (spans Ns = 1, 16, 256, 4096)
 //   inverse  : radix RL, 16, 16, 16   (spans Ns = 1, RL, 16 RL, 256 RL)
 // The last forward pass gives thread t the butterflies j and 4096 - j
@@ -822,12 +823,12 @@ template <typename T>
 int os_half_length(int64_t b) {
   int64_t m = 512;
   while (m < 4 * (b - 1) && m < 8192) m *= 2;
-  if (sizeof(T) == 4 && b > 4096) m = 16384;
+  if (b > 4096) m = 16384;
   return (int)m;
 }
 
 template <typename T>
-int64_t os_max_band() { return sizeof(T) == 4 ? 8192 : 4096; }
+int64_t os_max_band() { return 8192; }
 template int64_t os_max_band<float>();
 template int64_t os_max_band<double>();
 
@@ -889,8 +890,13 @@ static furax_status launch_os_reg(const furax_noise *N, const T *in, T *out, con
   // 32-bit sample offsets inside the kernel, and output rows addressed as
   // buffers of fewer than 2^31 bytes
   if (N->n_samp + 4 * (int64_t)M >= ((int64_t)1 << 31) ||
-      N->n_samp * (int64_t)sizeof(T) >= ((int64_t)1 << 31))
-    return launch_os<T, M, M / 16>(N, in, out, spec, tw, s);
+      N->n_samp * (int64_t)sizeof(T) >= ((int64_t)1 << 31)) {
+    // the LDS kernel holds a whole block: an FP64 32768-sample block does not fit
+    if constexpr (sizeof(T) == 8 && M > 8192)
+      return set_error(FURAX_EUNSUPPORTED, "FP64 band above 4096 lags on streams of 2^28 samples or more");
+    else
+      return launch_os<T, M, M / 16>(N, in, out, spec, tw, s);
+  }
   hipLaunchKernelGGL((k_os_reg<T, M, NT>), dim3((unsigned)ntask), dim3(NT), 0, s, in, out,
                      N->n_samp, b, nblk, spec, spec_stride, tw);
   FX_HIP(hipGetLastError());
@@ -1102,8 +1108,7 @@ furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *sp
       if constexpr (sizeof(T) == 8) return launch_os_reg<T, 8192, kOsThreads64>(N, in, out, sp, t, s);
       else return launch_os_reg<T, 8192, kOsThreads32>(N, in, out, sp, t, s);
     case 16384:
-      if constexpr (sizeof(T) == 4) return launch_os<T, 16384, 1024>(N, in, out, sp, t, s);
-      break;
+      return launch_os_reg<T, 16384, 512>(N, in, out, sp, t, s);
   }
   return set_error(FURAX_EUNSUPPORTED, "no overlap-save instance for this band");
 }

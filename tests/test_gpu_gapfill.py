@@ -72,14 +72,14 @@ def test_gap_fill_white_and_trivial(fx):
 
 def test_gap_fill_argument_errors(fx):
     D = dev()
-    c = torch.ones(5000, dtype=torch.float64, device=D)
-    C = fx.Noise("band", 1, 6000, lags=c)            # b = 5000 > 4096
-    t = torch.zeros(1, 6000, dtype=torch.float64, device=D)
-    g = torch.zeros(1, 6000, dtype=torch.uint8, device=D)
+    c = torch.ones(8193, dtype=torch.float64, device=D)
+    C = fx.Noise("band", 1, 9000, lags=c)            # b = 8193 > 8192
+    t = torch.zeros(1, 9000, dtype=torch.float64, device=D)
+    g = torch.zeros(1, 9000, dtype=torch.uint8, device=D)
     with pytest.raises(fx.FuraxError) as e:
         fx.gap_fill(C, g, t, t)
     assert e.value.status in (fx.EINVAL, fx.EUNSUPPORTED)
-    T = fx.Noise("deproj", 1, 6000, inv_var=torch.ones(1, dtype=torch.float64, device=D),
+    T = fx.Noise("deproj", 1, 9000, inv_var=torch.ones(1, dtype=torch.float64, device=D),
                  seg_len=100, order=1)
     with pytest.raises(fx.FuraxError) as e:
         fx.gap_fill(T, g, t, t)

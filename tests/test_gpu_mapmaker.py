@@ -186,9 +186,9 @@ def test_pcg_breakdown_and_invalid_args(fx):
                                                                          device=dev())),
                        torch.from_numpy(d2).to(dev()))
     assert e.value.status == fx.EINVAL
-    too_wide = fx.Noise("band", 2, 5000, lags=torch.ones(4097, dtype=torch.float64, device=dev()))
+    too_wide = fx.Noise("band", 2, 9000, lags=torch.ones(8193, dtype=torch.float64, device=dev()))
     with pytest.raises(fx.FuraxError) as e:
-        fx.noise_apply(too_wide, torch.zeros(2, 5000, dtype=torch.float64, device=dev()))
+        fx.noise_apply(too_wide, torch.zeros(2, 9000, dtype=torch.float64, device=dev()))
     assert e.value.status == fx.EUNSUPPORTED
 
 

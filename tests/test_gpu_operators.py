@@ -174,7 +174,8 @@ def test_hits_bitexact_and_sum(fx):
 # ---------------------------------------------------------------- N^-1
 @pytest.mark.parametrize("n_samp,b", [(1, 1), (100, 1), (5000, 7), (40000, 129), (70001, 4096),
                                       (16384, 4096), (200_000, 1000), (50_001, 2500),
-                                      (8194, 4096)])
+                                      (8194, 4096), (100_000, 8192), (60_001, 6000),
+                                      (24_579, 4097)])
 def test_band_noise_f64(fx, n_samp, b):
     rng = np.random.default_rng(n_samp + b)
     y = rng.standard_normal((2, n_samp))
