@@ -175,7 +175,7 @@ def test_hits_bitexact_and_sum(fx):
 @pytest.mark.parametrize("n_samp,b", [(1, 1), (100, 1), (5000, 7), (40000, 129), (70001, 4096),
                                       (16384, 4096), (200_000, 1000), (50_001, 2500),
                                       (8194, 4096), (100_000, 8192), (60_001, 6000),
-                                      (24_579, 4097)])
+                                      (24_579, 4097), (5000, 4096), (9000, 8192)])
 def test_band_noise_f64(fx, n_samp, b):
     rng = np.random.default_rng(n_samp + b)
     y = rng.standard_normal((2, n_samp))
@@ -187,7 +187,7 @@ def test_band_noise_f64(fx, n_samp, b):
 
 
 @pytest.mark.parametrize("n_samp,b", [(5000, 7), (70001, 4096), (100_000, 8192), (3, 2),
-                                      (50_001, 2500)])
+                                      (50_001, 2500), (5000, 4096), (9000, 8192), (40_000, 4097)])
 def test_band_noise_f32(fx, n_samp, b):
     rng = np.random.default_rng(n_samp + b)
     y = rng.standard_normal((3, n_samp)).astype(np.float32)
