@@ -512,10 +512,10 @@ __device__ __forceinline__ void reg_xchg16(C2<T> *s, C2<T> (&v)[M / NT], int tid
     for (int r = 0; r < 8; ++r) v[16 * q + r] = tmp[8 * q + r];
 }
 
-// (the second launch bound is waves per SIMD: with 256 threads, two
-// workgroups per CU; 512-thread workgroups measured slower in both precisions)
+// (the second launch bound is waves per SIMD: two workgroups per CU; an FP64
+// workgroup of 512 threads holds the whole register file of its CU)
 template <typename T, int M, int NT>
-__global__ void __launch_bounds__(NT, NT / 128)
+__global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : NT / 128)
 k_os_reg(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, int64_t nblk,
          const T *__restrict__ spec, int64_t spec_stride, const C2<double> *__restrict__ tw) {
   constexpr int RL = M / 4096;
@@ -707,6 +707,253 @@ k_os_reg(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident overlap-save with four exchanges, M = 8192.
+//
+// The same block, threads and half-block LDS buffer as k_os_reg, but the
+// transform takes radices 32, 16, 16 (spans 1, 32, 512) forward and 16, 16,
+// 32 (spans 1, 16, 256) inverse: each thread's 32 values are one radix-32
+// butterfly in the first forward and last inverse pass.  The last forward
+// pass gives thread t the butterflies j and 512 - j (0 and 256 for t = 0),
+// whose outputs Z[j + 512 r] and Z[512 - j + 512 (15 - r)] are the pairs
+// (k, M - k) of the split, and the split's outputs are the inputs of those
+// two butterflies in the first inverse pass: four exchanges per block
+// instead of six.  Output r of a 32-point DFT sits at p32(r) (dft32), of a
+// 16-point one at p16(r).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ constexpr int p16(int r) { return 4 * (r & 3) + (r >> 2); }
+__device__ __forceinline__ constexpr int p32(int r) { return (r & 16) + p16(r & 15); }
+
+// a * W32^k (conjugated for the inverse), k in [0, 16)
+template <typename T, bool INV>
+__device__ __forceinline__ C2<T> rot32(C2<T> a, int k) {
+  // cos and sin of pi k / 16
+  constexpr double c[16] = {1.0,
+                            0.98078528040323044913, 0.92387953251128675613,
+                            0.83146961230254523708, 0.70710678118654752440,
+                            0.55557023301960222474, 0.38268343236508977173,
+                            0.19509032201612826785, 0.0,
+                            -0.19509032201612826785, -0.38268343236508977173,
+                            -0.55557023301960222474, -0.70710678118654752440,
+                            -0.83146961230254523708, -0.92387953251128675613,
+                            -0.98078528040323044913};
+  constexpr double sn[16] = {0.0,
+                             0.19509032201612826785, 0.38268343236508977173,
+                             0.55557023301960222474, 0.70710678118654752440,
+                             0.83146961230254523708, 0.92387953251128675613,
+                             0.98078528040323044913, 1.0,
+                             0.98078528040323044913, 0.92387953251128675613,
+                             0.83146961230254523708, 0.70710678118654752440,
+                             0.55557023301960222474, 0.38268343236508977173,
+                             0.19509032201612826785};
+  if (k == 0) return a;
+  if (k == 8) return INV ? C2<T>{-a.y, a.x} : C2<T>{a.y, -a.x};
+  const T sg = INV ? (T)1 : (T)-1;
+  return cmul(a, C2<T>{(T)c[k], sg * (T)sn[k]});
+}
+
+// In-place 32-point DFT of v[r] = input r: output r ends in v[p32(r)].
+template <typename T, bool INV>
+__device__ __forceinline__ void dft32(C2<T> (&v)[32]) {
+  C2<T> e[16], o[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    e[m] = v[2 * m];
+    o[m] = v[2 * m + 1];
+  }
+  dft16<T, INV>(e);
+  dft16<T, INV>(o);
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int k = (p >> 2) + 4 * (p & 3);   // e[p], o[p] hold output k of the halves
+    const C2<T> t = rot32<T, INV>(o[p], k);
+    v[p] = cadd(e[p], t);
+    v[16 + p] = csub(e[p], t);
+  }
+}
+
+// v[r] *= w^r, r = 0..31 (w = W1, conjugated for the inverse).
+template <typename T, bool INV>
+__device__ __forceinline__ void twiddle32(C2<T> (&v)[32], C2<double> W1) {
+  twiddle16<T, INV>(*reinterpret_cast<C2<T>(*)[16]>(v), W1);
+  twiddle16<T, INV>(*reinterpret_cast<C2<T>(*)[16]>(v + 16), W1);
+  const C2<double> W2 = cmul(W1, W1), W4 = cmul(W2, W2), W8 = cmul(W4, W4);
+  const C2<T> w16 = narrow<T>(cmul(W8, W8));
+#pragma unroll
+  for (int r = 16; r < 32; ++r) v[r] = twiddle<T, INV>(v[r], w16);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256, 2)
+k_os_r32(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, int64_t nblk,
+         const T *__restrict__ spec, int64_t spec_stride, const C2<double> *__restrict__ tw) {
+  constexpr int M = 8192, L = 2 * M, HALF = M / 2, NT = 256;
+  __shared__ C2<T> s[HALF + HALF / 16];
+  const int tid0 = threadIdx.x;
+  const int64_t det = (int64_t)blockIdx.x / nblk, blk = (int64_t)blockIdx.x - det * nblk;
+  const int V = L - 2 * (b - 1);
+  const int32_t s0 = (int32_t)(blk * V) - (b - 1);
+  C2<T> v[32];
+
+  // ---- forward pass 0 (radix 32, span 1): inputs z[t + 256 r] from HBM
+  {
+    const int tid = pinned_tid<T>(tid0);
+    const __amdgpu_buffer_rsrc_t xr = row_buffer(const_cast<T *>(in) + det * n, n);
+#pragma unroll
+    for (int r = 0; r < 32; ++r) {
+      const int32_t g = s0 + 2 * (tid + NT * r);
+      v[r].x = buf_load<T>(xr, g >= 0 ? (uint32_t)g * (uint32_t)sizeof(T) : kDropOffset);
+      v[r].y = buf_load<T>(xr, g + 1 >= 0 ? (uint32_t)(g + 1) * (uint32_t)sizeof(T) : kDropOffset);
+    }
+    dft32<T, false>(v);
+  }
+  // ---- exchange: element 32 t + r (half t / 128, chosen per wave) -> v[16 q + r]
+  // = element t + 256 q + 512 r (half r / 8)
+  {
+    const int tid = pinned_tid<T>(tid0);
+    const int hw = __builtin_amdgcn_readfirstlane(tid >> 7);
+    C2<T> nv[32];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (hw == h) {
+#pragma unroll
+        for (int r = 0; r < 32; ++r) s[pad16(32 * tid + r - h * HALF)] = v[p32(r)];
+      }
+      lds_barrier();
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 8 * h; r < 8 * h + 8; ++r)
+          nv[16 * q + r] = s[pad16(tid + NT * q + 512 * r - h * HALF)];
+      lds_barrier();
+    }
+#pragma unroll
+    for (int e = 0; e < 32; ++e) v[e] = nv[e];
+  }
+  // ---- forward pass 1 (radix 16, span 32)
+#pragma unroll
+  for (int q = 0; q < 2; ++q) reg_r16<T, M, false>(v + 16 * q, pinned_tid<T>(tid0) + NT * q, 32, tw);
+  // ---- exchange: butterfly j = t + 256 q writes (j - k) 16 + k + 32 r (k = j mod 32,
+  // half q) -> paired layout v[16 e + r] = element j_e + 512 r (half r / 8)
+  {
+    const int tid = pinned_tid<T>(tid0);
+    const int j1 = tid == 0 ? 256 : 512 - tid;
+    C2<T> nv[32];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      {
+        const int j = tid + NT * h, k = j & 31;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          s[pad16((j - k) * 16 + k + 32 * r - h * HALF)] = v[16 * h + p16(r)];
+      }
+      lds_barrier();
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int r = 8 * h; r < 8 * h + 8; ++r)
+          nv[16 * e + r] = s[pad16((e ? j1 : tid) + 512 * r - h * HALF)];
+      lds_barrier();
+    }
+#pragma unroll
+    for (int e = 0; e < 32; ++e) v[e] = nv[e];
+  }
+  // ---- forward pass 2 (radix 16, span 512) on butterflies j0 = t, j1; split and
+  // kernel multiply; inverse pass 0 (radix 16, span 1) on the same butterflies
+  const int tidp = pinned_tid<T>(tid0);
+  const int jp[2] = {tidp, tidp == 0 ? 256 : 512 - tidp};
+#pragma unroll
+  for (int e = 0; e < 2; ++e) reg_r16<T, M, false>(v + 16 * e, jp[e], 512, tw);
+  {
+    const C2<T> *AB = reinterpret_cast<const C2<T> *>(spec + det * spec_stride + spec_coef_off(M));
+    const bool z0 = tidp == 0;
+    C2<T> Z[2][16];
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) Z[e][r] = v[16 * e + p16(r)];
+    C2<T> X[2][16];
+    // partner of element j_e + 512 r: butterfly j_(1-e), output 15 - r; for
+    // t = 0 (j0 = 0, j1 = 256) each butterfly pairs with itself: output
+    // (16 - r) mod 16 of butterfly 0, output 15 - r of butterfly 256.  Outputs
+    // (0, r) and (1, 15 - r) use the same two values and are formed together.
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const C2<T> a = Z[0][r], c = Z[1][15 - r];
+      const C2<T> pa = z0 ? Z[0][(16 - r) & 15] : c;
+      const C2<T> pc = z0 ? Z[1][r] : a;
+      X[0][r] = split_mul<T>(a, pa, AB[jp[0] + 512 * r]);
+      X[1][15 - r] = split_mul<T>(c, pc, AB[jp[1] + 512 * (15 - r)]);
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      dft16<T, true>(X[e]);
+#pragma unroll
+      for (int m = 0; m < 16; ++m) v[16 * e + m] = X[e][m];   // output r of butterfly j_e at p16(r)
+    }
+  }
+  // ---- exchange: element 16 j_e + r (half e) -> v[16 q + r] = element t + 256 q + 512 r
+  {
+    const int tid = pinned_tid<T>(tid0);
+    const int j1 = tid == 0 ? 256 : 512 - tid;
+    C2<T> nv[32];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s[pad16(16 * (h ? j1 : tid) + r - h * HALF)] = v[16 * h + p16(r)];
+      lds_barrier();
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 8 * h; r < 8 * h + 8; ++r)
+          nv[16 * q + r] = s[pad16(tid + NT * q + 512 * r - h * HALF)];
+      lds_barrier();
+    }
+#pragma unroll
+    for (int e = 0; e < 32; ++e) v[e] = nv[e];
+  }
+  // ---- inverse pass 1 (radix 16, span 16)
+#pragma unroll
+  for (int q = 0; q < 2; ++q) reg_r16<T, M, true>(v + 16 * q, pinned_tid<T>(tid0) + NT * q, 16, tw);
+  // ---- exchange: butterfly j = t + 256 q writes (j - k) 16 + k + 16 r (k = j mod 16,
+  // half q) -> v[r] = element t + 256 r, r < 32 (half r / 16)
+  {
+    const int tid = pinned_tid<T>(tid0);
+    C2<T> nv[32];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      {
+        const int j = tid + NT * h, k = j & 15;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          s[pad16((j - k) * 16 + k + 16 * r - h * HALF)] = v[16 * h + p16(r)];
+      }
+      lds_barrier();
+#pragma unroll
+      for (int r = 16 * h; r < 16 * h + 16; ++r) nv[r] = s[pad16(tid + NT * r - h * HALF)];
+      lds_barrier();
+    }
+#pragma unroll
+    for (int e = 0; e < 32; ++e) v[e] = nv[e];
+  }
+  // ---- inverse pass 2 (radix 32, span 256): outputs element t + 256 r, to HBM
+  {
+    const int tid = pinned_tid<T>(tid0);
+    twiddle32<T, true>(v, tw[2 * tid]);
+    dft32<T, true>(v);
+    const __amdgpu_buffer_rsrc_t zr = row_buffer(out + det * n, n);
+    const int lo = b - 1, hi = b - 1 + V;
+#pragma unroll
+    for (int r = 0; r < 32; ++r) {
+      const C2<T> w = v[p32(r)];
+      const int e = 2 * (tid + NT * r);
+      buf_store(zr, e >= lo && e < hi ? (uint32_t)(s0 + e) * (uint32_t)sizeof(T) : kDropOffset, w.x);
+      buf_store(zr, e + 1 >= lo && e + 1 < hi ? (uint32_t)(s0 + e + 1) * (uint32_t)sizeof(T)
+                                              : kDropOffset, w.y);
+    }
+  }
+}
+
 // Spectrum of the symmetric circular kernel of length L = 2M, divided by M,
 // and the split coefficients of split_mul.  One wave per pair (k, M - k),
 // k = 0..M/2: since cos(2 pi (M - k) tau / L) = (-1)^tau cos(2 pi k tau / L),
@@ -875,9 +1122,23 @@ static furax_status launch_os(const furax_noise *N, const T *in, T *out, const T
   return FURAX_OK;
 }
 
-// Threads per workgroup of the register-resident overlap-save, per precision.
-constexpr int kOsThreads64 = 256;
-constexpr int kOsThreads32 = 256;
+template <typename T>
+static furax_status launch_os_r32(const furax_noise *N, const T *in, T *out, const T *spec,
+                                  const C2<double> *tw, hipStream_t s) {
+  constexpr int M = 8192;
+  const int b = (int)N->bandwidth;
+  const int64_t V = 2 * M - 2 * (int64_t)(b - 1);
+  const int64_t nblk = (N->n_samp + V - 1) / V;
+  const int64_t ntask = N->n_det * nblk;
+  const int64_t spec_stride = N->toeplitz_stride ? spec_block(M) : 0;
+  if (N->n_samp + 4 * (int64_t)M >= ((int64_t)1 << 31) ||
+      N->n_samp * (int64_t)sizeof(T) >= ((int64_t)1 << 31))
+    return launch_os<T, M, M / 16>(N, in, out, spec, tw, s);
+  hipLaunchKernelGGL((k_os_r32<T>), dim3((unsigned)ntask), dim3(256), 0, s, in, out, N->n_samp, b,
+                     nblk, spec, spec_stride, tw);
+  FX_HIP(hipGetLastError());
+  return FURAX_OK;
+}
 
 template <typename T, int M, int NT>
 static furax_status launch_os_reg(const furax_noise *N, const T *in, T *out, const T *spec,
@@ -1105,8 +1366,7 @@ furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *sp
     case 2048: return launch_os<T, 2048, 128>(N, in, out, sp, t, s);
     case 4096: return launch_os<T, 4096, 256>(N, in, out, sp, t, s);
     case 8192:
-      if constexpr (sizeof(T) == 8) return launch_os_reg<T, 8192, kOsThreads64>(N, in, out, sp, t, s);
-      else return launch_os_reg<T, 8192, kOsThreads32>(N, in, out, sp, t, s);
+      return launch_os_r32<T>(N, in, out, sp, t, s);
     case 16384:
       return launch_os_reg<T, 16384, 512>(N, in, out, sp, t, s);
   }
