@@ -783,8 +783,10 @@ __device__ __forceinline__ void twiddle32(C2<T> (&v)[32], C2<double> W1) {
   for (int r = 16; r < 32; ++r) v[r] = twiddle<T, INV>(v[r], w16);
 }
 
+// (FP32: registers for four waves per SIMD, LDS for four workgroups per CU;
+// FP64: two of each)
 template <typename T>
-__global__ void __launch_bounds__(256, 2)
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2)
 k_os_r32(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, int64_t nblk,
          const T *__restrict__ spec, int64_t spec_stride, const C2<double> *__restrict__ tw) {
   constexpr int M = 8192, L = 2 * M, HALF = M / 2, NT = 256;
