@@ -348,7 +348,11 @@ template furax_status sp_build_runs<double>(SpPlan &, const PtArgs<double> &, co
 // or, when null, the nested plane gives it.
 // ---------------------------------------------------------------------------
 constexpr int kSpThreads = 512;
-constexpr int kSlotBatch = 4;                 // slot blocks in flight per wave
+// Slot blocks in flight per wave: four, except two for FP64 quaternion
+// pointing, whose per-sample attitude product would otherwise take the
+// registers of a second workgroup per CU (156 VGPRs with four, 108 with two).
+template <typename T, bool QUAT>
+constexpr int slot_batch() { return QUAT && sizeof(T) == 8 ? 2 : 4; }
 constexpr int kHwpPeriodMax = 1024;           // tabulated HWP periods
 constexpr int kHwpTable = kHwpPeriodMax + (int)kMaxRun;
 
@@ -446,6 +450,7 @@ k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_
   if (threadIdx.x == 0) L.run.pre[ch.nr] = ch.w;
   __syncthreads();
 
+  constexpr int kSlotBatch = slot_batch<T, QUAT>();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int kWaves = kSpThreads / 64;
   const int32_t base = ch.sp << log2P;
