@@ -9,11 +9,14 @@
 // input samples of one detector (zero outside the detector's stream) and
 // produces the V = L - 2(b-1) outputs whose stencil lies inside the block.
 // The real block is packed as M complex values (even samples -> real part,
-// odd -> imaginary), transformed by a Stockham radix-4 FFT of length M held in
-// LDS (128 KB for M = 16384 FP32 or M = 8192 FP64), split into the length-L
-// real spectrum, multiplied by the kernel's spectrum -- which is real because
-// the kernel is symmetric -- re-packed and transformed back.  The split,
-// multiply and re-pack are one pass over (k, M-k) pairs.
+// odd -> imaginary), transformed by a Stockham FFT of length M, split into the
+// length-L real spectrum, multiplied by the kernel's spectrum -- which is real
+// because the kernel is symmetric -- re-packed and transformed back.  The
+// split, multiply and re-pack are one 2x2 real mixing of each (k, M-k) pair.
+// Three kernels: k_os_r32 (M = 8192, the block in registers, radices 32, 16,
+// 16), k_os_reg (M = 16384, the block in registers, radix 16) and
+// k_overlap_save (M <= 4096, and streams too long for 32-bit offsets: the
+// block in LDS).
 #include <map>
 #include <mutex>
 #include <utility>
