@@ -109,7 +109,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nside512_256x2p20_band409
 # kernels making up each phase, by rocprofv3 kernel name ({T}: double or float)
 PHASE_KERNELS = {
     "apply": ["fx::k_apply<{T}, {T}, true, false>"],
-    "noise": ["fx::k_os_r32<{T}>", "fx::k_os_reg<{T}, ", "fx::k_overlap_save<{T}, "],
+    "noise": ["fx::k_os_r32x<{T}>", "fx::k_os_r32<{T}>", "fx::k_overlap_save<{T}, "],
     "transpose": ["fx::k_sp_accum<{T}, 0, false>", "fx::k_sp_reduce"],
 }
 

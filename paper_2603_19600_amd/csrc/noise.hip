@@ -14,7 +14,7 @@
 // because the kernel is symmetric -- re-packed and transformed back.  The
 // split, multiply and re-pack are one 2x2 real mixing of each (k, M-k) pair.
 // Three kernels: k_os_r32 (M = 8192, the block in registers, radices 32, 16,
-// 16), k_os_reg (M = 16384, the block in registers, radix 16) and
+// 16), k_os_r32x (M = 16384, the block in registers, radices 32, 32, 16) and
 // k_overlap_save (M <= 4096, and streams too long for 32-bit offsets: the
 // block in LDS).
 #include <map>
@@ -433,27 +433,17 @@ __device__ __forceinline__ void twiddle16(C2<T> (&v)[16], C2<double> W1) {
 }
 
 // ---------------------------------------------------------------------------
-// Register-resident overlap-save for the long blocks, M = 4096 RL (RL = 2 or
-// 4: M = 8192 for b <= 4096, M = 16384 for 4096 < b <= 8192).
+// Register-resident overlap-save for the long blocks (M = 8192 and 16384).
 //
 // NT threads (256 for M = 8192, 512 for M = 16384) hold the whole packed
 // block in registers (32 complex values each) and use LDS only to exchange
 // data between passes, through a buffer of HALF the block (64 KB in FP64, 32
 // or 64 KB in FP32), in two rounds: so two or more workgroups fit one CU and
-// one's HBM traffic overlaps another's FFT.
-//   forward  : radix 16, 16, 16, RL   (spans Ns = 1, 16, 256, 4096)
-//   inverse  : radix RL, 16, 16, 16   (spans Ns = 1, RL, 16 RL, 256 RL)
-// The last forward pass gives thread t the butterflies j and 4096 - j
-// (j = t + 256 i), whose outputs Z[j + 4096 r] and Z[4096 - j + 4096 r'] are
-// exactly the pairs (k, M - k) that the real-spectrum split needs, and the
-// split's outputs are exactly the inputs of those two butterflies in the
-// first inverse pass (radix RL, span 1): split, kernel multiply and that pass
-// run in registers with no exchange.  The first forward pass reads its inputs
-// from HBM and the last inverse pass writes its outputs there.  Every
-// exchange is static in which half a value travels: a radix-16 butterfly's
-// outputs lie in the lower half iff j < M/32, and a radix-16 pass's inputs
-// j + r M/16 iff r < 8.  Twiddles come from the FP64 table tw[j] =
-// exp(-2 pi i j / L) (L2-resident), one lookup per butterfly and pass.
+// one's HBM traffic overlaps another's FFT.  The first forward pass reads its
+// inputs from HBM and the last inverse pass writes its outputs there.  Every
+// exchange is static in which half a value travels.  Twiddles come from the
+// FP64 table tw[j] = exp(-2 pi i j / L) (L2-resident), one lookup per
+// butterfly and pass.
 // ---------------------------------------------------------------------------
 
 // Radix-16 butterfly q (j = tid + q NT) of a pass of span Ns, on v[16 q ..]:
@@ -466,256 +456,11 @@ __device__ __forceinline__ void reg_r16(C2<T> *v, int j, int Ns, const C2<double
   dft16<T, INV>(*reinterpret_cast<C2<T>(*)[16]>(v));
 }
 
-// Exchange after a radix-16 pass of span Ns (Ns divides M/32) into the layout
-// of the next radix-16 pass: v[16 q + r] = element j + r M/16.
-template <typename T, int M, int NT>
-__device__ __forceinline__ void reg_write16(C2<T> *s, const C2<T> (&v)[M / NT], int tid, int Ns,
-                                            int h) {
-  constexpr int B16 = M / 16 / NT, HALF = M / 2;
-  // butterflies j < M/32 (q < B16/2, or with one butterfly per thread the
-  // threads below NT/2) have all 16 outputs in the lower half
-#pragma unroll
-  for (int q = 0; q < B16; ++q) {
-    if constexpr (B16 >= 2) {
-      if ((q < B16 / 2) != (h == 0)) continue;
-    } else {
-      if ((tid < NT / 2) != (h == 0)) continue;
-    }
-    const int j = tid + q * NT, k = j & (Ns - 1);
-    const int d = (j - k) * 16 + k - h * HALF;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) s[pad16(d + r * Ns)] = v[16 * q + 4 * (r & 3) + (r >> 2)];
-  }
-}
-
-template <typename T, int M, int NT>
-__device__ __forceinline__ void reg_xchg16(C2<T> *s, C2<T> (&v)[M / NT], int tid_, int Ns) {
-  constexpr int NB16 = M / 16, B16 = NB16 / NT, HALF = M / 2;
-  const int tid = pinned_tid<T>(tid_);
-  C2<T> tmp[M / NT / 2];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    reg_write16<T, M, NT>(s, v, tid, Ns, h);
-    lds_barrier();
-#pragma unroll
-    for (int q = 0; q < B16; ++q) {
-      const int j = tid + q * NT;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const C2<T> e = s[pad16(j + (8 * h + r) * NB16 - h * HALF)];
-        if (h == 0) tmp[8 * q + r] = e;
-        else v[16 * q + 8 + r] = e;
-      }
-    }
-    lds_barrier();
-  }
-#pragma unroll
-  for (int q = 0; q < B16; ++q)
-#pragma unroll
-    for (int r = 0; r < 8; ++r) v[16 * q + r] = tmp[8 * q + r];
-}
-
-// (the second launch bound is waves per SIMD: two workgroups per CU; an FP64
-// workgroup of 512 threads holds the whole register file of its CU)
-template <typename T, int M, int NT>
-__global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : NT / 128)
-k_os_reg(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, int64_t nblk,
-         const T *__restrict__ spec, int64_t spec_stride, const C2<double> *__restrict__ tw) {
-  constexpr int RL = M / 4096;
-  static_assert(RL == 2 || RL == 4, "M = 8192 or 16384");
-  constexpr int L = 2 * M, HALF = M / 2, NB16 = M / 16, B16 = NB16 / NT, NPT = M / NT;
-  constexpr int NP = 2048 / NT;   // butterfly pairs of the last forward pass per thread
-  static_assert(B16 >= 1 && NPT == 2 * NP * RL, "whole butterflies per thread");
-  __shared__ C2<T> s[HALF + HALF / 16];
-  const int tid0 = threadIdx.x, tid = tid0;
-  const int64_t det = (int64_t)blockIdx.x / nblk, blk = (int64_t)blockIdx.x - det * nblk;
-  const int V = L - 2 * (b - 1);
-  // sample offsets within a detector's stream are 32-bit (the launcher checks
-  // n + L < 2^31), so each access is a uniform base plus one 32-bit offset
-  const int32_t s0 = (int32_t)(blk * V) - (b - 1);
-  C2<T> v[NPT];
-
-  // ---- forward pass 0 (radix 16, span 1) straight from HBM
-  {
-    // the detector's input row as a buffer: reads past its end, and the reads
-    // before its start (given kDropOffset), return zero, which is the zero
-    // padding of the first and last blocks
-    const __amdgpu_buffer_rsrc_t xr = row_buffer(const_cast<T *>(in) + det * n, n);
-#pragma unroll
-    for (int q = 0; q < B16; ++q)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int32_t g = s0 + 2 * (tid + q * NT + r * NB16);
-        v[16 * q + r].x = buf_load<T>(xr, g >= 0 ? (uint32_t)g * (uint32_t)sizeof(T) : kDropOffset);
-        v[16 * q + r].y =
-            buf_load<T>(xr, g + 1 >= 0 ? (uint32_t)(g + 1) * (uint32_t)sizeof(T) : kDropOffset);
-      }
-#pragma unroll
-    for (int q = 0; q < B16; ++q) reg_r16<T, M, false>(v + 16 * q, pinned_tid<T>(tid0) + q * NT, 1, tw);
-  }
-  reg_xchg16<T, M, NT>(s, v, tid, 1);
-  // ---- forward pass 1 (span 16), exchange
-#pragma unroll
-  for (int q = 0; q < B16; ++q) reg_r16<T, M, false>(v + 16 * q, pinned_tid<T>(tid0) + q * NT, 16, tw);
-  reg_xchg16<T, M, NT>(s, v, tid, 16);
-  // ---- forward pass 2 (span 256), exchange into the paired layout of pass 3:
-  // v[(2 i + h) RL + r] = element jh_i + 4096 r, j0 = tid + 256 i, j1 = 4096 - j0
-  // (2048 for j0 = 0)
-#pragma unroll
-  for (int q = 0; q < B16; ++q) reg_r16<T, M, false>(v + 16 * q, pinned_tid<T>(tid0) + q * NT, 256, tw);
-  {
-    const int tid = pinned_tid<T>(tid0);
-    C2<T> tmp[NPT / 2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      reg_write16<T, M, NT>(s, v, tid, 256, h);
-      lds_barrier();
-#pragma unroll
-      for (int i = 0; i < NP; ++i) {
-        const int j0 = tid + NT * i;
-        const int j1 = j0 == 0 ? 2048 : 4096 - j0;
-#pragma unroll
-        for (int e = 0; e < 2; ++e)
-#pragma unroll
-          for (int r = h * RL / 2; r < (h + 1) * RL / 2; ++r) {
-            const C2<T> val = s[pad16((e ? j1 : j0) + 4096 * r - h * HALF)];
-            if (h == 0) tmp[(2 * i + e) * (RL / 2) + r] = val;
-            else v[(2 * i + e) * RL + r] = val;
-          }
-      }
-      lds_barrier();
-    }
-#pragma unroll
-    for (int i = 0; i < NP; ++i)
-#pragma unroll
-      for (int e = 0; e < 2; ++e)
-#pragma unroll
-        for (int r = 0; r < RL / 2; ++r) v[(2 * i + e) * RL + r] = tmp[(2 * i + e) * (RL / 2) + r];
-  }
-  // ---- forward pass 3 (radix RL, span 4096), split + kernel multiply, inverse
-  // pass 0 (radix RL, span 1), all in registers
-  const C2<T> *AB = reinterpret_cast<const C2<T> *>(spec + det * spec_stride + spec_coef_off(M));
-#pragma unroll
-  for (int i = 0; i < NP; ++i) {
-    const int j0 = tid + NT * i;
-    const int j1 = j0 == 0 ? 2048 : 4096 - j0;
-    C2<T> Z[2][RL];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      C2<T> *w = v + (2 * i + e) * RL;
-      const C2<double> W1 = tw[2 * (e ? j1 : j0)];   // exp(-2 pi i j / M)
-      if constexpr (RL == 2) {
-        const C2<T> b1 = twiddle<T, false>(w[1], narrow<T>(W1));
-        Z[e][0] = cadd(w[0], b1);
-        Z[e][1] = csub(w[0], b1);
-      } else {
-        const C2<double> W2 = cmul(W1, W1), W3 = cmul(W1, W2);
-        C2<T> a0 = w[0], a1 = twiddle<T, false>(w[1], narrow<T>(W1));
-        C2<T> a2 = twiddle<T, false>(w[2], narrow<T>(W2)), a3 = twiddle<T, false>(w[3], narrow<T>(W3));
-        dft4<T, false>(a0, a1, a2, a3);
-        Z[e][0] = a0;
-        Z[e][1] = a1;
-        Z[e][2] = a2;
-        Z[e][3] = a3;
-      }
-    }
-    // element index of Z[e][r] is (e ? j1 : j0) + 4096 r; its partner M - that
-    // sits at Z[1 - e][RL - 1 - r], except in the pair j0 = 0, j1 = 2048,
-    // where Z[0][r] pairs with Z[0][(RL - r) % RL] and Z[1][r] with Z[1][RL - 1 - r]
-    const bool z0 = j0 == 0;
-    C2<T> X[2][RL];
-#pragma unroll
-    for (int e = 0; e < 2; ++e)
-#pragma unroll
-      for (int r = 0; r < RL; ++r) {
-        const int a = (e ? j1 : j0) + 4096 * r;
-        const C2<T> zb = (z0 && e == 0) ? Z[0][(RL - r) % RL] : Z[1 - e][RL - 1 - r];
-        const C2<T> zb0 = (z0 && e == 1) ? Z[1][RL - 1 - r] : zb;
-        X[e][r] = split_mul<T>(Z[e][r], zb0, AB[a]);
-      }
-    // inverse pass 0: radix RL, span 1 (no twiddles), in place
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      C2<T> *w = v + (2 * i + e) * RL;
-      if constexpr (RL == 2) {
-        w[0] = cadd(X[e][0], X[e][1]);
-        w[1] = csub(X[e][0], X[e][1]);
-      } else {
-        C2<T> a0 = X[e][0], a1 = X[e][1], a2 = X[e][2], a3 = X[e][3];
-        dft4<T, true>(a0, a1, a2, a3);
-        w[0] = a0;
-        w[1] = a1;
-        w[2] = a2;
-        w[3] = a3;
-      }
-    }
-  }
-  // ---- exchange: inverse pass 0 outputs (butterfly j at RL j + r; j0 < 2048
-  // in the lower half, j1 >= 2048 in the upper) -> radix-16 layout
-  {
-    const int tid = pinned_tid<T>(tid0);
-    C2<T> tmp[NPT / 2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-#pragma unroll
-      for (int i = 0; i < NP; ++i) {
-        const int j0 = tid + NT * i;
-        const int j = h == 0 ? j0 : (j0 == 0 ? 2048 : 4096 - j0);
-#pragma unroll
-        for (int r = 0; r < RL; ++r) s[pad16(RL * j + r - h * HALF)] = v[(2 * i + h) * RL + r];
-      }
-      lds_barrier();
-#pragma unroll
-      for (int q = 0; q < B16; ++q) {
-        const int j = tid + q * NT;
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const C2<T> e = s[pad16(j + (8 * h + r) * NB16 - h * HALF)];
-          if (h == 0) tmp[8 * q + r] = e;
-          else v[16 * q + 8 + r] = e;
-        }
-      }
-      lds_barrier();
-    }
-#pragma unroll
-    for (int q = 0; q < B16; ++q)
-#pragma unroll
-      for (int r = 0; r < 8; ++r) v[16 * q + r] = tmp[8 * q + r];
-  }
-  // ---- inverse passes 1 (span RL) and 2 (span 16 RL)
-#pragma unroll
-  for (int q = 0; q < B16; ++q) reg_r16<T, M, true>(v + 16 * q, pinned_tid<T>(tid0) + q * NT, RL, tw);
-  reg_xchg16<T, M, NT>(s, v, tid, RL);
-#pragma unroll
-  for (int q = 0; q < B16; ++q) reg_r16<T, M, true>(v + 16 * q, pinned_tid<T>(tid0) + q * NT, 16 * RL, tw);
-  reg_xchg16<T, M, NT>(s, v, tid, 16 * RL);
-  // ---- inverse pass 3 (span M/16): outputs j + r M/16, straight to HBM
-  // the detector's output row as a buffer of n values: stores past its end and
-  // the overlap outputs (given kDropOffset) are dropped by the hardware, so
-  // the stores need no branches
-  const __amdgpu_buffer_rsrc_t zr = row_buffer(out + det * n, n);
-  const int lo = b - 1, hi = b - 1 + V;
-#pragma unroll
-  for (int q = 0; q < B16; ++q) {
-    const int j = pinned_tid<T>(tid0) + q * NT;
-    reg_r16<T, M, true>(v + 16 * q, j, NB16, tw);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const C2<T> w = v[16 * q + 4 * (r & 3) + (r >> 2)];
-      const int e = 2 * (j + r * NB16);
-      buf_store(zr, e >= lo && e < hi ? (uint32_t)(s0 + e) * (uint32_t)sizeof(T) : kDropOffset, w.x);
-      buf_store(zr, e + 1 >= lo && e + 1 < hi ? (uint32_t)(s0 + e + 1) * (uint32_t)sizeof(T)
-                                              : kDropOffset, w.y);
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Register-resident overlap-save with four exchanges, M = 8192.
 //
-// The same block, threads and half-block LDS buffer as k_os_reg, but the
-// transform takes radices 32, 16, 16 (spans 1, 32, 512) forward and 16, 16,
-// 32 (spans 1, 16, 256) inverse: each thread's 32 values are one radix-32
+// 256 threads; the transform takes radices 32, 16, 16 (spans 1, 32, 512)
+// forward and 16, 16, 32 (spans 1, 16, 256) inverse: each thread's 32 values are one radix-32
 // butterfly in the first forward and last inverse pass.  The last forward
 // pass gives thread t the butterflies j and 512 - j (0 and 256 for t = 0),
 // whose outputs Z[j + 512 r] and Z[512 - j + 512 (15 - r)] are the pairs
@@ -959,6 +704,182 @@ k_os_r32(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same four-exchange scheme for M = 16384 (32768-sample blocks): 512
+// threads of 32 values, radices 32, 32, 16 forward (spans 1, 32, 1024) and
+// 16, 32, 32 inverse (spans 1, 16, 512).  The last forward pass pairs
+// butterflies j and 1024 - j (0 and 512 for thread 0).  Three of the four
+// exchanges move a whole radix-32 butterfly per thread in one round (its 32
+// outputs fall in one half, chosen per wave).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 2)
+k_os_r32x(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, int64_t nblk,
+          const T *__restrict__ spec, int64_t spec_stride, const C2<double> *__restrict__ tw) {
+  constexpr int M = 16384, L = 2 * M, HALF = M / 2, NT = 512;
+  __shared__ C2<T> s[HALF + HALF / 16];
+  const int tid0 = threadIdx.x;
+  const int64_t det = (int64_t)blockIdx.x / nblk, blk = (int64_t)blockIdx.x - det * nblk;
+  const int V = L - 2 * (b - 1);
+  const int32_t s0 = (int32_t)(blk * V) - (b - 1);
+  C2<T> v[32];
+
+  // ---- forward pass 0 (radix 32, span 1): inputs z[t + 512 r] from HBM
+  {
+    const int tid = pinned_tid<T>(tid0);
+    const __amdgpu_buffer_rsrc_t xr = row_buffer(const_cast<T *>(in) + det * n, n);
+#pragma unroll
+    for (int r = 0; r < 32; ++r) {
+      const int32_t g = s0 + 2 * (tid + NT * r);
+      v[r].x = buf_load<T>(xr, g >= 0 ? (uint32_t)g * (uint32_t)sizeof(T) : kDropOffset);
+      v[r].y = buf_load<T>(xr, g + 1 >= 0 ? (uint32_t)(g + 1) * (uint32_t)sizeof(T) : kDropOffset);
+    }
+    dft32<T, false>(v);
+  }
+  // ---- exchange: element 32 t + r (half t / 256) -> v[r] = element t + 512 r (half r / 16)
+  {
+    const int tid = pinned_tid<T>(tid0);
+    const int hw = __builtin_amdgcn_readfirstlane(tid >> 8);
+    C2<T> nv[32];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (hw == h) {
+#pragma unroll
+        for (int r = 0; r < 32; ++r) s[pad16(32 * tid + r - h * HALF)] = v[p32(r)];
+      }
+      lds_barrier();
+#pragma unroll
+      for (int r = 16 * h; r < 16 * h + 16; ++r) nv[r] = s[pad16(tid + NT * r - h * HALF)];
+      lds_barrier();
+    }
+#pragma unroll
+    for (int e = 0; e < 32; ++e) v[e] = nv[e];
+  }
+  // ---- forward pass 1 (radix 32, span 32): twiddles w^r, w = tw[32 k], k = t mod 32
+  {
+    const int tid = pinned_tid<T>(tid0);
+    twiddle32<T, false>(v, tw[32 * (tid & 31)]);
+    dft32<T, false>(v);
+  }
+  // ---- exchange: butterfly t writes (t - k) 32 + k + 32 r (k = t mod 32; half
+  // t / 256) -> paired layout v[16 e + r] = element j_e + 1024 r (half r / 8)
+  {
+    const int tid = pinned_tid<T>(tid0);
+    const int hw = __builtin_amdgcn_readfirstlane(tid >> 8);
+    const int j1 = tid == 0 ? 512 : 1024 - tid;
+    const int k = tid & 31;
+    C2<T> nv[32];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (hw == h) {
+#pragma unroll
+        for (int r = 0; r < 32; ++r) s[pad16((tid - k) * 32 + k + 32 * r - h * HALF)] = v[p32(r)];
+      }
+      lds_barrier();
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int r = 8 * h; r < 8 * h + 8; ++r)
+          nv[16 * e + r] = s[pad16((e ? j1 : tid) + 1024 * r - h * HALF)];
+      lds_barrier();
+    }
+#pragma unroll
+    for (int e = 0; e < 32; ++e) v[e] = nv[e];
+  }
+  // ---- forward pass 2 (radix 16, span 1024) on j0 = t, j1; split and kernel
+  // multiply; inverse pass 0 (radix 16, span 1) on the same butterflies
+  const int tidp = pinned_tid<T>(tid0);
+  const int jp[2] = {tidp, tidp == 0 ? 512 : 1024 - tidp};
+#pragma unroll
+  for (int e = 0; e < 2; ++e) reg_r16<T, M, false>(v + 16 * e, jp[e], 1024, tw);
+  {
+    const C2<T> *AB = reinterpret_cast<const C2<T> *>(spec + det * spec_stride + spec_coef_off(M));
+    const bool z0 = tidp == 0;
+    C2<T> Z[2][16];
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) Z[e][r] = v[16 * e + p16(r)];
+    C2<T> X[2][16];
+    // partner of element j_e + 1024 r: butterfly j_(1-e), output 15 - r; for
+    // t = 0 (j0 = 0, j1 = 512) each butterfly pairs with itself
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const C2<T> a = Z[0][r], c = Z[1][15 - r];
+      const C2<T> pa = z0 ? Z[0][(16 - r) & 15] : c;
+      const C2<T> pc = z0 ? Z[1][r] : a;
+      X[0][r] = split_mul<T>(a, pa, AB[jp[0] + 1024 * r]);
+      X[1][15 - r] = split_mul<T>(c, pc, AB[jp[1] + 1024 * (15 - r)]);
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      dft16<T, true>(X[e]);
+#pragma unroll
+      for (int m = 0; m < 16; ++m) v[16 * e + m] = X[e][m];
+    }
+  }
+  // ---- exchange: element 16 j_e + r (half e) -> v[r] = element t + 512 r (half r / 16)
+  {
+    const int tid = pinned_tid<T>(tid0);
+    const int j1 = tid == 0 ? 512 : 1024 - tid;
+    C2<T> nv[32];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s[pad16(16 * (h ? j1 : tid) + r - h * HALF)] = v[16 * h + p16(r)];
+      lds_barrier();
+#pragma unroll
+      for (int r = 16 * h; r < 16 * h + 16; ++r) nv[r] = s[pad16(tid + NT * r - h * HALF)];
+      lds_barrier();
+    }
+#pragma unroll
+    for (int e = 0; e < 32; ++e) v[e] = nv[e];
+  }
+  // ---- inverse pass 1 (radix 32, span 16): w = tw[64 k], k = t mod 16
+  {
+    const int tid = pinned_tid<T>(tid0);
+    twiddle32<T, true>(v, tw[64 * (tid & 15)]);
+    dft32<T, true>(v);
+  }
+  // ---- exchange: butterfly t writes (t - k) 32 + k + 16 r (k = t mod 16; half
+  // t / 256) -> v[r] = element t + 512 r (half r / 16)
+  {
+    const int tid = pinned_tid<T>(tid0);
+    const int hw = __builtin_amdgcn_readfirstlane(tid >> 8);
+    const int k = tid & 15;
+    C2<T> nv[32];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (hw == h) {
+#pragma unroll
+        for (int r = 0; r < 32; ++r) s[pad16((tid - k) * 32 + k + 16 * r - h * HALF)] = v[p32(r)];
+      }
+      lds_barrier();
+#pragma unroll
+      for (int r = 16 * h; r < 16 * h + 16; ++r) nv[r] = s[pad16(tid + NT * r - h * HALF)];
+      lds_barrier();
+    }
+#pragma unroll
+    for (int e = 0; e < 32; ++e) v[e] = nv[e];
+  }
+  // ---- inverse pass 2 (radix 32, span 512): outputs element t + 512 r, to HBM
+  {
+    const int tid = pinned_tid<T>(tid0);
+    twiddle32<T, true>(v, tw[2 * tid]);
+    dft32<T, true>(v);
+    const __amdgpu_buffer_rsrc_t zr = row_buffer(out + det * n, n);
+    const int lo = b - 1, hi = b - 1 + V;
+#pragma unroll
+    for (int r = 0; r < 32; ++r) {
+      const C2<T> w = v[p32(r)];
+      const int e = 2 * (tid + NT * r);
+      buf_store(zr, e >= lo && e < hi ? (uint32_t)(s0 + e) * (uint32_t)sizeof(T) : kDropOffset, w.x);
+      buf_store(zr, e + 1 >= lo && e + 1 < hi ? (uint32_t)(s0 + e + 1) * (uint32_t)sizeof(T)
+                                              : kDropOffset, w.y);
+    }
+  }
+}
+
 // Spectrum of the symmetric circular kernel of length L = 2M, divided by M,
 // and the split coefficients of split_mul.  One wave per pair (k, M - k),
 // k = 0..M/2: since cos(2 pi (M - k) tau / L) = (-1)^tau cos(2 pi k tau / L),
@@ -1066,16 +987,26 @@ void release_twiddles() {
   g_tw.clear();
 }
 
-// FFT half-length M used for a band of b lags in precision T: the smallest
-// power of two with M >= 4 (b - 1) (at most a quarter of each block is
-// halo), capped at 8192, the register-resident kernel's length -- for b up to
-// 4096 its two blocks per CU beat a longer block with fewer wasted outputs,
-// also in FP32 (measured).  Wider FP32 bands take one 16384-point block per CU.
+// The register-resident kernels take 32-bit sample offsets (n + 4M < 2^31)
+// and address each row as a buffer of fewer than 2^31 bytes.
 template <typename T>
-int os_half_length(int64_t b) {
+static bool os_reg_fits(int64_t n_samp, int64_t M) {
+  return n_samp + 4 * M < ((int64_t)1 << 31) && n_samp * (int64_t)sizeof(T) < ((int64_t)1 << 31);
+}
+
+// FFT half-length M used for noise model N in precision T: the smallest power
+// of two with M >= 4 (b - 1) (at most a quarter of each block is halo),
+// capped at 8192; 16384 above 3072 lags, where the longer block's smaller
+// halo outweighs its slower transform (measured crossover near 3000 lags in
+// both precisions).  A stream too long for the register kernels' 32-bit
+// offsets keeps M = 8192 up to 4096 lags, where the LDS kernel can take an
+// FP64 block.
+template <typename T>
+int os_half_length(const furax_noise *N) {
+  const int64_t b = N->bandwidth;
   int64_t m = 512;
   while (m < 4 * (b - 1) && m < 8192) m *= 2;
-  if (b > 4096) m = 16384;
+  if (b > 4096 || (b > 3072 && os_reg_fits<T>(N->n_samp, 16384))) m = 16384;
   return (int)m;
 }
 
@@ -1088,7 +1019,7 @@ template int64_t os_max_band<double>();
 template <typename T>
 size_t noise_workspace_bytes(const furax_noise *N) {
   if (N->kind != 1) return 0;
-  const int M = os_half_length<T>(N->bandwidth);
+  const int M = os_half_length<T>(N);
   const int64_t nk = N->toeplitz_stride ? N->n_det : 1;
   return (size_t)nk * spec_block(M) * sizeof(T);
 }
@@ -1099,7 +1030,7 @@ template size_t noise_workspace_bytes<double>(const furax_noise *);
 template <typename T>
 furax_status noise_prepare(const furax_noise *N, void *spec, hipStream_t s) {
   if (N->kind != 1) return FURAX_OK;
-  const int M = os_half_length<T>(N->bandwidth);
+  const int M = os_half_length<T>(N);
   TwTables tw;
   FX_TRY(get_twiddles(2 * M, s, tw));
   const int64_t nk = N->toeplitz_stride ? N->n_det : 1;
@@ -1136,35 +1067,31 @@ static furax_status launch_os_r32(const furax_noise *N, const T *in, T *out, con
   const int64_t nblk = (N->n_samp + V - 1) / V;
   const int64_t ntask = N->n_det * nblk;
   const int64_t spec_stride = N->toeplitz_stride ? spec_block(M) : 0;
-  if (N->n_samp + 4 * (int64_t)M >= ((int64_t)1 << 31) ||
-      N->n_samp * (int64_t)sizeof(T) >= ((int64_t)1 << 31))
-    return launch_os<T, M, M / 16>(N, in, out, spec, tw, s);
+  if (!os_reg_fits<T>(N->n_samp, M)) return launch_os<T, M, M / 16>(N, in, out, spec, tw, s);
   hipLaunchKernelGGL((k_os_r32<T>), dim3((unsigned)ntask), dim3(256), 0, s, in, out, N->n_samp, b,
                      nblk, spec, spec_stride, tw);
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }
 
-template <typename T, int M, int NT>
-static furax_status launch_os_reg(const furax_noise *N, const T *in, T *out, const T *spec,
-                                  const C2<double> *tw, hipStream_t s) {
+template <typename T>
+static furax_status launch_os_r32x(const furax_noise *N, const T *in, T *out, const T *spec,
+                                   const C2<double> *tw, hipStream_t s) {
+  constexpr int M = 16384;
   const int b = (int)N->bandwidth;
   const int64_t V = 2 * M - 2 * (int64_t)(b - 1);
   const int64_t nblk = (N->n_samp + V - 1) / V;
   const int64_t ntask = N->n_det * nblk;
   const int64_t spec_stride = N->toeplitz_stride ? spec_block(M) : 0;
-  // 32-bit sample offsets inside the kernel, and output rows addressed as
-  // buffers of fewer than 2^31 bytes
-  if (N->n_samp + 4 * (int64_t)M >= ((int64_t)1 << 31) ||
-      N->n_samp * (int64_t)sizeof(T) >= ((int64_t)1 << 31)) {
+  if (!os_reg_fits<T>(N->n_samp, M)) {
     // the LDS kernel holds a whole block: an FP64 32768-sample block does not fit
-    if constexpr (sizeof(T) == 8 && M > 8192)
+    if constexpr (sizeof(T) == 8)
       return set_error(FURAX_EUNSUPPORTED, "FP64 band above 4096 lags on streams of 2^28 samples or more");
     else
       return launch_os<T, M, M / 16>(N, in, out, spec, tw, s);
   }
-  hipLaunchKernelGGL((k_os_reg<T, M, NT>), dim3((unsigned)ntask), dim3(NT), 0, s, in, out,
-                     N->n_samp, b, nblk, spec, spec_stride, tw);
+  hipLaunchKernelGGL((k_os_r32x<T>), dim3((unsigned)ntask), dim3(512), 0, s, in, out, N->n_samp, b,
+                     nblk, spec, spec_stride, tw);
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }
@@ -1360,7 +1287,7 @@ furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *sp
     return FURAX_OK;
   }
   if (N->kind == 2) return launch_deproject<T>(N, in, out, nullptr, s);
-  const int M = os_half_length<T>(N->bandwidth);
+  const int M = os_half_length<T>(N);
   TwTables tw;
   FX_TRY(get_twiddles(2 * M, s, tw));
   const T *sp = static_cast<const T *>(spec);
@@ -1373,7 +1300,7 @@ furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *sp
     case 8192:
       return launch_os_r32<T>(N, in, out, sp, t, s);
     case 16384:
-      return launch_os_reg<T, 16384, 512>(N, in, out, sp, t, s);
+      return launch_os_r32x<T>(N, in, out, sp, t, s);
   }
   return set_error(FURAX_EUNSUPPORTED, "no overlap-save instance for this band");
 }

@@ -175,7 +175,8 @@ def test_hits_bitexact_and_sum(fx):
 @pytest.mark.parametrize("n_samp,b", [(1, 1), (100, 1), (5000, 7), (40000, 129), (70001, 4096),
                                       (16384, 4096), (200_000, 1000), (50_001, 2500),
                                       (8194, 4096), (100_000, 8192), (60_001, 6000),
-                                      (24_579, 4097), (5000, 4096), (9000, 8192)])
+                                      (24_579, 4097), (5000, 4096), (9000, 8192),
+                                      (40_003, 3072), (70_001, 3073), (26_625, 3500)])
 def test_band_noise_f64(fx, n_samp, b):
     rng = np.random.default_rng(n_samp + b)
     y = rng.standard_normal((2, n_samp))
@@ -187,7 +188,8 @@ def test_band_noise_f64(fx, n_samp, b):
 
 
 @pytest.mark.parametrize("n_samp,b", [(5000, 7), (70001, 4096), (100_000, 8192), (3, 2),
-                                      (50_001, 2500), (5000, 4096), (9000, 8192), (40_000, 4097)])
+                                      (50_001, 2500), (5000, 4096), (9000, 8192), (40_000, 4097),
+                                      (40_003, 3072), (70_001, 3073)])
 def test_band_noise_f32(fx, n_samp, b):
     rng = np.random.default_rng(n_samp + b)
     y = rng.standard_normal((3, n_samp)).astype(np.float32)
@@ -198,13 +200,15 @@ def test_band_noise_f32(fx, n_samp, b):
     assert rel_err(got, ref) <= 2e-6
 
 
+@pytest.mark.parametrize("b", [3000, 4096])
 @pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-12), (np.float32, 2e-6)])
-def test_band_noise_per_detector_long_kernels(fx, dtype, tol):
-    """Per-detector lags wide enough for the register-resident 8192-point blocks."""
+def test_band_noise_per_detector_long_kernels(fx, dtype, tol, b):
+    """Per-detector lags wide enough for the register-resident blocks (8192-
+    and 16384-point packed transforms)."""
     rng = np.random.default_rng(3)
     y = rng.standard_normal((3, 30001)).astype(dtype)
-    base = synth.toeplitz_lags(synth.WORKLOADS[2], 3000)
-    t = np.stack([base, 0.5 * base, 2.0 * base]) + 1e-3 * rng.standard_normal((3, 3000))
+    base = synth.toeplitz_lags(synth.WORKLOADS[2], b)
+    t = np.stack([base, 0.5 * base, 2.0 * base]) + 1e-3 * rng.standard_normal((3, b))
     t[:, 0] = np.abs(t[:, 0]) + 1.0
     ref = onz.band_apply(y.astype(np.float64), t, "fft")
     N = fx.Noise("band", 3, 30001, lags=torch.from_numpy(t).to(dev()))
