@@ -200,6 +200,22 @@ def test_band_noise_f32(fx, n_samp, b):
     assert rel_err(got, ref) <= 2e-6
 
 
+@pytest.mark.parametrize("dtype,b,wl,tol", [(np.float64, 4096, 2, 1e-12),
+                                             (np.float32, 4096, 3, 2e-6),
+                                             (np.float32, 8192, 5, 2e-6)])
+def test_band_noise_full_stream(fx, dtype, b, wl, tol):
+    """Whole 2^20-sample streams with the benchmark workloads' lags: the same
+    kernel and launch shape per detector as the timed iteration."""
+    n = synth.WORKLOADS[wl].n_samp
+    rng = np.random.default_rng(b + wl)
+    y = rng.standard_normal((3, n)).astype(dtype)
+    t = synth.toeplitz_lags(synth.WORKLOADS[wl], b)
+    ref = onz.band_apply(y.astype(np.float64), t, "fft")
+    N = fx.Noise("band", 3, n, lags=torch.from_numpy(t).to(dev()))
+    got = fx.noise_apply(N, torch.from_numpy(y).to(dev())).cpu().numpy()
+    assert rel_err(got, ref) <= tol
+
+
 @pytest.mark.parametrize("b", [3000, 4096])
 @pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-12), (np.float32, 2e-6)])
 def test_band_noise_per_detector_long_kernels(fx, dtype, tol, b):
