@@ -13,7 +13,9 @@ again with boresight-quaternion pointing (the same scan given as one attitude
 per time sample and one per detector, expanded per sample in the kernels) and
 with template deprojection (the weight F_T of Eq. (3): white weights with
 Legendre baselines of degree 0..3 removed from every 4096-sample segment) in
-place of the band-Toeplitz N^-1.
+place of the band-Toeplitz N^-1.  An FP32 workload (--config 5: nside 1024,
+1024 detectors x 2^20 samples, 8192 lags) is measured beside its FP64
+counterpart.
 
 Prints one JSON line (rank 0).
 """
@@ -400,6 +402,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=2, help="workload number (2, 3 or 5)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 variant")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the FP64 variant of an FP32 workload")
     ap.add_argument("--no-quat", action="store_true",
                     help="skip the boresight-quaternion pointing variants")
     ap.add_argument("--no-deproj", action="store_true",
@@ -454,6 +458,10 @@ def main():
     if not args.no_fp32 and w.dtype == "f64":
         w32 = synth.WORKLOADS[3] if args.config == 2 else w.with_(dtype="f32")
         fp32 = measure(w32, dev, args.steps, args.warmup)
+    fp64 = None
+    if not args.no_fp64 and w.dtype == "f32" and args.config != 3:
+        w64 = w.with_(dtype="f64", name=w.name.replace("_f32", "_f64"))
+        fp64 = measure(w64, dev, args.steps, args.warmup)
 
     quat = {}
     if not args.no_quat:
@@ -515,6 +523,11 @@ def main():
             "value": fp32["value"], "ms_per_step": fp32["ms_per_step"],
             "kernels": fp32["kernels"], "operator": fp32["operator"],
             "speedup_vs_fp64": fp32["value"] / primary["value"]},
+        "fp64": None if fp64 is None else {
+            "workload": w64.name,
+            "value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
+            "kernels": fp64["kernels"], "operator": fp64["operator"],
+            "fp32_speedup": primary["value"] / fp64["value"]},
         "quat": quat or None,
         "deproj": deproj or None,
         "gapfill": gapfill,
