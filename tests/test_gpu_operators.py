@@ -176,7 +176,8 @@ def test_hits_bitexact_and_sum(fx):
                                       (16384, 4096), (200_000, 1000), (50_001, 2500),
                                       (8194, 4096), (100_000, 8192), (60_001, 6000),
                                       (24_579, 4097), (5000, 4096), (9000, 8192),
-                                      (40_003, 3072), (70_001, 3073), (26_625, 3500)])
+                                      (40_003, 3072), (70_001, 3073), (26_625, 3500),
+                                      (26_624, 3073), (26_625, 3073), (5000, 5000)])
 def test_band_noise_f64(fx, n_samp, b):
     rng = np.random.default_rng(n_samp + b)
     y = rng.standard_normal((2, n_samp))
@@ -189,7 +190,8 @@ def test_band_noise_f64(fx, n_samp, b):
 
 @pytest.mark.parametrize("n_samp,b", [(5000, 7), (70001, 4096), (100_000, 8192), (3, 2),
                                       (50_001, 2500), (5000, 4096), (9000, 8192), (40_000, 4097),
-                                      (40_003, 3072), (70_001, 3073)])
+                                      (40_003, 3072), (70_001, 3073), (8192, 8192),
+                                      (16_386, 8192), (16_387, 8192), (32_772, 8192)])
 def test_band_noise_f32(fx, n_samp, b):
     rng = np.random.default_rng(n_samp + b)
     y = rng.standard_normal((3, n_samp)).astype(np.float32)
