@@ -717,7 +717,12 @@ __global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 2)
 k_os_r32x(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, int64_t nblk,
           const T *__restrict__ spec, int64_t spec_stride, const C2<double> *__restrict__ tw) {
   constexpr int M = 16384, L = 2 * M, HALF = M / 2, NT = 512;
-  __shared__ C2<T> s[HALF + HALF / 16];
+  constexpr int HP = HALF + HALF / 16;   // padded half: pad16(e - HALF) = pad16(e) - HP
+  // FP32 (VALU-bound) takes each exchange's LDS slots as one per-thread base
+  // plus compile-time offsets; FP64 (bound by its LDS exchanges and memory)
+  // measured faster with the slots computed per element.
+  constexpr bool kFold = sizeof(T) == 4;
+  __shared__ C2<T> s[HP];
   const int tid0 = threadIdx.x;
   const int64_t det = (int64_t)blockIdx.x / nblk, blk = (int64_t)blockIdx.x - det * nblk;
   const int V = L - 2 * (b - 1);
@@ -744,12 +749,16 @@ k_os_r32x(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, i
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (hw == h) {
+        const int wb = 34 * tid - h * HP;   // pad16(32 t + r - h HALF) = wb + pad16(r)
 #pragma unroll
-        for (int r = 0; r < 32; ++r) s[pad16(32 * tid + r - h * HALF)] = v[p32(r)];
+        for (int r = 0; r < 32; ++r)
+          s[kFold ? wb + r + (r >> 4) : pad16(32 * tid + r - h * HALF)] = v[p32(r)];
       }
       lds_barrier();
+      const int rb = pad16(tid);           // pad16(t + 512 (r + 16 h) - h HALF) = rb + 544 r
 #pragma unroll
-      for (int r = 16 * h; r < 16 * h + 16; ++r) nv[r] = s[pad16(tid + NT * r - h * HALF)];
+      for (int r = 0; r < 16; ++r)
+        nv[16 * h + r] = s[kFold ? rb + 544 * r : pad16(tid + NT * (r + 16 * h) - h * HALF)];
       lds_barrier();
     }
 #pragma unroll
@@ -772,15 +781,20 @@ k_os_r32x(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, i
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (hw == h) {
+        const int wb = 34 * (tid - k) + k + (k >> 4) - h * HP;
 #pragma unroll
-        for (int r = 0; r < 32; ++r) s[pad16((tid - k) * 32 + k + 32 * r - h * HALF)] = v[p32(r)];
+        for (int r = 0; r < 32; ++r)
+          s[kFold ? wb + 34 * r : pad16((tid - k) * 32 + k + 32 * r - h * HALF)] = v[p32(r)];
       }
       lds_barrier();
 #pragma unroll
-      for (int e = 0; e < 2; ++e)
+      for (int e = 0; e < 2; ++e) {
+        const int rb = pad16(e ? j1 : tid);  // pad16(j + 1024 (r + 8 h) - h HALF) = rb + 1088 r
 #pragma unroll
-        for (int r = 8 * h; r < 8 * h + 8; ++r)
-          nv[16 * e + r] = s[pad16((e ? j1 : tid) + 1024 * r - h * HALF)];
+        for (int r = 0; r < 8; ++r)
+          nv[16 * e + 8 * h + r] =
+              s[kFold ? rb + 1088 * r : pad16((e ? j1 : tid) + 1024 * (r + 8 * h) - h * HALF)];
+      }
       lds_barrier();
     }
 #pragma unroll
@@ -825,11 +839,15 @@ k_os_r32x(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, i
     C2<T> nv[32];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
+      const int wb = 17 * (h ? j1 : tid) - h * HP;   // pad16(16 j + r - h HALF), r < 16
 #pragma unroll
-      for (int r = 0; r < 16; ++r) s[pad16(16 * (h ? j1 : tid) + r - h * HALF)] = v[16 * h + p16(r)];
+      for (int r = 0; r < 16; ++r)
+        s[kFold ? wb + r : pad16(16 * (h ? j1 : tid) + r - h * HALF)] = v[16 * h + p16(r)];
       lds_barrier();
+      const int rb = pad16(tid);
 #pragma unroll
-      for (int r = 16 * h; r < 16 * h + 16; ++r) nv[r] = s[pad16(tid + NT * r - h * HALF)];
+      for (int r = 0; r < 16; ++r)
+        nv[16 * h + r] = s[kFold ? rb + 544 * r : pad16(tid + NT * (r + 16 * h) - h * HALF)];
       lds_barrier();
     }
 #pragma unroll
@@ -851,12 +869,16 @@ k_os_r32x(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, i
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (hw == h) {
+        const int wb = 34 * (tid - k) + k - h * HP;   // pad16((t - k) 32 + k + 16 r - h HALF)
 #pragma unroll
-        for (int r = 0; r < 32; ++r) s[pad16((tid - k) * 32 + k + 16 * r - h * HALF)] = v[p32(r)];
+        for (int r = 0; r < 32; ++r)
+          s[kFold ? wb + 17 * r : pad16((tid - k) * 32 + k + 16 * r - h * HALF)] = v[p32(r)];
       }
       lds_barrier();
+      const int rb = pad16(tid);
 #pragma unroll
-      for (int r = 16 * h; r < 16 * h + 16; ++r) nv[r] = s[pad16(tid + NT * r - h * HALF)];
+      for (int r = 0; r < 16; ++r)
+        nv[16 * h + r] = s[kFold ? rb + 544 * r : pad16(tid + NT * (r + 16 * h) - h * HALF)];
       lds_barrier();
     }
 #pragma unroll
