@@ -538,7 +538,11 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2)
 k_os_r32(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, int64_t nblk,
          const T *__restrict__ spec, int64_t spec_stride, const C2<double> *__restrict__ tw) {
   constexpr int M = 8192, L = 2 * M, HALF = M / 2, NT = 256;
-  __shared__ C2<T> s[HALF + HALF / 16];
+  constexpr int HP = HALF + HALF / 16;   // padded half: pad16(e - HALF) = pad16(e) - HP
+  // FP32 (VALU-bound) takes each exchange's LDS slots as one per-thread base
+  // plus compile-time offsets; FP64 keeps the slots computed per element.
+  constexpr bool kFold = sizeof(T) == 4;
+  __shared__ C2<T> s[HP];
   const int tid0 = threadIdx.x;
   const int64_t det = (int64_t)blockIdx.x / nblk, blk = (int64_t)blockIdx.x - det * nblk;
   const int V = L - 2 * (b - 1);
@@ -567,14 +571,16 @@ k_os_r32(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
     for (int h = 0; h < 2; ++h) {
       if (hw == h) {
 #pragma unroll
-        for (int r = 0; r < 32; ++r) s[pad16(32 * tid + r - h * HALF)] = v[p32(r)];
+        for (int r = 0; r < 32; ++r)
+          s[kFold ? 34 * tid - h * HP + r + (r >> 4) : pad16(32 * tid + r - h * HALF)] = v[p32(r)];
       }
       lds_barrier();
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
         for (int r = 8 * h; r < 8 * h + 8; ++r)
-          nv[16 * q + r] = s[pad16(tid + NT * q + 512 * r - h * HALF)];
+          nv[16 * q + r] = s[kFold ? pad16(tid) + 272 * q + 544 * (r - 8 * h)
+                                   : pad16(tid + NT * q + 512 * r - h * HALF)];
       lds_barrier();
     }
 #pragma unroll
@@ -595,14 +601,16 @@ k_os_r32(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
         const int j = tid + NT * h, k = j & 31;
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-          s[pad16((j - k) * 16 + k + 32 * r - h * HALF)] = v[16 * h + p16(r)];
+          s[kFold ? 17 * (tid - (tid & 31)) + pad16(tid & 31) + 34 * r
+                  : pad16((j - k) * 16 + k + 32 * r - h * HALF)] = v[16 * h + p16(r)];
       }
       lds_barrier();
 #pragma unroll
       for (int e = 0; e < 2; ++e)
 #pragma unroll
         for (int r = 8 * h; r < 8 * h + 8; ++r)
-          nv[16 * e + r] = s[pad16((e ? j1 : tid) + 512 * r - h * HALF)];
+          nv[16 * e + r] = s[kFold ? pad16(e ? j1 : tid) + 544 * (r - 8 * h)
+                                   : pad16((e ? j1 : tid) + 512 * r - h * HALF)];
       lds_barrier();
     }
 #pragma unroll
@@ -650,13 +658,16 @@ k_os_r32(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) s[pad16(16 * (h ? j1 : tid) + r - h * HALF)] = v[16 * h + p16(r)];
+      for (int r = 0; r < 16; ++r)
+        s[kFold ? 17 * (h ? j1 : tid) - h * HP + r : pad16(16 * (h ? j1 : tid) + r - h * HALF)] =
+            v[16 * h + p16(r)];
       lds_barrier();
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
         for (int r = 8 * h; r < 8 * h + 8; ++r)
-          nv[16 * q + r] = s[pad16(tid + NT * q + 512 * r - h * HALF)];
+          nv[16 * q + r] = s[kFold ? pad16(tid) + 272 * q + 544 * (r - 8 * h)
+                                   : pad16(tid + NT * q + 512 * r - h * HALF)];
       lds_barrier();
     }
 #pragma unroll
@@ -676,11 +687,13 @@ k_os_r32(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
         const int j = tid + NT * h, k = j & 15;
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-          s[pad16((j - k) * 16 + k + 16 * r - h * HALF)] = v[16 * h + p16(r)];
+          s[kFold ? 17 * (tid - (tid & 15)) + (tid & 15) + 17 * r
+                  : pad16((j - k) * 16 + k + 16 * r - h * HALF)] = v[16 * h + p16(r)];
       }
       lds_barrier();
 #pragma unroll
-      for (int r = 16 * h; r < 16 * h + 16; ++r) nv[r] = s[pad16(tid + NT * r - h * HALF)];
+      for (int r = 16 * h; r < 16 * h + 16; ++r)
+        nv[r] = s[kFold ? pad16(tid) + 272 * (r - 16 * h) : pad16(tid + NT * r - h * HALF)];
       lds_barrier();
     }
 #pragma unroll
