@@ -169,6 +169,21 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
 }
+// Two consecutive values of a row as one access (off: byte offset of the first).
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ C2<double> buf_load2(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
+  return __builtin_bit_cast(C2<double>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ C2<float> buf_load2(__amdgpu_buffer_rsrc_t r, uint32_t off, float) {
+  return __builtin_bit_cast(C2<float>, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_store2(__amdgpu_buffer_rsrc_t r, uint32_t off, C2<double> v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store2(__amdgpu_buffer_rsrc_t r, uint32_t off, C2<float> v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, off, 0, 0);
+}
 
 // The thread index as a value the compiler cannot move across this point:
 // LDS and store addresses derived from it are then computed where they are
@@ -717,6 +732,9 @@ k_os_r32(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
   }
 }
 
+// First valid output of a block for a band of b lags, rounded up to even.
+__host__ __device__ __forceinline__ int os_pair_lo(int b) { return (b - 1) + ((b - 1) & 1); }
+
 // ---------------------------------------------------------------------------
 // The same four-exchange scheme for M = 16384 (32768-sample blocks): 512
 // threads of 32 values, radices 32, 32, 16 forward (spans 1, 32, 1024) and
@@ -725,7 +743,7 @@ k_os_r32(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
 // exchanges move a whole radix-32 butterfly per thread in one round (its 32
 // outputs fall in one half, chosen per wave).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool PAIR>
 __global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 2)
 k_os_r32x(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, int64_t nblk,
           const T *__restrict__ spec, int64_t spec_stride, const C2<double> *__restrict__ tw) {
@@ -738,8 +756,10 @@ k_os_r32x(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, i
   __shared__ C2<T> s[HP];
   const int tid0 = threadIdx.x;
   const int64_t det = (int64_t)blockIdx.x / nblk, blk = (int64_t)blockIdx.x - det * nblk;
-  const int V = L - 2 * (b - 1);
-  const int32_t s0 = (int32_t)(blk * V) - (b - 1);
+  // valid outputs [lo, lo + V) of the block, lo = b - 1 rounded up to even so
+  // that the (even, odd) sample pairs a thread moves are all valid or all not
+  const int lo = os_pair_lo(b), V = L - 2 * lo;
+  const int32_t s0 = (int32_t)(blk * V) - lo;
   C2<T> v[32];
 
   // ---- forward pass 0 (radix 32, span 1): inputs z[t + 512 r] from HBM
@@ -748,9 +768,14 @@ k_os_r32x(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, i
     const __amdgpu_buffer_rsrc_t xr = row_buffer(const_cast<T *>(in) + det * n, n);
 #pragma unroll
     for (int r = 0; r < 32; ++r) {
-      const int32_t g = s0 + 2 * (tid + NT * r);
-      v[r].x = buf_load<T>(xr, g >= 0 ? (uint32_t)g * (uint32_t)sizeof(T) : kDropOffset);
-      v[r].y = buf_load<T>(xr, g + 1 >= 0 ? (uint32_t)(g + 1) * (uint32_t)sizeof(T) : kDropOffset);
+      const int32_t g = s0 + 2 * (tid + NT * r);   // even
+      if constexpr (PAIR) {
+        // n even: a pair is wholly before the row, inside it or past its end
+        v[r] = buf_load2(xr, g >= 0 ? (uint32_t)g * (uint32_t)sizeof(T) : kDropOffset, T());
+      } else {
+        v[r].x = buf_load<T>(xr, g >= 0 ? (uint32_t)g * (uint32_t)sizeof(T) : kDropOffset);
+        v[r].y = buf_load<T>(xr, g + 1 >= 0 ? (uint32_t)(g + 1) * (uint32_t)sizeof(T) : kDropOffset);
+      }
     }
     dft32<T, false>(v);
   }
@@ -903,14 +928,18 @@ k_os_r32x(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, i
     twiddle32<T, true>(v, tw[2 * tid]);
     dft32<T, true>(v);
     const __amdgpu_buffer_rsrc_t zr = row_buffer(out + det * n, n);
-    const int lo = b - 1, hi = b - 1 + V;
+    const int hi = lo + V;
 #pragma unroll
     for (int r = 0; r < 32; ++r) {
       const C2<T> w = v[p32(r)];
-      const int e = 2 * (tid + NT * r);
-      buf_store(zr, e >= lo && e < hi ? (uint32_t)(s0 + e) * (uint32_t)sizeof(T) : kDropOffset, w.x);
-      buf_store(zr, e + 1 >= lo && e + 1 < hi ? (uint32_t)(s0 + e + 1) * (uint32_t)sizeof(T)
-                                              : kDropOffset, w.y);
+      const int e = 2 * (tid + NT * r);   // even, as lo and hi are
+      if constexpr (PAIR) {
+        buf_store2(zr, e >= lo && e < hi ? (uint32_t)(s0 + e) * (uint32_t)sizeof(T) : kDropOffset, w);
+      } else {
+        buf_store(zr, e >= lo && e < hi ? (uint32_t)(s0 + e) * (uint32_t)sizeof(T) : kDropOffset, w.x);
+        buf_store(zr, e + 1 >= lo && e + 1 < hi ? (uint32_t)(s0 + e + 1) * (uint32_t)sizeof(T)
+                                                : kDropOffset, w.y);
+      }
     }
   }
 }
@@ -1114,7 +1143,7 @@ static furax_status launch_os_r32x(const furax_noise *N, const T *in, T *out, co
                                    const C2<double> *tw, hipStream_t s) {
   constexpr int M = 16384;
   const int b = (int)N->bandwidth;
-  const int64_t V = 2 * M - 2 * (int64_t)(b - 1);
+  const int64_t V = 2 * M - 2 * (int64_t)os_pair_lo(b);
   const int64_t nblk = (N->n_samp + V - 1) / V;
   const int64_t ntask = N->n_det * nblk;
   const int64_t spec_stride = N->toeplitz_stride ? spec_block(M) : 0;
@@ -1125,8 +1154,12 @@ static furax_status launch_os_r32x(const furax_noise *N, const T *in, T *out, co
     else
       return launch_os<T, M, M / 16>(N, in, out, spec, tw, s);
   }
-  hipLaunchKernelGGL((k_os_r32x<T>), dim3((unsigned)ntask), dim3(512), 0, s, in, out, N->n_samp, b,
-                     nblk, spec, spec_stride, tw);
+  if (N->n_samp % 2 == 0)
+    hipLaunchKernelGGL((k_os_r32x<T, true>), dim3((unsigned)ntask), dim3(512), 0, s, in, out,
+                       N->n_samp, b, nblk, spec, spec_stride, tw);
+  else
+    hipLaunchKernelGGL((k_os_r32x<T, false>), dim3((unsigned)ntask), dim3(512), 0, s, in, out,
+                       N->n_samp, b, nblk, spec, spec_stride, tw);
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }
