@@ -471,6 +471,9 @@ __device__ __forceinline__ void reg_r16(C2<T> *v, int j, int Ns, const C2<double
   dft16<T, INV>(*reinterpret_cast<C2<T>(*)[16]>(v));
 }
 
+// First valid output of a block for a band of b lags, rounded up to even.
+__host__ __device__ __forceinline__ int os_pair_lo(int b) { return (b - 1) + ((b - 1) & 1); }
+
 // ---------------------------------------------------------------------------
 // Register-resident overlap-save with four exchanges, M = 8192.
 //
@@ -548,7 +551,7 @@ __device__ __forceinline__ void twiddle32(C2<T> (&v)[32], C2<double> W1) {
 
 // (FP32: registers for four waves per SIMD, LDS for four workgroups per CU;
 // FP64: two of each)
-template <typename T>
+template <typename T, bool PAIR>
 __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2)
 k_os_r32(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, int64_t nblk,
          const T *__restrict__ spec, int64_t spec_stride, const C2<double> *__restrict__ tw) {
@@ -560,8 +563,9 @@ k_os_r32(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
   __shared__ C2<T> s[HP];
   const int tid0 = threadIdx.x;
   const int64_t det = (int64_t)blockIdx.x / nblk, blk = (int64_t)blockIdx.x - det * nblk;
-  const int V = L - 2 * (b - 1);
-  const int32_t s0 = (int32_t)(blk * V) - (b - 1);
+  // valid outputs [lo, lo + V) of the block, lo even (os_pair_lo)
+  const int lo = os_pair_lo(b), V = L - 2 * lo;
+  const int32_t s0 = (int32_t)(blk * V) - lo;
   C2<T> v[32];
 
   // ---- forward pass 0 (radix 32, span 1): inputs z[t + 256 r] from HBM
@@ -571,8 +575,12 @@ k_os_r32(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
 #pragma unroll
     for (int r = 0; r < 32; ++r) {
       const int32_t g = s0 + 2 * (tid + NT * r);
-      v[r].x = buf_load<T>(xr, g >= 0 ? (uint32_t)g * (uint32_t)sizeof(T) : kDropOffset);
-      v[r].y = buf_load<T>(xr, g + 1 >= 0 ? (uint32_t)(g + 1) * (uint32_t)sizeof(T) : kDropOffset);
+      if constexpr (PAIR) {   // n even: a pair is wholly inside or outside the row
+        v[r] = buf_load2(xr, g >= 0 ? (uint32_t)g * (uint32_t)sizeof(T) : kDropOffset, T());
+      } else {
+        v[r].x = buf_load<T>(xr, g >= 0 ? (uint32_t)g * (uint32_t)sizeof(T) : kDropOffset);
+        v[r].y = buf_load<T>(xr, g + 1 >= 0 ? (uint32_t)(g + 1) * (uint32_t)sizeof(T) : kDropOffset);
+      }
     }
     dft32<T, false>(v);
   }
@@ -720,20 +728,21 @@ k_os_r32(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
     twiddle32<T, true>(v, tw[2 * tid]);
     dft32<T, true>(v);
     const __amdgpu_buffer_rsrc_t zr = row_buffer(out + det * n, n);
-    const int lo = b - 1, hi = b - 1 + V;
+    const int hi = lo + V;
 #pragma unroll
     for (int r = 0; r < 32; ++r) {
       const C2<T> w = v[p32(r)];
       const int e = 2 * (tid + NT * r);
-      buf_store(zr, e >= lo && e < hi ? (uint32_t)(s0 + e) * (uint32_t)sizeof(T) : kDropOffset, w.x);
-      buf_store(zr, e + 1 >= lo && e + 1 < hi ? (uint32_t)(s0 + e + 1) * (uint32_t)sizeof(T)
-                                              : kDropOffset, w.y);
+      if constexpr (PAIR) {
+        buf_store2(zr, e >= lo && e < hi ? (uint32_t)(s0 + e) * (uint32_t)sizeof(T) : kDropOffset, w);
+      } else {
+        buf_store(zr, e >= lo && e < hi ? (uint32_t)(s0 + e) * (uint32_t)sizeof(T) : kDropOffset, w.x);
+        buf_store(zr, e + 1 >= lo && e + 1 < hi ? (uint32_t)(s0 + e + 1) * (uint32_t)sizeof(T)
+                                                : kDropOffset, w.y);
+      }
     }
   }
 }
-
-// First valid output of a block for a band of b lags, rounded up to even.
-__host__ __device__ __forceinline__ int os_pair_lo(int b) { return (b - 1) + ((b - 1) & 1); }
 
 // ---------------------------------------------------------------------------
 // The same four-exchange scheme for M = 16384 (32768-sample blocks): 512
@@ -1127,13 +1136,17 @@ static furax_status launch_os_r32(const furax_noise *N, const T *in, T *out, con
                                   const C2<double> *tw, hipStream_t s) {
   constexpr int M = 8192;
   const int b = (int)N->bandwidth;
-  const int64_t V = 2 * M - 2 * (int64_t)(b - 1);
+  if (!os_reg_fits<T>(N->n_samp, M)) return launch_os<T, M, M / 16>(N, in, out, spec, tw, s);
+  const int64_t V = 2 * M - 2 * (int64_t)os_pair_lo(b);
   const int64_t nblk = (N->n_samp + V - 1) / V;
   const int64_t ntask = N->n_det * nblk;
   const int64_t spec_stride = N->toeplitz_stride ? spec_block(M) : 0;
-  if (!os_reg_fits<T>(N->n_samp, M)) return launch_os<T, M, M / 16>(N, in, out, spec, tw, s);
-  hipLaunchKernelGGL((k_os_r32<T>), dim3((unsigned)ntask), dim3(256), 0, s, in, out, N->n_samp, b,
-                     nblk, spec, spec_stride, tw);
+  if (N->n_samp % 2 == 0)
+    hipLaunchKernelGGL((k_os_r32<T, true>), dim3((unsigned)ntask), dim3(256), 0, s, in, out,
+                       N->n_samp, b, nblk, spec, spec_stride, tw);
+  else
+    hipLaunchKernelGGL((k_os_r32<T, false>), dim3((unsigned)ntask), dim3(256), 0, s, in, out,
+                       N->n_samp, b, nblk, spec, spec_stride, tw);
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }
