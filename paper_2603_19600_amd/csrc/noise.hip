@@ -1069,17 +1069,17 @@ static bool os_reg_fits(int64_t n_samp, int64_t M) {
 
 // FFT half-length M used for noise model N in precision T: the smallest power
 // of two with M >= 4 (b - 1) (at most a quarter of each block is halo),
-// capped at 8192; 16384 above 3072 lags, where the longer block's smaller
-// halo outweighs its slower transform (measured crossover near 3000 lags in
-// both precisions).  A stream too long for the register kernels' 32-bit
-// offsets keeps M = 8192 up to 4096 lags, where the LDS kernel can take an
-// FP64 block.
+// capped at 8192; 16384 above 2560 lags in FP64 and 3072 in FP32, where the
+// longer block's smaller halo outweighs its slower transform (measured
+// crossovers).  A stream too long for the register kernels' 32-bit offsets
+// keeps M = 8192 up to 4096 lags, where the LDS kernel can take an FP64 block.
 template <typename T>
 int os_half_length(const furax_noise *N) {
   const int64_t b = N->bandwidth;
+  constexpr int64_t kLong = sizeof(T) == 8 ? 2560 : 3072;
   int64_t m = 512;
   while (m < 4 * (b - 1) && m < 8192) m *= 2;
-  if (b > 4096 || (b > 3072 && os_reg_fits<T>(N->n_samp, 16384))) m = 16384;
+  if (b > 4096 || (b > kLong && os_reg_fits<T>(N->n_samp, 16384))) m = 16384;
   return (int)m;
 }
 
