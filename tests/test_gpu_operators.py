@@ -219,7 +219,7 @@ def test_band_noise_full_stream(fx, dtype, b, wl, tol):
     assert rel_err(got, ref) <= tol
 
 
-@pytest.mark.parametrize("b", [3000, 4096])
+@pytest.mark.parametrize("b", [2500, 3000, 4096])
 @pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-12), (np.float32, 2e-6)])
 def test_band_noise_per_detector_long_kernels(fx, dtype, tol, b):
     """Per-detector lags wide enough for the register-resident blocks (8192-
