@@ -235,6 +235,28 @@ def test_band_noise_per_detector_long_kernels(fx, dtype, tol, b):
     assert rel_err(got, ref) <= tol
 
 
+@pytest.mark.parametrize("dtype,b,tol", [(np.float64, 4096, 1e-12), (np.float32, 4096, 2e-6),
+                                          (np.float64, 2500, 1e-12), (np.float32, 8192, 2e-6)])
+def test_band_noise_rows_off_16_byte_alignment(fx, dtype, b, tol):
+    """Streams of even length whose data starts one element past an aligned
+    address (a view into a larger buffer): the kernels' sample-pair accesses
+    then sit at half-pair alignment and must give the same result."""
+    n = 40_000
+    rng = np.random.default_rng(b + 7)
+    y = rng.standard_normal((2, n)).astype(dtype)
+    t = synth.toeplitz_lags(synth.WORKLOADS[2], b)
+    ref = onz.band_apply(y.astype(np.float64), t, "fft")
+    buf = torch.zeros(2 * n + 1, dtype=torch.from_numpy(y).dtype, device=dev())
+    yv = buf[1:].view(2, n)
+    yv.copy_(torch.from_numpy(y).to(dev()))
+    obuf = torch.zeros_like(buf)
+    zv = obuf[1:].view(2, n)
+    N = fx.Noise("band", 2, n, lags=torch.from_numpy(t).to(dev()))
+    fx.noise_apply(N, yv, out=zv)
+    assert rel_err(zv.cpu().numpy(), ref) <= tol
+    assert float(obuf[0]) == 0.0
+
+
 def test_band_noise_per_detector_kernels(fx):
     rng = np.random.default_rng(1)
     y = rng.standard_normal((3, 9000))
