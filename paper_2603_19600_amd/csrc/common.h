@@ -419,9 +419,12 @@ furax_status launch_noise(const furax_noise *N, const T *in, T *out, void *work,
                           size_t work_bytes, hipStream_t s);
 template <typename T>
 size_t noise_workspace_bytes(const furax_noise *N);
+// out = F_T in and / or the segments' template amplitudes; Lg: the Cholesky
+// factor of full-length segments' Gram matrix (noise_prepare's workspace for a
+// "deproj" model), or null to accumulate every segment's own.
 template <typename T>
 furax_status launch_deproject(const furax_noise *N, const T *in, T *out, double *amp,
-                              hipStream_t s);
+                              hipStream_t s, const double *Lg = nullptr);
 // Kernel spectrum of a band model (noise_workspace_bytes<T> bytes at spec),
 // then the weight (or, for a covariance, N itself) applied to [n_det][n_samp].
 template <typename T>

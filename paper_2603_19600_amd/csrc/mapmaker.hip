@@ -277,7 +277,7 @@ static furax_status normal_prepare(NormalPlan<T> &pl, hipStream_t s) {
                      pl.P->n_det, N->kind != 1 ? N->inv_var : nullptr,
                      N->kind == 1 ? N->toeplitz : nullptr, N->toeplitz_stride, w);
   FX_HIP(hipGetLastError());
-  if (N->kind == 1) FX_TRY(noise_prepare<T>(N, pl.work + pl.L.spec, s));
+  if (N->kind != 0) FX_TRY(noise_prepare<T>(N, pl.work + pl.L.spec, s));
   return FURAX_OK;
 }
 

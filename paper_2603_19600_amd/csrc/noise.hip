@@ -1088,9 +1088,14 @@ int64_t os_max_band() { return 8192; }
 template int64_t os_max_band<float>();
 template int64_t os_max_band<double>();
 
-// Spectrum buffer size for a noise model in precision T.
+constexpr int kMaxDeprojNP = 8;   // template deprojection: Legendre degrees 0..7
+static furax_status launch_deproj_gram(const furax_noise *N, double *Lg, hipStream_t s);
+
+// Workspace of a noise model in precision T: the band kernel's spectrum, or
+// the template deprojection's Gram factor.
 template <typename T>
 size_t noise_workspace_bytes(const furax_noise *N) {
+  if (N->kind == 2) return sizeof(double) * kMaxDeprojNP * kMaxDeprojNP;   // Gram factor
   if (N->kind != 1) return 0;
   const int M = os_half_length<T>(N);
   const int64_t nk = N->toeplitz_stride ? N->n_det : 1;
@@ -1102,6 +1107,7 @@ template size_t noise_workspace_bytes<double>(const furax_noise *);
 // Compute the kernel spectrum into `spec` (noise_workspace_bytes<T> bytes).
 template <typename T>
 furax_status noise_prepare(const furax_noise *N, void *spec, hipStream_t s) {
+  if (N->kind == 2) return launch_deproj_gram(N, static_cast<double *>(spec), s);
   if (N->kind != 1) return FURAX_OK;
   const int M = os_half_length<T>(N);
   TwTables tw;
@@ -1182,12 +1188,14 @@ static furax_status launch_os_r32x(const furax_noise *N, const T *in, T *out, co
 // W = w_k I and T the Legendre baselines P_0 .. P_{NP-1} of each segment:
 //   z = w_k (y - T_s G^-1 T_s^T y),  G = T_s^T T_s.
 // One workgroup per (detector, segment).  Pass 1 accumulates, in FP64, the
-// projections T_s^T y and the Gram matrix G (upper triangle) over the
-// segment's samples; the partial sums are combined in a fixed order (wave
-// shuffles, then the waves in order), and one thread solves G c = T_s^T y by
-// Cholesky.  Pass 2 re-reads the segment (L2-resident) and writes
-// w_k (y - sum_j c_j P_j).  The Gram sums are recomputed per segment: they cost
-// arithmetic only, the kernel is bound by its two TOD streams.
+// projections T_s^T y over the segment's samples; the partial sums are
+// combined in a fixed order (wave shuffles, then the waves in order), and one
+// thread solves G c = T_s^T y by Cholesky.  Pass 2 re-reads the segment
+// (L2-resident) and writes w_k (y - sum_j c_j P_j).  G depends only on the
+// segment's length: every full-length segment takes the Cholesky factor that
+// k_deproj_gram computes once per application (the same sums in the same
+// order), and only a stream's longer last segment accumulates its own Gram
+// sums in pass 1.
 // ---------------------------------------------------------------------------
 constexpr int kDeprojThreads = 256;
 
@@ -1207,39 +1215,12 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <typename T, int NP>
-__global__ void __launch_bounds__(kDeprojThreads) k_deproject(const T *__restrict__ in,
-                                                              T *__restrict__ out, int64_t n,
-                                                              int64_t seg_len, int64_t nseg,
-                                                              const double *__restrict__ w,
-                                                              double *__restrict__ amp) {
-#pragma clang fp contract(off)
-  constexpr int NG = NP * (NP + 1) / 2;
-  constexpr int NV = NP + NG;
+// Workgroup sums of acc[0..NV) in a fixed order: each wave's shuffle tree,
+// then the waves in order; the result is valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void deproj_reduce(double (&acc)[NV], double (&part)[kDeprojThreads / 64][NV],
+                                              double (&r)[NV]) {
   constexpr int NW = kDeprojThreads / 64;
-  __shared__ double part[NW][NV];
-  __shared__ double coef[NP];
-  const int64_t det = (int64_t)blockIdx.x / nseg, seg = (int64_t)blockIdx.x - det * nseg;
-  const int64_t i0 = seg * seg_len;
-  const int64_t len = seg + 1 < nseg ? seg_len : n - i0;
-  const T *y = in + det * n + i0;
-  T *z = out + det * n + i0;
-  const double dlen = (double)len;
-  double acc[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-  for (int64_t i = threadIdx.x; i < len; i += kDeprojThreads) {
-    double P[NP];
-    legendre_at<NP>((2.0 * (double)i + 1.0) / dlen - 1.0, P);
-    const double yi = (double)y[i];
-#pragma unroll
-    for (int j = 0; j < NP; ++j) acc[j] += P[j] * yi;
-    int g = NP;
-#pragma unroll
-    for (int j = 0; j < NP; ++j)
-#pragma unroll
-      for (int l = j; l < NP; ++l) acc[g++] += P[j] * P[l];
-  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -1248,54 +1229,168 @@ __global__ void __launch_bounds__(kDeprojThreads) k_deproject(const T *__restric
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double r[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       r[v] = part[0][v];
 #pragma unroll
       for (int q = 1; q < NW; ++q) r[v] += part[q][v];
     }
-    // G = L L^T (G[j][l] = r[NP + idx(j, l)], upper triangle by rows), then
-    // forward and back substitution for c
+  }
+}
+
+// Lower Cholesky factor Lm of G, given as its upper triangle by rows in g.
+template <int NP>
+__device__ __forceinline__ void gram_cholesky(const double *g, double (&Lm)[NP][NP]) {
+#pragma clang fp contract(off)
+  int k = 0;
+#pragma unroll
+  for (int j = 0; j < NP; ++j)
+#pragma unroll
+    for (int l = j; l < NP; ++l) Lm[l][j] = g[k++];   // lower triangle holds G
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    double d = Lm[j][j];
+#pragma unroll
+    for (int m = 0; m < j; ++m) d -= Lm[j][m] * Lm[j][m];
+    d = sqrt(d);
+    Lm[j][j] = d;
+#pragma unroll
+    for (int l = j + 1; l < NP; ++l) {
+      double v = Lm[l][j];
+#pragma unroll
+      for (int m = 0; m < j; ++m) v -= Lm[l][m] * Lm[j][m];
+      Lm[l][j] = v / d;
+    }
+  }
+}
+
+// c = G^-1 rhs by forward and back substitution with G = Lm Lm^T.
+template <int NP>
+__device__ __forceinline__ void chol_solve(const double (&Lm)[NP][NP], const double *rhs,
+                                           double (&c)[NP]) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    double v = rhs[j];
+#pragma unroll
+    for (int m = 0; m < j; ++m) v -= Lm[j][m] * c[m];
+    c[j] = v / Lm[j][j];
+  }
+#pragma unroll
+  for (int j = NP - 1; j >= 0; --j) {
+    double v = c[j];
+#pragma unroll
+    for (int m = j + 1; m < NP; ++m) v -= Lm[m][j] * c[m];
+    c[j] = v / Lm[j][j];
+  }
+}
+
+// Gram sums of sample i of a segment of length dlen, added to g[0..NG).
+template <int NP>
+__device__ __forceinline__ void gram_add(const double (&P)[NP], double *g) {
+#pragma clang fp contract(off)
+  int k = 0;
+#pragma unroll
+  for (int j = 0; j < NP; ++j)
+#pragma unroll
+    for (int l = j; l < NP; ++l) g[k++] += P[j] * P[l];
+}
+
+// The Cholesky factor of G for a segment of seg_len samples, into Lg[NP][NP].
+template <int NP>
+__global__ void __launch_bounds__(kDeprojThreads) k_deproj_gram(int64_t seg_len,
+                                                                double *__restrict__ Lg) {
+#pragma clang fp contract(off)
+  constexpr int NG = NP * (NP + 1) / 2;
+  __shared__ double part[kDeprojThreads / 64][NG];
+  const double dlen = (double)seg_len;
+  double acc[NG];
+#pragma unroll
+  for (int v = 0; v < NG; ++v) acc[v] = 0.0;
+  for (int64_t i = threadIdx.x; i < seg_len; i += kDeprojThreads) {
+    double P[NP];
+    legendre_at<NP>((2.0 * (double)i + 1.0) / dlen - 1.0, P);
+    gram_add<NP>(P, acc);
+  }
+  double r[NG];
+  deproj_reduce<NG>(acc, part, r);
+  if (threadIdx.x == 0) {
     double Lm[NP][NP];
-    int g = NP;
+    gram_cholesky<NP>(r, Lm);
 #pragma unroll
     for (int j = 0; j < NP; ++j)
 #pragma unroll
-      for (int l = j; l < NP; ++l) {
-        Lm[l][j] = r[g];   // lower triangle holds G
-        ++g;
-      }
+      for (int l = 0; l < NP; ++l) Lg[j * NP + l] = l <= j ? Lm[j][l] : 0.0;
+  }
+}
+
+// Lg: the factor of full-length segments from k_deproj_gram, or null (every
+// segment accumulates its own Gram sums).
+template <typename T, int NP>
+__global__ void __launch_bounds__(kDeprojThreads) k_deproject(const T *__restrict__ in,
+                                                              T *__restrict__ out, int64_t n,
+                                                              int64_t seg_len, int64_t nseg,
+                                                              const double *__restrict__ w,
+                                                              double *__restrict__ amp,
+                                                              const double *__restrict__ Lg) {
+#pragma clang fp contract(off)
+  constexpr int NG = NP * (NP + 1) / 2;
+  constexpr int NV = NP + NG;
+  __shared__ double part[kDeprojThreads / 64][NV];
+  __shared__ double part_y[kDeprojThreads / 64][NP];
+  __shared__ double coef[NP];
+  const int64_t det = (int64_t)blockIdx.x / nseg, seg = (int64_t)blockIdx.x - det * nseg;
+  const int64_t i0 = seg * seg_len;
+  const int64_t len = seg + 1 < nseg ? seg_len : n - i0;
+  const T *y = in + det * n + i0;
+  T *z = out + det * n + i0;
+  const double dlen = (double)len;
+  // workgroup-uniform: a full-length segment with a precomputed factor
+  const bool known = Lg != nullptr && len == seg_len;
+  double acc[NV];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
-      double d = Lm[j][j];
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  if (known) {
+    for (int64_t i = threadIdx.x; i < len; i += kDeprojThreads) {
+      double P[NP];
+      legendre_at<NP>((2.0 * (double)i + 1.0) / dlen - 1.0, P);
+      const double yi = (double)y[i];
 #pragma unroll
-      for (int k = 0; k < j; ++k) d -= Lm[j][k] * Lm[j][k];
-      d = sqrt(d);
-      Lm[j][j] = d;
+      for (int j = 0; j < NP; ++j) acc[j] += P[j] * yi;
+    }
+  } else {
+    for (int64_t i = threadIdx.x; i < len; i += kDeprojThreads) {
+      double P[NP];
+      legendre_at<NP>((2.0 * (double)i + 1.0) / dlen - 1.0, P);
+      const double yi = (double)y[i];
 #pragma unroll
-      for (int l = j + 1; l < NP; ++l) {
-        double v = Lm[l][j];
+      for (int j = 0; j < NP; ++j) acc[j] += P[j] * yi;
+      gram_add<NP>(P, acc + NP);
+    }
+  }
+  double r[NV];
+  if (known) {
+    double a[NP], rp[NP];
 #pragma unroll
-        for (int k = 0; k < j; ++k) v -= Lm[l][k] * Lm[j][k];
-        Lm[l][j] = v / d;
-      }
+    for (int v = 0; v < NP; ++v) a[v] = acc[v];
+    deproj_reduce<NP>(a, part_y, rp);
+#pragma unroll
+    for (int v = 0; v < NP; ++v) r[v] = rp[v];
+  } else {
+    deproj_reduce<NV>(acc, part, r);
+  }
+  if (threadIdx.x == 0) {
+    double Lm[NP][NP];
+    if (known) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j)
+#pragma unroll
+        for (int l = 0; l < NP; ++l) Lm[j][l] = Lg[j * NP + l];
+    } else {
+      gram_cholesky<NP>(r + NP, Lm);
     }
     double c[NP];
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-      double v = r[j];
-#pragma unroll
-      for (int k = 0; k < j; ++k) v -= Lm[j][k] * c[k];
-      c[j] = v / Lm[j][j];
-    }
-#pragma unroll
-    for (int j = NP - 1; j >= 0; --j) {
-      double v = c[j];
-#pragma unroll
-      for (int k = j + 1; k < NP; ++k) v -= Lm[k][j] * c[k];
-      c[j] = v / Lm[j][j];
-    }
+    chol_solve<NP>(Lm, r, c);
 #pragma unroll
     for (int j = 0; j < NP; ++j) coef[j] = c[j];
     if (amp) {   // the template fit (T^T W T)^-1 T^T W y of this segment (w cancels)
@@ -1321,37 +1416,60 @@ __global__ void __launch_bounds__(kDeprojThreads) k_deproject(const T *__restric
 
 template <typename T, int NP>
 static furax_status launch_deproject_np(const furax_noise *N, const T *in, T *out, double *amp,
-                                        hipStream_t s) {
+                                        const double *Lg, hipStream_t s) {
   const int64_t nseg = std::max<int64_t>(1, N->n_samp / N->tmpl_seg_len);
   hipLaunchKernelGGL((k_deproject<T, NP>), dim3((unsigned)(N->n_det * nseg)),
                      dim3(kDeprojThreads), 0, s, in, out, N->n_samp, N->tmpl_seg_len, nseg,
-                     N->inv_var, amp);
+                     N->inv_var, amp, Lg);
   FX_HIP(hipGetLastError());
   return FURAX_OK;
+}
+
+template <int NP>
+static furax_status launch_deproj_gram_np(const furax_noise *N, double *Lg, hipStream_t s) {
+  hipLaunchKernelGGL((k_deproj_gram<NP>), dim3(1), dim3(kDeprojThreads), 0, s,
+                     (int64_t)N->tmpl_seg_len, Lg);
+  FX_HIP(hipGetLastError());
+  return FURAX_OK;
+}
+
+// The full-length segments' Cholesky factor into Lg (kMaxDeprojNP^2 doubles).
+static furax_status launch_deproj_gram(const furax_noise *N, double *Lg, hipStream_t s) {
+  switch (N->tmpl_order) {
+    case 0: return launch_deproj_gram_np<1>(N, Lg, s);
+    case 1: return launch_deproj_gram_np<2>(N, Lg, s);
+    case 2: return launch_deproj_gram_np<3>(N, Lg, s);
+    case 3: return launch_deproj_gram_np<4>(N, Lg, s);
+    case 4: return launch_deproj_gram_np<5>(N, Lg, s);
+    case 5: return launch_deproj_gram_np<6>(N, Lg, s);
+    case 6: return launch_deproj_gram_np<7>(N, Lg, s);
+    case 7: return launch_deproj_gram_np<8>(N, Lg, s);
+  }
+  return set_error(FURAX_EINVAL, "tmpl_order must be in [0, 7]");
 }
 
 // out = F_T in (out may be null: amplitudes only); amp [n_det][n_seg][order + 1]
 // receives the template fit of each segment when not null.
 template <typename T>
 furax_status launch_deproject(const furax_noise *N, const T *in, T *out, double *amp,
-                              hipStream_t s) {
+                              hipStream_t s, const double *Lg) {
   if (N->n_samp == 0) return FURAX_OK;
   switch (N->tmpl_order) {
-    case 0: return launch_deproject_np<T, 1>(N, in, out, amp, s);
-    case 1: return launch_deproject_np<T, 2>(N, in, out, amp, s);
-    case 2: return launch_deproject_np<T, 3>(N, in, out, amp, s);
-    case 3: return launch_deproject_np<T, 4>(N, in, out, amp, s);
-    case 4: return launch_deproject_np<T, 5>(N, in, out, amp, s);
-    case 5: return launch_deproject_np<T, 6>(N, in, out, amp, s);
-    case 6: return launch_deproject_np<T, 7>(N, in, out, amp, s);
-    case 7: return launch_deproject_np<T, 8>(N, in, out, amp, s);
+    case 0: return launch_deproject_np<T, 1>(N, in, out, amp, Lg, s);
+    case 1: return launch_deproject_np<T, 2>(N, in, out, amp, Lg, s);
+    case 2: return launch_deproject_np<T, 3>(N, in, out, amp, Lg, s);
+    case 3: return launch_deproject_np<T, 4>(N, in, out, amp, Lg, s);
+    case 4: return launch_deproject_np<T, 5>(N, in, out, amp, Lg, s);
+    case 5: return launch_deproject_np<T, 6>(N, in, out, amp, Lg, s);
+    case 6: return launch_deproject_np<T, 7>(N, in, out, amp, Lg, s);
+    case 7: return launch_deproject_np<T, 8>(N, in, out, amp, Lg, s);
   }
   return set_error(FURAX_EINVAL, "tmpl_order must be in [0, 7]");
 }
 template furax_status launch_deproject<float>(const furax_noise *, const float *, float *, double *,
-                                              hipStream_t);
+                                              hipStream_t, const double *);
 template furax_status launch_deproject<double>(const furax_noise *, const double *, double *,
-                                               double *, hipStream_t);
+                                               double *, hipStream_t, const double *);
 
 // Apply the weight: N^-1 given a prepared spectrum (kind 1) or the diagonal
 // weights (kind 0), or the template deprojection F_T (kind 2).
@@ -1367,7 +1485,8 @@ furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *sp
     FX_HIP(hipGetLastError());
     return FURAX_OK;
   }
-  if (N->kind == 2) return launch_deproject<T>(N, in, out, nullptr, s);
+  if (N->kind == 2)
+    return launch_deproject<T>(N, in, out, nullptr, s, static_cast<const double *>(spec));
   const int M = os_half_length<T>(N);
   TwTables tw;
   FX_TRY(get_twiddles(2 * M, s, tw));
