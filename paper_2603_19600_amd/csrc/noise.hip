@@ -1199,6 +1199,12 @@ static furax_status launch_os_r32x(const furax_noise *N, const T *in, T *out, co
 // ---------------------------------------------------------------------------
 constexpr int kDeprojThreads = 256;
 
+// P_0 .. P_{NP-1} at x in [-1, 1] by the three-term recurrence, each step
+// multiplied by the constant 1 / (j + 1) rather than divided (within an ulp of
+// the quotient; sample i of a segment of length len sits at
+// x = (2 i + 1) / len - 1, taken as (2 i + 1) * (1 / len) - 1 for the same
+// reason): the basis is evaluated the same way in every pass and in the Gram
+// factor, so the projection stays exact for the basis used.
 template <int NP>
 __device__ __forceinline__ void legendre_at(double x, double (&P)[NP]) {
 #pragma clang fp contract(off)
@@ -1206,7 +1212,7 @@ __device__ __forceinline__ void legendre_at(double x, double (&P)[NP]) {
   if constexpr (NP > 1) P[1] = x;
 #pragma unroll
   for (int j = 1; j + 1 < NP; ++j)
-    P[j + 1] = ((double)(2 * j + 1) * x * P[j] - (double)j * P[j - 1]) / (double)(j + 1);
+    P[j + 1] = ((double)(2 * j + 1) * x * P[j] - (double)j * P[j - 1]) * (1.0 / (double)(j + 1));
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -1285,7 +1291,7 @@ __device__ __forceinline__ void chol_solve(const double (&Lm)[NP][NP], const dou
   }
 }
 
-// Gram sums of sample i of a segment of length dlen, added to g[0..NG).
+// Gram sums of one sample's basis values P, added to g[0..NG).
 template <int NP>
 __device__ __forceinline__ void gram_add(const double (&P)[NP], double *g) {
 #pragma clang fp contract(off)
@@ -1303,13 +1309,13 @@ __global__ void __launch_bounds__(kDeprojThreads) k_deproj_gram(int64_t seg_len,
 #pragma clang fp contract(off)
   constexpr int NG = NP * (NP + 1) / 2;
   __shared__ double part[kDeprojThreads / 64][NG];
-  const double dlen = (double)seg_len;
+  const double inv_len = 1.0 / (double)seg_len;
   double acc[NG];
 #pragma unroll
   for (int v = 0; v < NG; ++v) acc[v] = 0.0;
   for (int64_t i = threadIdx.x; i < seg_len; i += kDeprojThreads) {
     double P[NP];
-    legendre_at<NP>((2.0 * (double)i + 1.0) / dlen - 1.0, P);
+    legendre_at<NP>((2.0 * (double)i + 1.0) * inv_len - 1.0, P);
     gram_add<NP>(P, acc);
   }
   double r[NG];
@@ -1344,7 +1350,7 @@ __global__ void __launch_bounds__(kDeprojThreads) k_deproject(const T *__restric
   const int64_t len = seg + 1 < nseg ? seg_len : n - i0;
   const T *y = in + det * n + i0;
   T *z = out + det * n + i0;
-  const double dlen = (double)len;
+  const double inv_len = 1.0 / (double)len;
   // workgroup-uniform: a full-length segment with a precomputed factor
   const bool known = Lg != nullptr && len == seg_len;
   double acc[NV];
@@ -1353,7 +1359,7 @@ __global__ void __launch_bounds__(kDeprojThreads) k_deproject(const T *__restric
   if (known) {
     for (int64_t i = threadIdx.x; i < len; i += kDeprojThreads) {
       double P[NP];
-      legendre_at<NP>((2.0 * (double)i + 1.0) / dlen - 1.0, P);
+      legendre_at<NP>((2.0 * (double)i + 1.0) * inv_len - 1.0, P);
       const double yi = (double)y[i];
 #pragma unroll
       for (int j = 0; j < NP; ++j) acc[j] += P[j] * yi;
@@ -1361,7 +1367,7 @@ __global__ void __launch_bounds__(kDeprojThreads) k_deproject(const T *__restric
   } else {
     for (int64_t i = threadIdx.x; i < len; i += kDeprojThreads) {
       double P[NP];
-      legendre_at<NP>((2.0 * (double)i + 1.0) / dlen - 1.0, P);
+      legendre_at<NP>((2.0 * (double)i + 1.0) * inv_len - 1.0, P);
       const double yi = (double)y[i];
 #pragma unroll
       for (int j = 0; j < NP; ++j) acc[j] += P[j] * yi;
@@ -1406,7 +1412,7 @@ __global__ void __launch_bounds__(kDeprojThreads) k_deproject(const T *__restric
   const double wk = w[det];
   for (int64_t i = threadIdx.x; i < len; i += kDeprojThreads) {
     double P[NP];
-    legendre_at<NP>((2.0 * (double)i + 1.0) / dlen - 1.0, P);
+    legendre_at<NP>((2.0 * (double)i + 1.0) * inv_len - 1.0, P);
     double fit = 0.0;
 #pragma unroll
     for (int j = 0; j < NP; ++j) fit += c[j] * P[j];
