@@ -371,7 +371,12 @@ furax_status launch_scatter(const PtArgs<T> &a, const T *tod, const double *w_de
 // Superpixel-major accumulation (superpix.hip).
 // ---------------------------------------------------------------------------
 constexpr int kSpPix = 1024;        // pixels per superpixel (32 x 32 nested block)
-constexpr int kChunkRuns = 1024;    // runs per accumulation workgroup
+// Runs per accumulation workgroup: 512 with angle pointing (the smaller LDS
+// run table lets three workgroups share a CU), 1024 with quaternion pointing
+// (register-bound there, where fewer chunks mean less per-chunk set-up).
+template <bool QUAT>
+constexpr int chunk_runs() { return QUAT ? 1024 : 512; }
+constexpr int kChunkRunsMax = 1024;
 constexpr int64_t kMaxRun = 1024;   // longest run of consecutive samples
 
 struct SpChunk {

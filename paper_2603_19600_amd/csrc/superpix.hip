@@ -12,7 +12,7 @@
 //    pixels (a 32 x 32 block of one base face).  Each detector's stream is cut
 //    into runs of consecutive samples that stay in one superpixel, the runs
 //    are sorted by superpixel (stably, so the order is deterministic) and
-//    grouped into chunks of at most kChunkRuns runs;
+//    grouped into chunks of at most chunk_runs() runs;
 //  * at every application one workgroup per chunk streams its runs -- tens of
 //    consecutive samples each, so the loads stay coalesced -- and adds into
 //    LDS sums indexed directly by the pixel's offset inside the superpixel:
@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(kBlock) k_run_bounds(int64_t n, const uint32_t
 // (offset << 24 | exclusive prefix of the lengths within the chunk) and record
 // the chunk's total sample count.
 constexpr int kFinalizeThreads = 1024;
-static_assert(kChunkRuns <= kFinalizeThreads, "one thread per run");
+static_assert(kChunkRunsMax <= kFinalizeThreads, "one thread per run");
 __global__ void __launch_bounds__(kFinalizeThreads) k_run_finalize(uint64_t *__restrict__ runs,
                                                                    SpChunk *__restrict__ chunks) {
   __shared__ int32_t buf[2][kFinalizeThreads];
@@ -287,13 +287,14 @@ furax_status sp_build_runs(SpPlan &sp, const PtArgs<T> &a, const int32_t *plane,
 
   std::vector<SpChunk> ch;
   std::vector<int32_t> first(sp.n_sp + 1);
+  const int64_t cr = a.qb ? chunk_runs<true>() : chunk_runs<false>();
   int64_t r = 0;
   for (int64_t p = 0; p < sp.n_sp; ++p) {
     first[p] = (int32_t)ch.size();
-    for (int64_t c = 0; c < hc[p]; c += kChunkRuns) {
+    for (int64_t c = 0; c < hc[p]; c += cr) {
       SpChunk k;
       k.r0 = fl[p] + c;
-      k.nr = (int32_t)std::min<int64_t>(kChunkRuns, hc[p] - c);
+      k.nr = (int32_t)std::min<int64_t>(cr, hc[p] - c);
       k.sp = (int32_t)p;
       k.w = 0;
       k.pad = 0;
@@ -348,40 +349,44 @@ template furax_status sp_build_runs<double>(SpPlan &, const PtArgs<double> &, co
 // or, when null, the nested plane gives it.
 // ---------------------------------------------------------------------------
 constexpr int kSpThreads = 512;
-// Slot blocks in flight per wave: four, except two for FP64 quaternion
-// pointing, whose per-sample attitude product would otherwise take the
-// registers of a second workgroup per CU (156 VGPRs with four, 108 with two).
+// Occupancy of the accumulation: the LDS below (the superpixel's sums, a HWP
+// table for periods up to 256 samples, 512 runs per chunk) comes to ~50 KB,
+// room for three workgroups per CU, and the slot blocks in flight per wave
+// are four in FP32 but two in FP64, whose wider values would otherwise take
+// more registers than three workgroups leave (80 VGPRs with two; FP64
+// quaternion pointing: 108 instead of 156).
 template <typename T, bool QUAT>
-constexpr int slot_batch() { return QUAT && sizeof(T) == 8 ? 2 : 4; }
-constexpr int kHwpPeriodMax = 1024;           // tabulated HWP periods
+constexpr int slot_batch() { return sizeof(T) == 8 ? 2 : 4; }
+constexpr int kHwpPeriodMax = 256;            // tabulated HWP periods
 constexpr int kHwpTable = kHwpPeriodMax + (int)kMaxRun;
 
+template <int NR>
 struct SpRunLds {
-  int32_t det[kChunkRuns], i0[kChunkRuns];    // detector, first sample index
-  int32_t pre[kChunkRuns + 1];
-  int32_t hwp0[kChunkRuns];                   // (first sample index) mod hwp_den
-  double gw[kChunkRuns], dpsi[kChunkRuns];
+  int32_t det[NR], i0[NR];    // detector, first sample index
+  int32_t pre[NR + 1];
+  int32_t hwp0[NR];           // (first sample index) mod hwp_den
+  double gw[NR], dpsi[NR];
 };
-template <int KIND>
+template <int KIND, int NR>
 struct SpLds;
-template <>
-struct SpLds<0> {
+template <int NR>
+struct SpLds<0, NR> {
   double acc[3][kSpPix];
   union {
     double two_alpha[kHwpTable];
     double2 turn4a[kHwpPeriodMax];   // quaternion pointing: (cos, sin) 4 alpha for u < den
   };
-  SpRunLds run;
+  SpRunLds<NR> run;
 };
-template <>
-struct SpLds<1> {
+template <int NR>
+struct SpLds<1, NR> {
   double acc[6][kSpPix];
   int32_t hits[kSpPix];
   union {
     double two_alpha[kHwpTable];
     double2 turn4a[kHwpPeriodMax];   // quaternion pointing: (cos, sin) 4 alpha for u < den
   };
-  SpRunLds run;
+  SpRunLds<NR> run;
 };
 
 // Last run r in [lo, hi) with pre[r] <= j (pre ascending, pre[lo] <= j).
@@ -400,7 +405,7 @@ k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_
            const uint16_t *__restrict__ local, const int32_t *__restrict__ nest_plane,
            const uint64_t *__restrict__ runs, const SpChunk *__restrict__ chunks, int32_t log2P,
            double *__restrict__ partial) {
-  __shared__ SpLds<KIND> L;
+  __shared__ SpLds<KIND, chunk_runs<QUAT>()> L;
   constexpr int NV = KIND == 0 ? 3 : 6;
   const int P = 1 << log2P;
   const SpChunk ch = chunks[blockIdx.x];
