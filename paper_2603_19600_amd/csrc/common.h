@@ -371,11 +371,12 @@ furax_status launch_scatter(const PtArgs<T> &a, const T *tod, const double *w_de
 // Superpixel-major accumulation (superpix.hip).
 // ---------------------------------------------------------------------------
 constexpr int kSpPix = 1024;        // pixels per superpixel (32 x 32 nested block)
-// Runs per accumulation workgroup: 512 with angle pointing (the smaller LDS
-// run table lets three workgroups share a CU), 1024 with quaternion pointing
-// (register-bound there, where fewer chunks mean less per-chunk set-up).
-template <bool QUAT>
-constexpr int chunk_runs() { return QUAT ? 1024 : 512; }
+// Runs per accumulation workgroup (SpPlan::chunk_runs): 512 with angle
+// pointing up to nside 512, where the smaller LDS run table lets three
+// workgroups share a CU; 1024 otherwise -- with quaternion pointing the kernel
+// is register-bound, and at finer nside runs are shorter, so that smaller
+// chunks would hold too few samples to repay their set-up.
+constexpr int kChunkRunsSmall = 512;
 constexpr int kChunkRunsMax = 1024;
 constexpr int64_t kMaxRun = 1024;   // longest run of consecutive samples
 
@@ -390,6 +391,7 @@ struct SpChunk {
 // Everything the superpixel accumulation needs, built once per pointing.
 struct SpPlan {
   int32_t nside = 0, log2P = 0, n_values = 0;
+  int32_t chunk_runs = kChunkRunsMax;   // runs per chunk: kChunkRunsSmall or kChunkRunsMax
   int64_t npix = 0, n_sp = 0, n_runs = 0, n_chunks = 0;
   int32_t *n2r = nullptr, *r2n = nullptr;   // nested -> ring, ring -> nested [npix]
   uint64_t *runs = nullptr;                 // offset << 24 | chunk-local prefix of lengths

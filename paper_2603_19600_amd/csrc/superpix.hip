@@ -12,7 +12,7 @@
 //    pixels (a 32 x 32 block of one base face).  Each detector's stream is cut
 //    into runs of consecutive samples that stay in one superpixel, the runs
 //    are sorted by superpixel (stably, so the order is deterministic) and
-//    grouped into chunks of at most chunk_runs() runs;
+//    grouped into chunks of at most SpPlan::chunk_runs runs;
 //  * at every application one workgroup per chunk streams its runs -- tens of
 //    consecutive samples each, so the loads stay coalesced -- and adds into
 //    LDS sums indexed directly by the pixel's offset inside the superpixel:
@@ -287,7 +287,8 @@ furax_status sp_build_runs(SpPlan &sp, const PtArgs<T> &a, const int32_t *plane,
 
   std::vector<SpChunk> ch;
   std::vector<int32_t> first(sp.n_sp + 1);
-  const int64_t cr = a.qb ? chunk_runs<true>() : chunk_runs<false>();
+  sp.chunk_runs = !a.qb && sp.nside <= 512 ? kChunkRunsSmall : kChunkRunsMax;
+  const int64_t cr = sp.chunk_runs;
   int64_t r = 0;
   for (int64_t p = 0; p < sp.n_sp; ++p) {
     first[p] = (int32_t)ch.size();
@@ -349,14 +350,17 @@ template furax_status sp_build_runs<double>(SpPlan &, const PtArgs<double> &, co
 // or, when null, the nested plane gives it.
 // ---------------------------------------------------------------------------
 constexpr int kSpThreads = 512;
-// Occupancy of the accumulation: the LDS below (the superpixel's sums, a HWP
-// table for periods up to 256 samples, 512 runs per chunk) comes to ~50 KB,
-// room for three workgroups per CU, and the slot blocks in flight per wave
-// are four in FP32 but two in FP64, whose wider values would otherwise take
-// more registers than three workgroups leave (80 VGPRs with two; FP64
-// quaternion pointing: 108 instead of 156).
-template <typename T, bool QUAT>
-constexpr int slot_batch() { return sizeof(T) == 8 ? 2 : 4; }
+// Occupancy of the accumulation: with 512 runs per chunk the LDS below (the
+// superpixel's sums, a HWP table for periods up to 256 samples, the run table)
+// comes to ~50 KB, room for three workgroups per CU, and FP64 then takes two
+// slot blocks per wave instead of four, whose wider values would otherwise
+// take more registers than three workgroups leave (80 VGPRs with two).  FP64
+// quaternion pointing takes two as well (108 VGPRs instead of 156: a second
+// workgroup per CU).
+template <typename T, bool QUAT, int NR>
+constexpr int slot_batch() {
+  return sizeof(T) == 8 && (QUAT || NR == kChunkRunsSmall) ? 2 : 4;
+}
 constexpr int kHwpPeriodMax = 256;            // tabulated HWP periods
 constexpr int kHwpTable = kHwpPeriodMax + (int)kMaxRun;
 
@@ -399,13 +403,13 @@ __device__ __forceinline__ int32_t run_of(const int32_t *pre, int32_t lo, int32_
   return lo;
 }
 
-template <typename T, int KIND, bool QUAT>
+template <typename T, int KIND, bool QUAT, int NR>
 __global__ void __launch_bounds__(kSpThreads)
 k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_det,
            const uint16_t *__restrict__ local, const int32_t *__restrict__ nest_plane,
            const uint64_t *__restrict__ runs, const SpChunk *__restrict__ chunks, int32_t log2P,
            double *__restrict__ partial) {
-  __shared__ SpLds<KIND, chunk_runs<QUAT>()> L;
+  __shared__ SpLds<KIND, NR> L;
   constexpr int NV = KIND == 0 ? 3 : 6;
   const int P = 1 << log2P;
   const SpChunk ch = chunks[blockIdx.x];
@@ -455,7 +459,7 @@ k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_
   if (threadIdx.x == 0) L.run.pre[ch.nr] = ch.w;
   __syncthreads();
 
-  constexpr int kSlotBatch = slot_batch<T, QUAT>();
+  constexpr int kSlotBatch = slot_batch<T, QUAT, NR>();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int kWaves = kSpThreads / 64;
   const int32_t base = ch.sp << log2P;
@@ -603,13 +607,17 @@ furax_status sp_transpose(const SpPlan &sp, const PtArgs<T> &a, const T *tod,
                           double *q, MapLayout ql, hipStream_t s) {
   if (sp.n_chunks > 0) {
     if (a.qb)
-      hipLaunchKernelGGL((k_sp_accum<T, 0, true>), dim3((unsigned)sp.n_chunks), dim3(kSpThreads),
-                         0, s, a, tod, w_det, local, nest_plane, sp.runs, sp.chunks, sp.log2P,
-                         sp.partial);
+      hipLaunchKernelGGL((k_sp_accum<T, 0, true, kChunkRunsMax>), dim3((unsigned)sp.n_chunks),
+                         dim3(kSpThreads), 0, s, a, tod, w_det, local, nest_plane, sp.runs,
+                         sp.chunks, sp.log2P, sp.partial);
+    else if (sp.chunk_runs == kChunkRunsSmall)
+      hipLaunchKernelGGL((k_sp_accum<T, 0, false, kChunkRunsSmall>), dim3((unsigned)sp.n_chunks),
+                         dim3(kSpThreads), 0, s, a, tod, w_det, local, nest_plane, sp.runs,
+                         sp.chunks, sp.log2P, sp.partial);
     else
-      hipLaunchKernelGGL((k_sp_accum<T, 0, false>), dim3((unsigned)sp.n_chunks), dim3(kSpThreads),
-                         0, s, a, tod, w_det, local, nest_plane, sp.runs, sp.chunks, sp.log2P,
-                         sp.partial);
+      hipLaunchKernelGGL((k_sp_accum<T, 0, false, kChunkRunsMax>), dim3((unsigned)sp.n_chunks),
+                         dim3(kSpThreads), 0, s, a, tod, w_det, local, nest_plane, sp.runs,
+                         sp.chunks, sp.log2P, sp.partial);
     FX_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_sp_reduce, dim3(grid_for(sp.npix, 16384)), dim3(kBlock), 0, s, sp.npix,
@@ -632,13 +640,20 @@ furax_status sp_bj_build(const SpPlan &sp, const PtArgs<T> &a, const double *w_d
                          const int32_t *nest_plane, double *M6, int32_t *hits, hipStream_t s) {
   if (sp.n_chunks > 0) {
     if (a.qb)
-      hipLaunchKernelGGL((k_sp_accum<T, 1, true>), dim3((unsigned)sp.n_chunks), dim3(kSpThreads),
-                         0, s, a, (const T *)nullptr, w_det, (const uint16_t *)nullptr,
-                         nest_plane, sp.runs, sp.chunks, sp.log2P, sp.partial);
+      hipLaunchKernelGGL((k_sp_accum<T, 1, true, kChunkRunsMax>), dim3((unsigned)sp.n_chunks),
+                         dim3(kSpThreads), 0, s, a, (const T *)nullptr, w_det,
+                         (const uint16_t *)nullptr, nest_plane, sp.runs, sp.chunks, sp.log2P,
+                         sp.partial);
+    else if (sp.chunk_runs == kChunkRunsSmall)
+      hipLaunchKernelGGL((k_sp_accum<T, 1, false, kChunkRunsSmall>), dim3((unsigned)sp.n_chunks),
+                         dim3(kSpThreads), 0, s, a, (const T *)nullptr, w_det,
+                         (const uint16_t *)nullptr, nest_plane, sp.runs, sp.chunks, sp.log2P,
+                         sp.partial);
     else
-      hipLaunchKernelGGL((k_sp_accum<T, 1, false>), dim3((unsigned)sp.n_chunks), dim3(kSpThreads),
-                         0, s, a, (const T *)nullptr, w_det, (const uint16_t *)nullptr,
-                         nest_plane, sp.runs, sp.chunks, sp.log2P, sp.partial);
+      hipLaunchKernelGGL((k_sp_accum<T, 1, false, kChunkRunsMax>), dim3((unsigned)sp.n_chunks),
+                         dim3(kSpThreads), 0, s, a, (const T *)nullptr, w_det,
+                         (const uint16_t *)nullptr, nest_plane, sp.runs, sp.chunks, sp.log2P,
+                         sp.partial);
     FX_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_sp_reduce, dim3(grid_for(sp.npix, 16384)), dim3(kBlock), 0, s, sp.npix,
