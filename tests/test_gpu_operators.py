@@ -276,6 +276,28 @@ def test_diag_noise(fx):
     assert np.array_equal(got, w[:, None] * y)
 
 
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 3e-6)])
+def test_superpixel_paths_at_nside_1024(fx, dtype, tol):
+    """Angle pointing at nside 1024: the superpixel P^T and block-Jacobi build
+    use 1024-run chunks there (runs are shorter than at nside 512)."""
+    nside, nd, ns, b = 1024, 3, 30011, 257
+    w, h, t = case(nside, nd, ns, dtype=dtype)
+    P = to_pointing(nside, t)
+    lags = synth.toeplitz_lags(w, b)
+    N = fx.Noise("band", nd, ns, lags=torch.from_numpy(lags).to(dev()))
+    prob = omm.Problem(nside, h["theta"], h["phi"], h["psi"], "band", lags=lags,
+                       gain=h["gain"], dpsi=h["dpsi"], hwp=h["hwp"])
+    x = synth.sky_map(w)
+    pix, c, s = prob.geometry()
+    ref = omm.normal_apply(prob, pix, c, s, x.numpy())
+    got = fx.normal_apply(P, N, x.to(dev())).cpu().numpy()
+    assert rel_err(got, ref) <= tol
+    M6, hits = fx.bj_build(P, N)
+    M_ref, h_ref = omm.bj_build(pix, c, s, prob.wdiag(), prob.npix, prob.gain)
+    assert np.array_equal(hits.cpu().numpy(), h_ref)
+    assert rel_err(M6.cpu().numpy(), M_ref) <= (1e-12 if dtype == "f64" else 1e-6)
+
+
 # ---------------------------------------------------------------- normal operator
 @pytest.mark.parametrize("kind,dtype", [("diag", "f64"), ("band", "f64"), ("diag", "f32"),
                                         ("band", "f32")])
