@@ -1419,7 +1419,8 @@ __global__ void __launch_bounds__(kDeprojThreads) k_deproject(const T *__restric
     double fit = 0.0;
 #pragma unroll
     for (int j = 0; j < NP; ++j) fit += c[j] * P[j];
-    z[i] = (T)(wk * ((double)y[i] - fit));
+    // the output is not read again by this kernel: stored non-temporally
+    __builtin_nontemporal_store((T)(wk * ((double)y[i] - fit)), z + i);
   }
 }
 
