@@ -53,11 +53,13 @@ def test_gap_fill_matches_oracle(fx, b, dtype, tol):
     assert rel_err(got[gaps], ref[gaps]) <= tol
 
 
-def test_gap_fill_long_band_matches_oracle(fx):
-    """A covariance of more than 4096 lags (32768-sample overlap-save blocks)."""
-    c, d, nr, gaps = _case(2, 7000, 4500, seed=11)
+@pytest.mark.parametrize("n_samp", [7000, 7001])
+def test_gap_fill_long_band_matches_oracle(fx, n_samp):
+    """A covariance of more than 4096 lags (32768-sample overlap-save blocks),
+    on even (sample pairs) and odd (single samples) stream lengths."""
+    c, d, nr, gaps = _case(2, n_samp, 4500, seed=11)
     ref = ogf.gap_fill(d, gaps, nr, c)
-    C = fx.Noise("band", 2, 7000, lags=torch.from_numpy(c).to(dev()))
+    C = fx.Noise("band", 2, n_samp, lags=torch.from_numpy(c).to(dev()))
     out, iters, rel, st = fx.gap_fill(C, torch.from_numpy(gaps.astype(np.uint8)).to(dev()),
                                       torch.from_numpy(d).to(dev()), torch.from_numpy(nr).to(dev()),
                                       max_iter=2000, rtol=1e-12)

@@ -178,7 +178,8 @@ def test_hits_bitexact_and_sum(fx):
                                       (24_579, 4097), (5000, 4096), (9000, 8192),
                                       (40_003, 3072), (70_001, 3073), (26_625, 3500),
                                       (26_624, 3073), (26_625, 3073), (5000, 5000),
-                                      (30_002, 2560), (30_002, 2561)])
+                                      (30_002, 2560), (30_002, 2561), (30_001, 2500),
+                                      (30_001, 3000)])
 def test_band_noise_f64(fx, n_samp, b):
     rng = np.random.default_rng(n_samp + b)
     y = rng.standard_normal((2, n_samp))
