@@ -29,8 +29,10 @@ Pins: with diagonal N the block-Jacobi preconditioner IS the inverse, so PCG
 reaches the per-pixel np.linalg.solve binned map in one iteration; with band
 N on tiny inputs the result equals np.linalg.solve of the dense normal
 matrix; noiseless data recover the input map exactly; the A-norm of the
-error decreases monotonically; the 3x3 inverse and rcond agree with
-np.linalg.inv / np.linalg.cond; a detector-split sum equals the unsplit one.
+error decreases monotonically; the 3x3 inverse and rcond match a block
+inverted by hand (adjugate over determinant) and diagonal blocks, and blocks
+singular in exact arithmetic come out invalid; a detector-split sum equals the
+unsplit one.
 """
 from __future__ import annotations
 
@@ -81,56 +83,42 @@ def sym3(M6) -> np.ndarray:
 
 
 def bj_invert(M6, hits, rcond_min: float = 1e-3, min_hits: int = 3):
-    """Inverse of each symmetric 3x3 block from its Cholesky factorisation.
+    """Inverse and 1-norm reciprocal condition number of each 3x3 block, by definition.
 
-    The blocks are sums of w (1, c, s)^T (1, c, s) with w > 0, hence positive
-    semi-definite, and M = L L^T is the backward-stable way to invert them:
-    a block that is singular in exact arithmetic (every sample of the pixel at
-    the same polariser angle, or at two angles pi/2 apart) meets a pivot that
-    is zero, negative or of rounding size, so its computed inverse is huge and
-    its rcond tiny.  (The adjugate / determinant formula does not have that
-    property: for a rank-one block every cofactor is rounding noise and their
-    ratio can be of order one.)  M^-1 = L^-T L^-1 with L^-1 formed by forward
-    substitution.
+    For each pixel's block M (sym3 of M6):
+      * rcond = 1 / (||M||_1 ||M^-1||_1), i.e. 1 / numpy.linalg.cond(M, 1), for a
+        block that is positive definite (every eigenvalue > 0, numpy.linalg.eigvalsh)
+        with a finite condition number; rcond = 0 for any other block (singular,
+        indefinite, non-finite).  The blocks of the method are sums of
+        w (1, c, s)^T (1, c, s) with w > 0, so they are positive semi-definite,
+        and one that is singular in exact arithmetic (all of a pixel's samples at
+        one polariser angle, or at two angles pi/2 apart) has a tiny rcond, or 0;
+      * M^-1 = numpy.linalg.inv(M) on the blocks with rcond > 0, 0 elsewhere;
+      * valid = hits >= min_hits and rcond >= rcond_min; Minv is 0 on invalid pixels.
 
-    Returns (Minv [6, npix], valid [npix] bool, rcond [npix]).  rcond is the
-    1-norm reciprocal condition number 1 / (||M||_1 ||M^-1||_1); a block
-    whose factorisation meets a non-positive pivot has inverse 0 and rcond 0.
+    Returns (Minv [6, npix] as II, IQ, IU, QQ, QU, UU; valid [npix] bool; rcond [npix]).
     """
-    a, b, c, d, e, f = (np.asarray(v, dtype=np.float64) for v in M6)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        l11 = np.sqrt(a)
-        l21 = b / l11
-        l31 = c / l11
-        t22 = d - l21 * l21
-        l22 = np.sqrt(t22)
-        l32 = (e - l31 * l21) / l22
-        t33 = f - l31 * l31 - l32 * l32
-        l33 = np.sqrt(t33)
-        i11 = 1.0 / l11
-        i22 = 1.0 / l22
-        i33 = 1.0 / l33
-        i21 = -(l21 * i11) * i22
-        i32 = -(l32 * i22) * i33
-        i31 = -(l31 * i11 + l32 * i21) * i33
-        inv = np.stack([i11 * i11 + i21 * i21 + i31 * i31,
-                        i21 * i22 + i31 * i32,
-                        i31 * i33,
-                        i22 * i22 + i32 * i32,
-                        i32 * i33,
-                        i33 * i33])
-        ok = (a > 0.0) & (t22 > 0.0) & (t33 > 0.0) & np.isfinite(inv).all(axis=0)
-        inv = np.where(ok[None, :], inv, 0.0)
-        n1 = np.maximum.reduce([np.abs(a) + np.abs(b) + np.abs(c),
-                                np.abs(b) + np.abs(d) + np.abs(e),
-                                np.abs(c) + np.abs(e) + np.abs(f)])
-        ia, ib, ic, id_, ie, if_ = inv
-        n1i = np.maximum.reduce([np.abs(ia) + np.abs(ib) + np.abs(ic),
-                                 np.abs(ib) + np.abs(id_) + np.abs(ie),
-                                 np.abs(ic) + np.abs(ie) + np.abs(if_)])
-        rcond = 1.0 / (n1 * n1i)
-    rcond = np.where(ok & np.isfinite(rcond), rcond, 0.0)
-    valid = (hits >= min_hits) & (rcond >= rcond_min)
+    Ms = sym3(np.asarray(M6, dtype=np.float64))
+    n = Ms.shape[0]
+    rcond = np.zeros(n)
+    inv = np.zeros((6, n))
+    # an all-zero block (unobserved pixel) is singular: rcond 0, inverse 0
+    fin = np.isfinite(Ms).all(axis=(1, 2)) & (Ms != 0.0).any(axis=(1, 2))
+    if fin.any():
+        Mf = Ms[fin]
+        with np.errstate(all="ignore"):
+            cond = np.linalg.cond(Mf, 1)              # inf for a singular block
+        pd = np.linalg.eigvalsh(Mf)[:, 0] > 0.0
+        ok = pd & np.isfinite(cond)
+        rc = np.zeros(len(Mf))
+        rc[ok] = 1.0 / cond[ok]
+        rcond[fin] = rc
+        idx = np.flatnonzero(fin)[ok]
+        if idx.size:
+            Mi = np.linalg.inv(Ms[idx])
+            inv[:, idx] = np.stack([Mi[:, 0, 0], Mi[:, 0, 1], Mi[:, 0, 2],
+                                    Mi[:, 1, 1], Mi[:, 1, 2], Mi[:, 2, 2]])
+    valid = (np.asarray(hits) >= min_hits) & (rcond >= rcond_min)
     inv = np.where(valid[None, :], inv, 0.0)
     return inv, valid, rcond
 
@@ -144,7 +132,11 @@ def bj_apply(Minv6, r) -> np.ndarray:
 
 
 def dot(u, v) -> float:
-    return math.fsum((np.asarray(u) * np.asarray(v)).ravel().tolist())
+    """sum_j u_j v_j, each product rounded once and the sum exactly rounded
+    (math.fsum); zero products (unobserved unknowns) are left out, which does
+    not change an exact sum."""
+    prod = (np.asarray(u) * np.asarray(v)).ravel()
+    return math.fsum(prod[prod != 0.0].tolist())
 
 
 @dataclass

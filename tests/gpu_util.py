@@ -46,3 +46,38 @@ def rel_err(a, b):
     b = np.asarray(b, dtype=np.float64)
     den = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / (den if den > 0 else 1.0))
+
+
+def check_pixel_mismatches(nside, theta, phi, got, ref, z=None):
+    """Every pixel where the device (got) and the oracle (ref) disagree must be
+    explained by a one-ulp difference of the cosine: with z_cr the correctly
+    rounded cos(theta) (mpmath at 40 digits; or the given z, for directions
+    whose cosine is known), the pixel must change between z_cr - 1 ulp and
+    z_cr + 1 ulp (the direction lies in the ulp band of a ring or pixel edge),
+    got must be the pixel of one of z_cr - 1 ulp, z_cr, z_cr + 1 ulp, and the
+    oracle's answer too.  No other mismatch is allowed.  Returns the number of
+    explained mismatches."""
+    import mpmath
+
+    from oracle import healpix as ohp
+
+    got = np.asarray(got).ravel()
+    ref = np.asarray(ref).ravel()
+    theta = np.asarray(theta, dtype=np.float64).ravel()
+    phi = np.asarray(phi, dtype=np.float64).ravel()
+    mism = np.flatnonzero(got != ref)
+    for i in mism:
+        if z is None:
+            with mpmath.workdps(40):
+                zc = float(mpmath.cos(mpmath.mpf(float(theta[i]))))
+        else:
+            zc = float(np.asarray(z).ravel()[i])
+        cand = np.array([np.nextafter(zc, -2.0), zc, np.nextafter(zc, 2.0)])
+        pc = ohp.zphi2pix_ring(nside, cand, np.full(3, phi[i]))
+        band = len(set(pc.tolist())) > 1
+        assert band, (f"pixel mismatch outside the ulp band: theta={theta[i]!r} phi={phi[i]!r} "
+                      f"got {got[i]} oracle {ref[i]} (cos band pixels {pc.tolist()})")
+        assert int(got[i]) in pc.tolist() and int(ref[i]) in pc.tolist(), (
+            f"theta={theta[i]!r} phi={phi[i]!r}: got {got[i]}, oracle {ref[i]}, "
+            f"pixels within one ulp of the correctly rounded cosine {pc.tolist()}")
+    return len(mism)

@@ -14,7 +14,7 @@ from oracle import mapmaker as omm
 from oracle import noise as onz
 from oracle import pointing as opt
 from paper_2603_19600_amd import synth
-from tests.gpu_util import case, dev, rel_err, to_pointing
+from tests.gpu_util import case, check_pixel_mismatches, dev, rel_err, to_pointing
 
 pytestmark = pytest.mark.gpu
 
@@ -39,8 +39,8 @@ def test_ang2pix_random_points_bitexact(fx, nside):
     th, ph = synth.uniform_sphere(nside, 2_000_000)
     ref = ohp.ang2pix_ring(nside, th.numpy(), ph.numpy())
     got = fx.ang2pix(nside, th.to(dev()), ph.to(dev())).cpu().numpy()
-    mism = np.flatnonzero(got != ref)
-    assert len(mism) <= 2, (nside, mism[:10])
+    # bit-exact except where a one-ulp cosine difference is resolved by mpmath
+    check_pixel_mismatches(nside, th.numpy(), ph.numpy(), got, ref)
 
 
 @pytest.mark.parametrize("nside", [4, 64, 1024])
@@ -61,13 +61,10 @@ def test_ang2pix_ring_boundaries_ulp_neighbourhood(fx, nside):
     ph[::4] = np.round(ph[::4] / (math.pi / (2 * n))) * (math.pi / (2 * n))
     ref = ohp.ang2pix_ring(n, th, ph)
     got = fx.ang2pix(n, torch.from_numpy(th).to(dev()), torch.from_numpy(ph).to(dev()))
-    mism = np.flatnonzero(got.cpu().numpy() != ref)
     # a mismatch is only acceptable where the device cosine differs by 1 ulp:
-    # then z sits within ~1 ulp of a boundary and both answers are adjacent rings
-    for i in mism:
-        z = math.cos(th[i])
-        assert min(abs(z - b) for b in zs) < 4 * np.spacing(1.0), (th[i], ph[i])
-    assert len(mism) <= max(2, th.size // 1000)
+    # then z sits within 1 ulp of a boundary, and mpmath's correctly rounded
+    # cosine decides between the two adjacent pixels
+    check_pixel_mismatches(n, th, ph, got.cpu().numpy(), ref)
 
 
 def test_ang2pix_f32_inputs_and_invalid(fx):
@@ -75,7 +72,7 @@ def test_ang2pix_f32_inputs_and_invalid(fx):
     th32, ph32 = th.float(), ph.float()
     ref = ohp.ang2pix_ring(256, th32.double().numpy(), ph32.double().numpy())
     got = fx.ang2pix(256, th32.to(dev()), ph32.to(dev())).cpu().numpy()
-    assert (got != ref).sum() <= 1
+    check_pixel_mismatches(256, th32.double().numpy(), ph32.double().numpy(), got, ref)
     bad_t = torch.tensor([-0.1, math.pi + 0.1, float("nan"), 0.3, 1.0, 0.0, math.pi],
                          dtype=torch.float64)
     bad_p = torch.tensor([0.0, 0.0, 0.0, float("nan"), float("inf"), 7.0, -7.0],

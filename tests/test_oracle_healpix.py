@@ -109,3 +109,48 @@ def test_scan_continuity():
     pixsize = math.sqrt(4 * math.pi / hp.npix(w.nside))
     # the scan moves ~0.09 deg per sample; consecutive pixel centres are neighbours
     assert dist.max() < 2.5 * pixsize + math.radians(0.1)
+
+
+def test_pixel_mismatch_check_accepts_only_the_ulp_band():
+    """The GPU tests' pixel comparison accepts a disagreement only where a
+    one-ulp change of the cosine moves the pixel (resolved with mpmath's
+    correctly rounded cosine); a wrong pixel anywhere else fails."""
+    from tests.gpu_util import check_pixel_mismatches
+
+    nside = 64
+    # directions whose cosine lies within an ulp of an equatorial pixel edge:
+    # at phi = 0.3, floor(N (0.5 + tt) - 0.75 N z) steps at z = (N (0.5 + tt) - 40) / (0.75 N)
+    ph0 = 0.3
+    z_edge = (nside * (0.5 + ph0 / (math.pi / 2)) - 40.0) / (0.75 * nside)
+    z = z_edge + np.arange(-200, 201) * np.spacing(z_edge)
+    ph = np.full(z.size, ph0)
+    th = np.arccos(z)                      # unused when the cosine is given
+    ref = hp.zphi2pix_ring(nside, z, ph)
+    lo = hp.zphi2pix_ring(nside, np.nextafter(z, -2.0), ph)
+    hi = hp.zphi2pix_ring(nside, np.nextafter(z, 2.0), ph)
+    flipped = 0
+    for i in np.flatnonzero(lo != hi):
+        for a in (lo[i], hi[i]):
+            if a != ref[i]:
+                got = ref.copy()
+                got[i] = a
+                assert check_pixel_mismatches(nside, th, ph, got, ref, z=z) == 1
+                flipped += 1
+    # two ulps away from the edge the same substitution is rejected
+    i = int(np.flatnonzero(lo != hi)[0])
+    far = i - 3 if ref[i - 3] == ref[i] else i + 3
+    got = ref.copy()
+    got[far] = lo[i] if lo[i] != ref[far] else hi[i]
+    with pytest.raises(AssertionError):
+        check_pixel_mismatches(nside, th, ph, got, ref, z=z)
+    assert flipped >= 1
+    # a planted wrong pixel away from every edge is rejected
+    rng = np.random.default_rng(5)
+    th2 = np.arccos(rng.uniform(-0.5, 0.5, 100))
+    ph2 = rng.uniform(0, 2 * math.pi, 100)
+    ref2 = hp.ang2pix_ring(nside, th2, ph2)
+    bad = ref2.copy()
+    bad[17] += 1
+    with pytest.raises(AssertionError):
+        check_pixel_mismatches(nside, th2, ph2, bad, ref2)
+    assert check_pixel_mismatches(nside, th2, ph2, ref2, ref2) == 0

@@ -44,6 +44,24 @@ def test_bj_inverse_and_rcond_vs_numpy():
     assert not v2.any()
 
 
+def test_bj_invert_closed_forms():
+    """A block inverted by hand and diagonal blocks.
+
+    M = [[4,1,0],[1,3,1],[0,1,2]]: det 18, adjugate [[5,-2,1],[-2,8,-4],[1,-4,11]],
+    so M^-1 = adj/18, ||M||_1 = 5, ||M^-1||_1 = 16/18 and rcond = 18/80.
+    diag(a, b, c): M^-1 = diag(1/a, 1/b, 1/c), rcond = min/max of (a, b, c).
+    A zero block (unobserved pixel) has rcond 0 and inverse 0."""
+    M6 = np.array([[4.0, 2.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 0.0], [3.0, 5.0, 0.0],
+                   [1.0, 0.0, 0.0], [2.0, 0.5, 0.0]])
+    inv, valid, rcond = mm.bj_invert(M6, np.array([5, 5, 5]), 1e-3, 3)
+    np.testing.assert_allclose(inv[:, 0], np.array([5, -2, 1, 8, -4, 11]) / 18.0, rtol=1e-14)
+    np.testing.assert_allclose(rcond[0], 18.0 / 80.0, rtol=1e-14)
+    np.testing.assert_allclose(inv[:, 1], [0.5, 0, 0, 0.2, 0, 2.0], rtol=1e-15)
+    np.testing.assert_allclose(rcond[1], 0.5 / 5.0, rtol=1e-15)
+    assert valid[0] and valid[1] and not valid[2]
+    assert rcond[2] == 0.0 and np.all(inv[:, 2] == 0.0)
+
+
 def test_bj_rank_deficient_blocks_are_invalid():
     """Blocks singular in exact arithmetic -- every sample at one polariser angle
     (rank 1), or at two angles pi/2 apart (rank 2) -- must come out invalid with
