@@ -5,17 +5,22 @@ A step is one block-Jacobi PCG iteration of the map-maker: q = P^T N^-1 P p
 P^T) plus the FP64 vector updates and dot products.  Inputs are synthetic,
 seeded and resident in HBM before the timed region.
 
-Default workload: HEALPix nside 512, 256 detectors x 2^20 samples, FP64
-pointing/TOD, 1/f noise weighted by a band-Toeplitz of 4096 lags, ideal HWP at
-2 Hz.  The FP32 variant of the same workload (FP32 pointing, TOD and FFT,
-FP64 accumulation, dots and preconditioner) is measured beside it, and both
-again with boresight-quaternion pointing (the same scan given as one attitude
-per time sample and one per detector, expanded per sample in the kernels) and
-with template deprojection (the weight F_T of Eq. (3): white weights with
-Legendre baselines of degree 0..3 removed from every 4096-sample segment) in
-place of the band-Toeplitz N^-1.  An FP32 workload (--config 5: nside 1024,
-1024 detectors x 2^20 samples, 8192 lags) is measured beside its FP64
-counterpart.
+Default workload (the largest single-GPU one): HEALPix nside 1024, 1024
+detectors x 2^20 samples (1.07e9 samples), 1/f noise weighted by a
+band-Toeplitz of 8192 lags, ideal HWP at 2 Hz, 100 PCG iterations.  The
+headline is the FP32 path (FP32 pointing, TOD and FFT arithmetic; FP64
+binning, vectors, dot products and 3x3 inversion); the plain FP64 path of the
+same workload is measured beside it, and the line reports the relative
+difference of the two solved maps after the 100 iterations.  Also measured:
+the same workload with boresight-quaternion pointing, with template
+deprojection (the weight F_T of Eq. (3)) in place of N^-1, the chi-square
+gradient of the differentiation workload (nside 256, 64 x 2^20 FP32), gap
+filling, a device copy (the achievable bandwidth), and the FP64 oracle's
+P^T N^-1 P on a 16-detector prefix of the workload on the host's cores.
+
+The headline iterations are timed with HIP events around the timed steps
+only; the per-phase times come from a separate pass of the same number of
+iterations with the library's phase events on.
 
 Prints one JSON line (rank 0).
 """
@@ -36,13 +41,18 @@ if ROOT not in sys.path:
 
 METRIC = "TOD samples/s per PCG iter of P^T N^-1 P (FP32 vs FP64) + % HBM peak"
 HBM_PEAK_GBS = 8000.0
+TARGET_FRAC = 0.60
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_inputs(w, dev):
+def make_inputs(w, dev, prec):
+    """Pointing, noise model and data of workload w (FP32 canonical inputs) for
+    the path of precision prec: the FP32 path reads the FP32 arrays, the FP64
+    path their exact FP64 promotion, and both solve the same data (the FP32
+    path's signal plus white noise)."""
     import torch
 
     from paper_2603_19600_amd import furax as fx
@@ -50,13 +60,21 @@ def make_inputs(w, dev):
 
     t0 = time.time()
     hwp = (w.hwp_num, w.hwp_den, 0.0) if w.hwp else None
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    m_true = synth.sky_map(w, device=dev)
     if w.pointing == "quat":
         P = fx.QuatPointing(w.nside, synth.boresight_quaternions(w, device=dev),
-                            synth.detector_quaternions(w, device=dev),
-                            torch.float64 if w.dtype == "f64" else torch.float32, hwp=hwp)
+                            synth.detector_quaternions(w, device=dev), torch.float32, hwp=hwp)
+        d = fx.pointing_apply(P, m_true.float())
+        if prec == "f64":
+            P = P.with_(dtype=torch.float64)
     else:
-        pt = synth.pointing(w, device=dev, det_chunk=8)
+        pt = synth.pointing(w, device=dev, det_chunk=8)          # canonical dtype of w
         P = fx.Pointing(w.nside, pt.theta, pt.phi, pt.psi, hwp=hwp)
+        d = fx.pointing_apply(P, m_true.to(pt.theta.dtype))
+        if prec != w.dtype:
+            P = P.with_(theta=pt.theta.to(tdt), phi=pt.phi.to(tdt), psi=pt.psi.to(tdt))
+        del pt
     if w.noise == "band":
         lags = torch.from_numpy(synth.toeplitz_lags(w)).to(dev)
         N = fx.Noise("band", w.n_det, w.n_samp, lags=lags)
@@ -69,50 +87,54 @@ def make_inputs(w, dev):
         N = fx.Noise("diag", w.n_det, w.n_samp,
                      inv_var=torch.full((w.n_det,), 1.0 / w.sigma ** 2, dtype=torch.float64,
                                         device=dev))
-    m_true = synth.sky_map(w, device=dev)
-    d = fx.pointing_apply(P, m_true)                       # signal (HIP path; bench only)
     # white noise streams: the 1/f model enters through the band-Toeplitz
-    # weights, and no operator's cost depends on the data values (this also
-    # keeps library FFTs, which the counter profiler cannot follow, out of it)
-    d += synth.noise(w, device=dev, shape_1f=False).to(d.dtype)
+    # weights, and no operator's cost depends on the data values
+    d = (d + synth.noise(w, device=dev, shape_1f=False).to(d.dtype)).to(tdt)
     torch.cuda.synchronize()
-    log(f"{w.name}: inputs generated in {time.time() - t0:.1f} s")
+    log(f"{w.name} ({prec} path): inputs generated in {time.time() - t0:.1f} s")
     return P, N, d
 
 
 def kernel_bytes(w):
-    """Algorithmic HBM bytes per launch of each phase of one PCG iteration (what
-    the operator must move as the method defines it, whatever the kernel reads)."""
+    """Algorithmic HBM bytes per launch of each phase of one PCG iteration.
+
+    P: the pointing stream once and the map read once (what the operator
+    needs; its TOD output and the per-sample label it hands to P^T are the
+    decomposition's intermediates, not counted).  N^-1: its TOD in and out.
+    P^T: what it reads (the angle plane psi, the 2-byte pixel label, the
+    weighted TOD) and the FP64 map written once."""
     e = 8 if w.dtype == "f64" else 4
     S = w.n_det * w.n_samp
-    # pointing stream per phase: theta, phi, psi planes, or (quaternion
-    # pointing) one boresight attitude per time sample and one per detector
-    pt = S * 3 * e if w.pointing != "quat" else 32 * (w.n_samp + w.n_det)
+    if w.pointing == "quat":
+        pt_p, pt_t = 32 * (w.n_samp + w.n_det), 32 * (w.n_samp + w.n_det) + S * 2
+    else:
+        pt_p, pt_t = S * 3 * e, S * (e + 2)
     return {
-        # P: pointing in, TOD out, the map read once
-        "apply": pt + S * e + 3 * w.npix * e,
-        # N^-1: TOD in, TOD out
+        "apply": pt_p + 3 * w.npix * e,
         "noise": S * 2 * e,
-        # P^T: pointing and TOD in, the FP64 map written once
-        "transpose": pt + S * e + 3 * w.npix * 8,
+        "transpose": pt_t + S * e + 3 * w.npix * 8,
     }
 
 
 def operator_bytes(w):
-    """Algorithmic bytes of a whole PCG iteration: the pointing stream once plus
-    the map-domain vectors (p, q, x, r, z, preconditioner: ~52 FP64 per pixel).
-    The TOD itself never has to reach HBM when P, N^-1 and P^T are fused."""
+    """B_alg of a whole PCG iteration: the pointing stream once plus the
+    map-domain vectors (p, q, x, r, z and the preconditioner: ~52 FP64 values
+    per pixel).  The TOD never has to reach HBM when P, N^-1 and P^T are fused."""
     e = 8 if w.dtype == "f64" else 4
     pt = w.n_det * w.n_samp * 3 * e if w.pointing != "quat" else 32 * (w.n_samp + w.n_det)
     return pt + 52 * 8 * w.npix
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nside512_256x2p20_band4096.txt")
+def traffic_file(w):
+    tag = w.name.replace("^", "p").replace("_hwp", "").replace("_f32", "").replace("_f64", "")
+    return os.path.join(ROOT, "profiles", f"traffic_{tag}.txt")
+
+
 # kernels making up each phase, by rocprofv3 kernel name ({T}: double or float)
 PHASE_KERNELS = {
     "apply": ["fx::k_apply<{T}, {T}, true, false>"],
-    "noise": ["fx::k_os_r32x<{T}>", "fx::k_os_r32<{T}>", "fx::k_overlap_save<{T}, "],
-    "transpose": ["fx::k_sp_accum<{T}, 0, false>", "fx::k_sp_reduce"],
+    "noise": ["fx::k_os_r32x<{T}", "fx::k_os_r32<{T}", "fx::k_overlap_save<{T}, "],
+    "transpose": ["fx::k_sp_accum<{T}, 0, false", "fx::k_sp_reduce"],
 }
 
 
@@ -129,63 +151,82 @@ def source_fingerprint():
     return h.hexdigest()
 
 
-def measured_traffic(phase, dtype):
-    """HBM bytes per launch of a phase from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE record, each counter scaled by what it reads for a plain 1 GiB
-    device copy; None when the record is missing or the kernels changed since."""
+def measured_traffic(w, phase):
+    """HBM bytes per launch of a phase from the committed rocprofv3 record:
+    FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for the library's
+    non-temporal device copy of known size (the cache policy of the kernels'
+    streams).  None when the record is missing, the kernels changed since it
+    was taken, or the read counter falls below the bytes the phase must read
+    (then it is not measuring them)."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file(w)) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
     if rec.get("source_sha256") != source_fingerprint():
         return None
-    cal = rec["calibration_kib"]
-    cb = rec["calibration_copy_bytes"]
+    cal = rec["calibration"]["nontemporal"]
+    cb = rec["calibration"]["bytes"]
     sf, sw = cb / (cal["FETCH_SIZE"] * 1024.0), cb / (cal["WRITE_SIZE"] * 1024.0)
-    T = "double" if dtype == "f64" else "float"
-    total, found = 0.0, 0
+    T = "double" if w.dtype == "f64" else "float"
+    rd, wr, found = 0.0, 0.0, 0
     for pat in PHASE_KERNELS[phase]:
         pat = pat.format(T=T)
         for name, v in rec["kernels"].items():
             if name.startswith(pat):
-                total += v["FETCH_SIZE"] * 1024.0 * sf + v["WRITE_SIZE"] * 1024.0 * sw
+                rd += v["FETCH_SIZE"] * 1024.0 * sf
+                wr += v["WRITE_SIZE"] * 1024.0 * sw
                 found += 1
-    return total if found else None
+    if not found:
+        return None
+    e = 8 if w.dtype == "f64" else 4
+    S = w.n_det * w.n_samp
+    must_read = {"apply": S * 3 * e, "noise": S * e, "transpose": S * (2 * e + 2)}[phase]
+    if rd < 0.98 * must_read:
+        return None            # the read counter does not see all of the stream's requests
+    return {"read": rd, "write": wr, "total": rd + wr, "must_read": must_read}
 
 
-def run_pcg(fx, P, N, d, steps, warmup):
+def run_pcg(fx, P, N, d, steps, warmup, iters):
+    """warmup iterations, `steps` timed with no phase events, `steps` more with
+    the phase events on, then the rest up to `iters`; returns the timed ms per
+    iteration, the phase sums, the final map and the session's info."""
     import torch
 
-    sess = fx.PCGSession(P, N, d, max_iter=steps + warmup, rtol=0.0, no_early_exit=True)
+    total = max(iters, warmup + 2 * steps)
+    sess = fx.PCGSession(P, N, d, max_iter=total, rtol=0.0, no_early_exit=True)
     sess.iterate(warmup)
     torch.cuda.synchronize()
-    sess.set_timing(True)
-    sess.read_timing()
     # the library launches on torch's current stream, where these events go too
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
     e0.record()
     sess.iterate(steps)
     e1.record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / steps
+    sess.set_timing(True)
+    sess.read_timing()
+    sess.iterate(steps)
     phases = sess.read_timing()
+    sess.set_timing(False)
+    rest = total - warmup - 2 * steps
+    if rest > 0:
+        sess.iterate(rest)
     x, valid, info, st = sess.finish()
     sess.close()
-    ms = e0.elapsed_time(e1) / steps
-    return ms, wall, info, phases
+    return ms, phases, x, valid, info
 
 
-def measure(w, dev, steps, warmup):
+def measure(w, dev, steps, warmup, prec, keep_map=False):
     import torch
 
     from paper_2603_19600_amd import furax as fx
 
-    P, N, d = make_inputs(w, dev)
-    ms, wall, info, phases = run_pcg(fx, P, N, d, steps, warmup)
+    P, N, d = make_inputs(w, dev, prec)
+    w = w.with_(dtype=prec)
+    ms, phases, x, valid, info = run_pcg(fx, P, N, d, steps, warmup, w.iters)
     S = w.n_det * w.n_samp
-    res = {"ms_per_step": ms, "value": S / (ms * 1e-3), "wall_s": wall, "iters": info.iters,
+    res = {"workload": w.name.replace("_f32", "_" + prec), "ms_per_step": ms, "value": S / (ms * 1e-3), "iters": info.iters,
            "rel_resid": info.rel_resid, "n_valid": info.n_valid}
     kb = kernel_bytes(w)
     n = max(phases["iters"], 1)
@@ -196,16 +237,122 @@ def measure(w, dev, steps, warmup):
         if k in kb and t > 0:
             row["alg_bytes"] = kb[k]
             row["GB_s"] = kb[k] / (t * 1e-3) / 1e9
+            row["frac"] = row["GB_s"] / HBM_PEAK_GBS
         res["kernels"][k] = row
     ob = operator_bytes(w)
     res["operator"] = {"alg_bytes_per_iter": ob, "B_alg_per_sample": ob / S,
-                       "GB_s": ob / (ms * 1e-3) / 1e9, "frac_hbm_peak": ob / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-    log(f"{w.name}: {ms:.3f} ms/iter, {res['value']:.4g} samples/s, rel resid {info.rel_resid:.3e}")
+                       "GB_s": ob / (ms * 1e-3) / 1e9,
+                       "frac_hbm_peak": ob / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "target_frac": TARGET_FRAC}
+    log(f"{w.name}: {ms:.3f} ms/iter, {res['value']:.4g} samples/s; after {info.iters} "
+        f"iterations rel resid {info.rel_resid:.3e}")
     log("phases: " + ", ".join(f"{k} {v['ms']:.3f} ms" + (f" {v['GB_s']:.0f} GB/s" if "GB_s" in v else "")
                                for k, v in res["kernels"].items()))
     del P, N, d
+    if not keep_map:
+        del x, valid
+        x = None
+    torch.cuda.empty_cache()
+    return res, x
+
+
+def measure_copy(dev, gib=4):
+    """Device copy of `gib` GiB by the library's stream copy, plain and
+    non-temporal: read + write GB/s, the achievable-bandwidth ceiling."""
+    import torch
+
+    from paper_2603_19600_amd import furax as fx
+
+    nb = gib << 30
+    src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    out = {"bytes_copied": nb}
+    for name, nt in (("plain", False), ("nontemporal", True)):
+        fx.stream_copy(src, dst, nt)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record()
+        for _ in range(reps):
+            fx.stream_copy(src, dst, nt)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": ms, "GB_s": 2 * nb / (ms * 1e-3) / 1e9,
+                     "frac": 2 * nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    assert torch.equal(src[:1024], dst[:1024])
+    del src, dst
+    torch.cuda.empty_cache()
+    log(f"device copy: plain {out['plain']['GB_s']:.0f} GB/s, non-temporal "
+        f"{out['nontemporal']['GB_s']:.0f} GB/s (read + write)")
+    return out
+
+
+def measure_chi2(w, dev, steps=5):
+    """The differentiation workload: chi2 forward (furax_chi2) plus the gradient
+    with respect to the map, the gains and the angle offsets (furax_chi2_grad,
+    pointing recomputed), through the torch.autograd.Function; samples/s of one
+    forward + backward and each pass's algorithmic GB/s (pointing and data
+    read once per pass, the map read, the FP64 map gradient written)."""
+    import torch
+
+    from paper_2603_19600_amd import furax as fx
+    from paper_2603_19600_amd import synth
+
+    pt = synth.pointing(w, device=dev, det_chunk=8)
+    P = fx.Pointing(w.nside, pt.theta, pt.phi, pt.psi)
+    iv = torch.full((w.n_det,), 1.0 / w.sigma ** 2, dtype=torch.float64, device=dev)
+    N = fx.Noise("diag", w.n_det, w.n_samp, inv_var=iv)
+    m_true = synth.sky_map(w, device=dev)
+    d = (fx.pointing_apply(P, m_true).double() + synth.noise(w, device=dev)).float()
+    m = (m_true + 0.1).requires_grad_(True)
+    g = torch.ones(w.n_det, dtype=torch.float64, device=dev, requires_grad=True)
+    dp = torch.zeros(w.n_det, dtype=torch.float64, device=dev, requires_grad=True)
+
+    def step():
+        m.grad = g.grad = dp.grad = None
+        fx.chi2_loss(P, N, d, m, g, dp).backward()
+
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    # the two passes alone
+    tf = _time(lambda: fx.chi2(P, N, m.detach(), d), steps)
+    tb = _time(lambda: fx.chi2_grad(P, N, m.detach(), d), steps)
+    S = w.n_det * w.n_samp
+    fwd_bytes = S * (3 * 4 + 4) + 3 * w.npix * 8
+    bwd_bytes = S * (3 * 4 + 4) + 3 * w.npix * 8 * 2
+    res = {"workload": w.name, "ms_fwd_bwd": ms, "samples_per_s": S / (ms * 1e-3),
+           "ms_forward": tf, "ms_gradient": tb,
+           "forward": {"alg_bytes": fwd_bytes, "GB_s": fwd_bytes / (tf * 1e-3) / 1e9,
+                       "frac": fwd_bytes / (tf * 1e-3) / 1e9 / HBM_PEAK_GBS},
+           "gradient": {"alg_bytes": bwd_bytes, "GB_s": bwd_bytes / (tb * 1e-3) / 1e9,
+                        "frac": bwd_bytes / (tb * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+    log(f"chi2 {w.name}: forward + gradient {ms:.3f} ms ({res['samples_per_s']:.4g} samples/s); "
+        f"forward {tf:.3f} ms, gradient {tb:.3f} ms")
+    del P, N, d, m, pt
     torch.cuda.empty_cache()
     return res
+
+
+def _time(fn, reps):
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
 
 
 def measure_gapfill(w, dev, frac=0.01, rtol=1e-10):
@@ -234,45 +381,120 @@ def measure_gapfill(w, dev, frac=0.01, rtol=1e-10):
     S = w.n_det * w.n_samp
     log(f"gap fill: {iters} CG iterations in {dt * 1e3:.1f} ms ({dt * 1e3 / max(iters, 1):.3f} ms "
         f"per iteration), worst |r|/|b| {rel:.2e}")
-    return {"workload": w.name.replace(f"band{w.bandwidth}", f"gapfill{w.bandwidth}"),
-            "missing_fraction": float(gaps.double().mean()), "cg_iters": iters,
-            "rel_resid": rel, "ms_total": dt * 1e3, "ms_per_cg_iter": dt * 1e3 / max(iters, 1),
-            "samples_per_s_per_cg_iter": S / (dt / max(iters, 1))}
+    res = {"workload": w.name.replace(f"band{w.bandwidth}", f"gapfill{w.bandwidth}"),
+           "missing_fraction": float(gaps.double().mean()), "cg_iters": iters,
+           "rel_resid": rel, "ms_total": dt * 1e3, "ms_per_cg_iter": dt * 1e3 / max(iters, 1),
+           "samples_per_s_per_cg_iter": S / (dt / max(iters, 1))}
+    del C, d, nr, gaps, out
+    torch.cuda.empty_cache()
+    return res
 
 
-def cpu_baseline(w, n_det):
-    """The FP64 NumPy oracle's P^T N^-1 P on a detector prefix of the same workload,
-    on one host core (BLAS/OpenMP pools limited to one thread)."""
-    import numpy as np
-    from threadpoolctl import threadpool_limits
-
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle's P^T N^-1 P on a detector prefix.
+# ---------------------------------------------------------------------------
+def _oracle_inputs(cfg, k0, k1):
+    """The oracle's problem for detectors [k0, k1) of workload cfg, and the map."""
     from oracle import mapmaker as omm
     from paper_2603_19600_amd import synth
 
-    pt = synth.pointing(w, n_det=n_det)
-    lags = synth.toeplitz_lags(w) if w.noise == "band" else None
+    w = synth.WORKLOADS[cfg]
+    pt = synth.pointing(w, det0=k0, n_det=k1 - k0)
     hwp = (w.hwp_num, w.hwp_den, 0.0) if w.hwp else None
     prob = omm.Problem(w.nside, pt.theta.double().numpy(), pt.phi.double().numpy(),
-                       pt.psi.double().numpy(), w.noise,
-                       inv_var=None if lags is not None else np.ones(n_det), lags=lags, hwp=hwp)
-    x = synth.sky_map(w).numpy()
+                       pt.psi.double().numpy(), "band", lags=synth.toeplitz_lags(w), hwp=hwp)
+    return prob, synth.sky_map(w).numpy()
+
+
+def _oracle_apply(prob, x):
+    """One application of A x = sum_k P_k^T N_k^-1 P_k x by the oracle, the
+    pointing expanded first (as at every application); returns the touched
+    pixels and their three Stokes sums."""
+    import numpy as np
+
+    from oracle import mapmaker as omm
+
+    pix, c, s = prob.geometry()
+    q = omm.normal_apply(prob, pix, c, s, x)
+    nz = np.flatnonzero(np.any(q != 0.0, axis=0))
+    return nz, q[:, nz]
+
+
+def _oracle_worker(cfg, k0, k1, ready, go, out):
+    from threadpoolctl import threadpool_limits
+
     with threadpool_limits(limits=1):
+        prob, x = _oracle_inputs(cfg, k0, k1)
+        ready.put(k0)
+        go.wait()
+        out.put(_oracle_apply(prob, x))
+
+
+def cpu_baseline(cfg, n_det, workers):
+    """The FP64 NumPy oracle's P^T N^-1 P on an n_det-detector prefix of the
+    workload: on one host core, and over `workers` processes each applying it
+    to its own shard of the detectors (the paper's decomposition
+    sum_k P_k^T N_k^-1 P_k), summed here.  Inputs are generated before the
+    timed regions."""
+    import multiprocessing as mp
+
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from paper_2603_19600_amd import synth
+
+    w = synth.WORKLOADS[cfg]
+    S = n_det * w.n_samp
+    with threadpool_limits(limits=1):
+        prob, x = _oracle_inputs(cfg, 0, n_det)
         t0 = time.perf_counter()
         c0 = time.process_time()
-        pix, c, s = prob.geometry()           # pointing is expanded at every application
-        omm.normal_apply(prob, pix, c, s, x)
-        cpu = time.process_time() - c0
-        dt = time.perf_counter() - t0
-    S = n_det * w.n_samp
-    return {"value": S / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"one application of P^T N^-1 P (FP64 NumPy oracle, pointing expanded, "
-                      f"FFT band-Toeplitz) on a {n_det}-detector x {w.n_samp}-sample prefix of "
-                      f"the workload, {dt:.1f} s wall, {cpu:.1f} s CPU",
-            "seconds": dt}
+        nz1, q1 = _oracle_apply(prob, x)
+        one = time.perf_counter() - t0
+        cpu1 = time.process_time() - c0
+    del prob
+    bounds = np.linspace(0, n_det, workers + 1).round().astype(int)
+    shards = [(int(a), int(b)) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
+    ctx = mp.get_context("spawn")
+    ready, out, go = ctx.Queue(), ctx.Queue(), ctx.Event()
+    procs = [ctx.Process(target=_oracle_worker, args=(cfg, a, b, ready, go, out), daemon=True)
+             for a, b in shards]
+    for p in procs:
+        p.start()
+    for _ in procs:
+        ready.get(timeout=600)
+    t0 = time.perf_counter()
+    go.set()
+    q = np.zeros((3, w.npix))
+    for _ in procs:
+        nz, vals = out.get(timeout=600)
+        q[:, nz] += vals
+    many = time.perf_counter() - t0
+    for p in procs:
+        p.join(timeout=60)
+    ref = np.zeros_like(q)
+    ref[:, nz1] = q1
+    agree = float(np.abs(q - ref).max() / max(np.abs(ref).max(), 1e-300))
+    log(f"cpu baseline: {n_det} detectors, 1 core {S / one:.4g} samples/s ({one:.1f} s); "
+        f"{len(shards)} processes {S / many:.4g} samples/s ({many:.1f} s); shards vs whole "
+        f"{agree:.1e}")
+    return {"value": S / many, "unit": "samples/s", "cores": len(shards), "kind": "oracle",
+            "sample": f"one application of P^T N^-1 P by the FP64 NumPy oracle (pointing "
+                      f"expanded, single-FFT band-Toeplitz, bincount binning) on the first "
+                      f"{n_det} detectors x {w.n_samp} samples of {w.name}, split by detector "
+                      f"over {len(shards)} worker processes (one thread each) and summed; "
+                      f"{many:.1f} s wall",
+            "seconds": many,
+            "one_core": {"value": S / one, "cores": 1, "seconds": one, "cpu_seconds": cpu1},
+            "shards_vs_whole_max_rel": agree}
 
 
 def host_info():
     info = {"nproc": os.cpu_count(), "machine": platform.machine()}
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
         for ln in out.splitlines():
@@ -327,32 +549,56 @@ def summarize_trace(db_dir, out, command, title):
         fh.write("\n".join(lines) + "\n")
 
 
-def traffic_record(fetch_dir, write_dir, out, commands):
-    """The FETCH_SIZE / WRITE_SIZE record measured_traffic() reads: KiB per
-    dispatch of every library kernel, the 1 GiB calibration copy's counts, and
+def traffic_record(dirs, out, commands):
+    """The traffic record measured_traffic() reads, from rocprofv3 --pmc runs of
+    this script (one counter group per run: FETCH_SIZE; WRITE_SIZE; optionally
+    the request-size counters TCC_EA0_RDREQ_32B/64B/128B): the mean per
+    dispatch of every counter of every library kernel, the same counters of
+    the two 1 GiB calibration copies (the first dispatch of each kind), and
     the fingerprint of the sources they were taken on."""
     import collections
     import sqlite3
 
     vals = collections.defaultdict(lambda: collections.defaultdict(list))
-    calib = {}
-    for d in (fetch_dir, write_dir):
+    calib = {"plain": {}, "nontemporal": {}}
+    for d in dirs:
         for db in _rocpd_dbs(d):
             con = sqlite3.connect(db)
-            for name, cname, v, grid in con.execute(
-                    "select kernel_name, counter_name, value, grid_size from counters_collection "
+            first = {}
+            for name, cname, v, disp in con.execute(
+                    "select kernel_name, counter_name, value, dispatch_id from counters_collection "
                     "order by dispatch_id"):
-                if "copy" in name and grid == (1 << 26) and cname not in calib:
-                    calib[cname] = v
-                if "fx::" in name:
+                if "k_stream_copy" in name:
+                    kind = "nontemporal" if "<true>" in name else "plain"
+                    first.setdefault(kind, disp)
+                    if disp == first[kind]:
+                        calib[kind][cname] = v
+                elif "fx::" in name:
                     vals[_short_kernel(name)][cname].append(v)
-    rec = {"calibration_copy_bytes": 1 << 30, "calibration_kib": calib, "commands": commands,
+    rec = {"calibration": {"bytes": 1 << 30, **calib}, "commands": commands,
            "source_sha256": source_fingerprint(), "kernels": {}}
     for k, d in vals.items():
         rec["kernels"][k] = {c: sum(v) / len(v) for c, v in d.items()}
-        rec["kernels"][k]["dispatches"] = len(d.get("FETCH_SIZE", []))
+        rec["kernels"][k]["dispatches"] = max(len(v) for v in d.values())
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1, sort_keys=True)
+
+
+def calibration_copies(dev):
+    """One plain and one non-temporal 1 GiB copy (2^30 bytes read, 2^30
+    written) by the library's stream copy: the dispatches of known traffic
+    that the profiler's counters are scaled by."""
+    import torch
+
+    from paper_2603_19600_amd import furax as fx
+
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    fx.stream_copy(src, dst, False)
+    fx.stream_copy(src, dst, True)
+    torch.cuda.synchronize()
+    del src, dst
+    torch.cuda.empty_cache()
 
 
 def counter_summary(dirs, out, commands, title):
@@ -400,25 +646,31 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2, help="workload number (2, 3 or 5)")
-    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 variant")
-    ap.add_argument("--no-fp64", action="store_true",
-                    help="skip the FP64 variant of an FP32 workload")
+    ap.add_argument("--config", type=int, default=5,
+                    help="workload number: 5 (default, nside 1024) or 3 (nside 512); the FP32 "
+                         "path is the headline and the FP64 path runs beside it")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 path")
     ap.add_argument("--no-quat", action="store_true",
-                    help="skip the boresight-quaternion pointing variants")
+                    help="skip the boresight-quaternion pointing variant")
     ap.add_argument("--no-deproj", action="store_true",
-                    help="skip the template-deprojection variants")
+                    help="skip the template-deprojection variant")
+    ap.add_argument("--no-chi2", action="store_true", help="skip the chi-square gradient")
     ap.add_argument("--no-gapfill", action="store_true",
                     help="skip the gap-filling measurement")
+    ap.add_argument("--no-copy", action="store_true", help="skip the device-copy ceiling")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-dets", type=int, default=64)
+    ap.add_argument("--cpu-dets", type=int, default=16)
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="worker processes of the CPU baseline (capped by the host's CPUs)")
     ap.add_argument("--summarize-trace", metavar="DIR",
                     help="write the kernel-trace summary of a rocprofv3 output directory to --out")
-    ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="write the FETCH_SIZE / WRITE_SIZE record of two rocprofv3 --pmc runs "
-                         "to --out")
+    ap.add_argument("--traffic-record", nargs="+", metavar="DIR",
+                    help="write the traffic record of rocprofv3 --pmc runs (FETCH_SIZE, "
+                         "WRITE_SIZE, ...) to --out")
     ap.add_argument("--counter-summary", nargs="+", metavar="DIR",
                     help="write the per-kernel counter table of rocprofv3 --pmc outputs to --out")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="only run the 1 GiB device copies the traffic counters are scaled by")
     ap.add_argument("--out")
     ap.add_argument("--command", action="append", default=[],
                     help="the profiling command(s) to record in the summary")
@@ -431,7 +683,7 @@ def main():
         counter_summary(args.counter_summary, args.out, args.command, args.title)
         return
     if args.traffic_record:
-        traffic_record(args.traffic_record[0], args.traffic_record[1], args.out, args.command)
+        traffic_record(args.traffic_record, args.out, args.command)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -445,57 +697,68 @@ def main():
     from paper_2603_19600_amd import synth
 
     dev = torch.device("cuda:0")
-    # a plain 1 GiB device copy: the reference that scales rocprofv3's
-    # FETCH_SIZE / WRITE_SIZE counters to bytes (it reads and writes 1 GiB)
-    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    del src, dst
+    calibration_copies(dev)
+    if args.calibrate:
+        return
     w = synth.WORKLOADS[args.config]
-    primary = measure(w, dev, args.steps, args.warmup)
-    fp32 = None
-    if not args.no_fp32 and w.dtype == "f64":
-        w32 = synth.WORKLOADS[3] if args.config == 2 else w.with_(dtype="f32")
-        fp32 = measure(w32, dev, args.steps, args.warmup)
+    if w.dtype != "f32" or w.noise != "band":
+        raise SystemExit("--config must name an FP32 band-noise workload (3 or 5)")
+    primary, x32 = measure(w, dev, args.steps, args.warmup, "f32", keep_map=not args.no_fp64)
     fp64 = None
-    if not args.no_fp64 and w.dtype == "f32" and args.config != 3:
-        w64 = w.with_(dtype="f64", name=w.name.replace("_f32", "_f64"))
-        fp64 = measure(w64, dev, args.steps, args.warmup)
+    map_err = None
+    if not args.no_fp64:
+        fp64, x64 = measure(w, dev, args.steps, args.warmup, "f64", keep_map=True)
+        # both paths ran the workload's iterations from the same data; the FP64
+        # path is pinned to the oracle by the parity tests
+        num = float(torch.linalg.vector_norm(x32 - x64))
+        den = float(torch.linalg.vector_norm(x64))
+        per = [float(torch.linalg.vector_norm(x32[i] - x64[i]) / torch.linalg.vector_norm(x64[i]))
+               for i in range(3)]
+        map_err = {"rel": num / den, "I": per[0], "Q": per[1], "U": per[2],
+                   "iterations": primary["iters"],
+                   "rel_resid_f32": primary["rel_resid"], "rel_resid_f64": fp64["rel_resid"]}
+        log(f"solved maps after {primary['iters']} iterations: FP32 vs FP64 {num / den:.3e} "
+            f"(I {per[0]:.2e}, Q {per[1]:.2e}, U {per[2]:.2e})")
+        del x32, x64
+        torch.cuda.empty_cache()
 
-    quat = {}
+    variants = {}
     if not args.no_quat:
-        for wq in ([w] + ([synth.WORKLOADS[3]] if fp32 is not None and args.config == 2 else [])):
-            r = measure(wq.with_(pointing="quat"), dev, args.steps, args.warmup)
-            quat[wq.dtype] = {"workload": wq.name + "_quat", "value": r["value"],
-                              "ms_per_step": r["ms_per_step"], "kernels": r["kernels"],
-                              "operator": r["operator"]}
-
-    deproj = {}
+        r, _ = measure(w.with_(pointing="quat", name=w.name + "_quat"), dev, args.steps,
+                       args.warmup, "f32")
+        variants["quat"] = {k: r[k] for k in ("workload", "value", "ms_per_step", "kernels",
+                                              "operator")}
     if not args.no_deproj:
-        for wd in ([w] + ([synth.WORKLOADS[3]] if fp32 is not None and args.config == 2 else [])):
-            r = measure(wd.with_(noise="deproj"), dev, args.steps, args.warmup)
-            deproj[wd.dtype] = {"workload": wd.name.replace(f"band{wd.bandwidth}",
-                                                            f"deproj{wd.tmpl_seg_len}o{wd.tmpl_order}"),
-                                "value": r["value"], "ms_per_step": r["ms_per_step"],
-                                "kernels": r["kernels"], "operator": r["operator"]}
+        wd = w.with_(noise="deproj", name=w.name.replace(
+            f"band{w.bandwidth}", f"deproj{w.tmpl_seg_len}o{w.tmpl_order}"))
+        r, _ = measure(wd, dev, args.steps, args.warmup, "f32")
+        variants["deproj"] = {k: r[k] for k in ("workload", "value", "ms_per_step", "kernels",
+                                                "operator")}
+    chi2 = None if args.no_chi2 else measure_chi2(synth.WORKLOADS[4], dev)
+    gapfill = None if args.no_gapfill else measure_gapfill(synth.WORKLOADS[2], dev)
+    copy = None if args.no_copy else measure_copy(dev)
 
-    gapfill = None
-    if not args.no_gapfill and w.dtype == "f64" and w.bandwidth <= 4096:
-        gapfill = measure_gapfill(w, dev)
-
-    # the dominant operator kernel of the iteration
+    # the dominant kernel of the headline iteration
     name, k = max(((n, v) for n, v in primary["kernels"].items() if "alg_bytes" in v),
                   key=lambda kv: kv[1]["ms"])
-    traffic = measured_traffic(name, w.dtype)
+    traffic = measured_traffic(w, name)
     roofline = {"bound": "hbm", "kernel": name, "achieved": k["GB_s"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": k["GB_s"] / HBM_PEAK_GBS, "traffic": traffic,
-                "alg_bytes_per_launch": k["alg_bytes"], "ms_per_launch": k["ms"]}
+                "unit": "GB/s", "frac": k["GB_s"] / HBM_PEAK_GBS,
+                "traffic": None if traffic is None else traffic["total"],
+                "traffic_read_write": traffic,
+                "alg_bytes_per_launch": k["alg_bytes"], "ms_per_launch": k["ms"],
+                "iteration_frac": primary["operator"]["frac_hbm_peak"],
+                "iteration_target_frac": TARGET_FRAC}
+    if copy is not None:
+        roofline["copy_ceiling_GB_s"] = copy["nontemporal"]["GB_s"]
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, args.cpu_dets)
-        log(f"cpu baseline: {cpu['value']:.4g} samples/s ({cpu['seconds']:.1f} s)")
+        try:
+            ncpu = len(os.sched_getaffinity(0))
+        except Exception:
+            ncpu = os.cpu_count() or 1
+        cpu = cpu_baseline(args.config, args.cpu_dets, max(1, min(args.cpu_workers, ncpu)))
 
     S = w.n_det * w.n_samp
     line = {
@@ -509,28 +772,28 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": w.dtype,
-        "data": "synthetic (seeded spin+precession scan, random IQU sky, white noise data, 1/f band-Toeplitz weights)",
+        "dtype": "f32",
+        "data": "synthetic (seeded spin+precession scan, random IQU sky, white noise data, "
+                "1/f band-Toeplitz weights)",
         "config": {"workload": w.name, "nside": w.nside, "n_det": w.n_det, "n_samp": w.n_samp,
                    "samples": S, "noise": w.noise, "bandwidth": w.bandwidth, "hwp": w.hwp,
-                   "pcg_precision": w.dtype, "parallelism": "single GPU"},
+                   "pcg_iterations": w.iters, "pcg_precision": "f32 operator, f64 vectors/dots",
+                   "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": primary["kernels"],
         "operator": primary["operator"],
-        "fp32": None if fp32 is None else {
-            "workload": synth.WORKLOADS[3].name if args.config == 2 else w.name + "_f32",
-            "value": fp32["value"], "ms_per_step": fp32["ms_per_step"],
-            "kernels": fp32["kernels"], "operator": fp32["operator"],
-            "speedup_vs_fp64": fp32["value"] / primary["value"]},
+        "rel_resid": primary["rel_resid"],
         "fp64": None if fp64 is None else {
-            "workload": w64.name,
-            "value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
-            "kernels": fp64["kernels"], "operator": fp64["operator"],
+            "workload": fp64["workload"], "value": fp64["value"],
+            "ms_per_step": fp64["ms_per_step"], "kernels": fp64["kernels"],
+            "operator": fp64["operator"], "rel_resid": fp64["rel_resid"],
             "fp32_speedup": primary["value"] / fp64["value"]},
-        "quat": quat or None,
-        "deproj": deproj or None,
+        "map_error_fp32_vs_fp64": map_err,
+        "variants": variants or None,
+        "chi2_grad": chi2,
         "gapfill": gapfill,
+        "copy": copy,
         "host": host_info(),
     }
     print(json.dumps(line), flush=True)

@@ -299,6 +299,22 @@ furax_status furax_pointing_vjp(const furax_pointing *P, int32_t map_dt, const v
                                 const void *tod_cot, double *grad_map, double *grad_gain,
                                 double *grad_dpsi, hipStream_t stream);
 
+/* The gradient of chi2 = r^T N^-1 r, r = d - P m (diagonal N), with respect
+ * to the map, the detector gains and the polarisation-angle offsets, in one
+ * pass over the pointing (recomputed, not stored):
+ *   grad_map  [3][npix] FP64 (+)= -2 P^T (N^-1 r)                (accumulated),
+ *   grad_gain [n_det] FP64     =  -2 sum_i u[k,i] (P_1 m)[k,i],    u = N^-1 r,
+ *   grad_dpsi [n_det] FP64     =  -2 sum_i u[k,i] g_k (-2 Q sin 2psi_eff + 2 U cos 2psi_eff),
+ *   chi2_out  (device FP64 scalar, or NULL) = chi2 at the same point.
+ * Any output may be NULL to skip it.  tod: [n_det][n_samp] of the pointing's
+ * dtype; the map as for furax_chi2.  The per-detector sums and chi2 are
+ * deterministic (fixed-order FP64 reductions); the map gradient is binned in
+ * LDS per sample tile and flushed with FP64 atomics, so its last bits may
+ * vary from run to run.  Allocates its partial sums stream-ordered. */
+furax_status furax_chi2_grad(const furax_pointing *P, const furax_noise *N, int32_t map_dt,
+                             const void *map, const void *tod, double *chi2_out, double *grad_map,
+                             double *grad_gain, double *grad_dpsi, hipStream_t stream);
+
 /* Template fit of a noise model of kind 2 (TemplateOperator, Eq. (1)/(3)):
  * the amplitudes t = (T^T W T)^-1 T^T W y of every detector's and segment's
  * Legendre baselines, e.g. of the residual d - P m after a solve.
@@ -334,6 +350,16 @@ furax_status furax_gap_fill(const furax_noise *C, int32_t dt, const uint8_t *gap
                             const void *tod, const void *noise_real, void *out,
                             const furax_gapfill_opts *opt, furax_gapfill_info *info,
                             hipStream_t stream);
+
+/* Measurement utility, not a step of the method: dst[0 .. bytes) =
+ * src[0 .. bytes) on the device (bytes a multiple of 16, both buffers 16-byte
+ * aligned and not overlapping).  nontemporal = 1 moves the data with
+ * non-temporal loads and stores, the cache policy of the kernels' pointing and
+ * TOD streams; 0 with plain ones.  It gives the achievable read + write HBM
+ * bandwidth beside the kernels, and a kernel of known traffic that calibrates
+ * the profiler's memory counters. */
+furax_status furax_stream_copy(const void *src, void *dst, int64_t bytes, int32_t nontemporal,
+                               hipStream_t stream);
 
 /* Thread-local description of the last non-OK status (never NULL). */
 const char *furax_last_error(void);

@@ -130,6 +130,10 @@ furax_status chi2_impl(const furax_pointing *P, const furax_noise *N, int32_t ma
                        const void *map, const T *tod, double *chi2_out, T *resid_w,
                        hipStream_t s);
 template <typename T>
+furax_status chi2_grad_impl(const furax_pointing *P, const furax_noise *N, int32_t map_dt,
+                            const void *map, const T *tod, double *chi2_out, double *grad_map,
+                            double *grad_gain, double *grad_dpsi, hipStream_t s);
+template <typename T>
 furax_status vjp_impl(const furax_pointing *P, int32_t map_dt, const void *map, const T *cot,
                       double *grad_map, double *grad_gain, double *grad_dpsi, hipStream_t s);
 void release_twiddles();
@@ -142,6 +146,23 @@ static furax_status check_pcg_opts(const furax_pcg_opts *o, const furax_pointing
     return set_error(FURAX_EINVAL, "precision must equal the pointing dtype");
   if (!(o->rcond_min >= 0.0) && !o->valid_in) return set_error(FURAX_EINVAL, "rcond_min must be >= 0");
   return FURAX_OK;
+}
+
+// Device copy used as the bandwidth ceiling beside the kernels and as the
+// reference of known size for the traffic counters (not a step of the method).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__global__ void __launch_bounds__(kBlock) k_stream_copy(const u32x4 *__restrict__ src,
+                                                        u32x4 *__restrict__ dst, int64_t n16) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n16; i += stride) {
+    if constexpr (NT) {
+      __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+    } else {
+      dst[i] = src[i];
+    }
+  }
 }
 
 }  // namespace fx
@@ -362,6 +383,23 @@ furax_status furax_chi2(const furax_pointing *P, const furax_noise *N, int32_t m
                            stream);
 }
 
+furax_status furax_chi2_grad(const furax_pointing *P, const furax_noise *N, int32_t map_dt,
+                             const void *map, const void *tod, double *chi2_out, double *grad_map,
+                             double *grad_gain, double *grad_dpsi, hipStream_t stream) {
+  FX_TRY(check_pointing(P));
+  FX_TRY(check_noise(N, P->n_det, P->n_samp, P->dtype));
+  if (N->kind != 0) return set_error(FURAX_EUNSUPPORTED, "chi2 supports diagonal noise only");
+  if (!dtype_ok(map_dt)) return set_error(FURAX_EINVAL, "bad map dtype");
+  if (P->dtype == FURAX_F64 && map_dt != FURAX_F64)
+    return set_error(FURAX_EINVAL, "FP64 pointing needs an FP64 map");
+  if (!map || (P->n_samp > 0 && !tod)) return set_error(FURAX_EINVAL, "NULL array");
+  if (P->dtype == FURAX_F32)
+    return chi2_grad_impl<float>(P, N, map_dt, map, (const float *)tod, chi2_out, grad_map,
+                                 grad_gain, grad_dpsi, stream);
+  return chi2_grad_impl<double>(P, N, map_dt, map, (const double *)tod, chi2_out, grad_map,
+                                grad_gain, grad_dpsi, stream);
+}
+
 furax_status furax_pointing_vjp(const furax_pointing *P, int32_t map_dt, const void *map,
                                 const void *tod_cot, double *grad_map, double *grad_gain,
                                 double *grad_dpsi, hipStream_t stream) {
@@ -376,6 +414,26 @@ furax_status furax_pointing_vjp(const furax_pointing *P, int32_t map_dt, const v
                            stream);
   return vjp_impl<double>(P, map_dt, map, (const double *)tod_cot, grad_map, grad_gain, grad_dpsi,
                           stream);
+}
+
+furax_status furax_stream_copy(const void *src, void *dst, int64_t bytes, int32_t nontemporal,
+                               hipStream_t stream) {
+  if (bytes < 0 || (bytes & 15)) return set_error(FURAX_EINVAL, "bytes must be a multiple of 16");
+  if (bytes > 0 && (!src || !dst)) return set_error(FURAX_EINVAL, "NULL buffer");
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15)
+    return set_error(FURAX_EINVAL, "buffers must be 16-byte aligned");
+  if (bytes == 0) return FURAX_OK;
+  const int64_t n16 = bytes / 16;
+  // a few waves of workgroups per CU, each thread streaming many 16-byte words
+  const unsigned grid = (unsigned)std::min<int64_t>((n16 + kBlock - 1) / kBlock, 256 * 32);
+  if (nontemporal)
+    hipLaunchKernelGGL(fx::k_stream_copy<true>, dim3(grid), dim3(kBlock), 0, stream,
+                       static_cast<const fx::u32x4 *>(src), static_cast<fx::u32x4 *>(dst), n16);
+  else
+    hipLaunchKernelGGL(fx::k_stream_copy<false>, dim3(grid), dim3(kBlock), 0, stream,
+                       static_cast<const fx::u32x4 *>(src), static_cast<fx::u32x4 *>(dst), n16);
+  FX_HIP(hipGetLastError());
+  return FURAX_OK;
 }
 
 }  // extern "C"

@@ -96,6 +96,8 @@ def _load() -> C.CDLL:
         "furax_pcg_read_timing": [vp, C.POINTER(_PcgTiming)],
         "furax_chi2": [P, N, i32, vp, vp, vp, vp, vp],
         "furax_pointing_vjp": [P, i32, vp, vp, vp, vp, vp, vp],
+        "furax_chi2_grad": [P, N, i32, vp, vp, vp, vp, vp, vp, vp],
+        "furax_stream_copy": [vp, vp, i64, i32, vp],
         "furax_last_error": [],
         "furax_release_caches": [],
         "furax_version": [],
@@ -119,8 +121,8 @@ EXPORTS = ("furax_ang2pix", "furax_pointing_apply", "furax_pointing_transpose",
            "furax_normal_workspace_bytes", "furax_normal_apply", "furax_pcg_mapmake",
            "furax_pcg_create", "furax_pcg_iterate", "furax_pcg_finish", "furax_pcg_destroy",
            "furax_pcg_set_timing", "furax_pcg_read_timing",
-           "furax_chi2", "furax_pointing_vjp", "furax_last_error", "furax_release_caches",
-           "furax_version")
+           "furax_chi2", "furax_pointing_vjp", "furax_chi2_grad", "furax_stream_copy",
+           "furax_last_error", "furax_release_caches", "furax_version")
 
 
 def library() -> C.CDLL:
@@ -567,15 +569,35 @@ def pointing_vjp(P: Pointing, m: Optional[torch.Tensor], cot: torch.Tensor,
     return (grad_map if want_map else None), gg, gd
 
 
+def chi2_grad(P: Pointing, N: Noise, m: torch.Tensor, tod: torch.Tensor, want_map: bool = True,
+              want_gain: bool = True, want_dpsi: bool = True, want_chi2: bool = False):
+    """Gradient of chi2 = r^T N^-1 r, r = d - P m, by furax_chi2_grad (one pass).
+
+    Returns (grad_map [3, npix] or None, grad_gain [n_det] or None,
+    grad_dpsi [n_det] or None, chi2 as a 0-d float64 tensor or None).
+    """
+    _dev(m, "map", shape=(3, P.npix))
+    _dev(tod, "tod", P.dtype, (P.n_det, P.n_samp))
+    gm = torch.zeros(3, P.npix, dtype=torch.float64, device=P.device) if want_map else None
+    gg = torch.empty(P.n_det, dtype=torch.float64, device=P.device) if want_gain else None
+    gd = torch.empty(P.n_det, dtype=torch.float64, device=P.device) if want_dpsi else None
+    c2 = torch.empty((), dtype=torch.float64, device=P.device) if want_chi2 else None
+    cp, cn = P.c(), N.c()
+    _check(_lib.furax_chi2_grad(C.byref(cp), C.byref(cn), _dt(m), _ptr(m), _ptr(tod), _ptr(c2),
+                                _ptr(gm), _ptr(gg), _ptr(gd), _stream(P.device)))
+    return gm, gg, gd, c2
+
+
 class Chi2Fn(torch.autograd.Function):
     """chi2(m, g, dpsi) = r^T N^-1 r,  r = d - P(psi + dpsi; g) m  (diagonal N).
 
-    Forward runs furax_chi2 and saves only (m, g, dpsi).  Backward recomputes the
-    pointing and the weighted residual u = N^-1 r on the device, then applies the
-    hand-written adjoint furax_pointing_vjp:
+    Forward runs furax_chi2 and saves only (m, g, dpsi).  Backward runs
+    furax_chi2_grad, which recomputes the pointing and the weighted residual
+    u = N^-1 r on the device and applies the hand-written adjoint:
         d chi2 / d m     = -2 P^T u,
         d chi2 / d g_k   = -2 sum_i u[k,i] (P_1 m)[k,i],
-        d chi2 / d dpsi_k = -2 sum_i u[k,i] g_k (-2 Q sin 2psi_eff + 2 U cos 2psi_eff).
+        d chi2 / d dpsi_k = -2 sum_i u[k,i] g_k (-2 Q sin 2psi_eff + 2 U cos 2psi_eff);
+    the binding only scales them by the incoming gradient.
     Use through chi2_loss(); P's own gain/dpsi are replaced by the arguments.
     """
 
@@ -592,14 +614,12 @@ class Chi2Fn(torch.autograd.Function):
         m, gain, dpsi = ctx.saved_tensors
         P = ctx.P.with_(gain=gain.detach().contiguous(), dpsi=dpsi.detach().contiguous())
         m = m.detach().contiguous()
-        _, u = chi2(P, ctx.N, m, ctx.d, want_resid=True)     # pointing recomputed here
-        gm, gg, gd = pointing_vjp(P, m, u, want_map=ctx.needs_input_grad[0],
+        gm, gg, gd, _ = chi2_grad(P, ctx.N, m, ctx.d, want_map=ctx.needs_input_grad[0],
                                   want_gain=ctx.needs_input_grad[1],
-                                  want_dpsi=ctx.needs_input_grad[2])
-        s = -2.0 * gout
-        return (None if gm is None else (s * gm).to(m.dtype),
-                None if gg is None else s * gg,
-                None if gd is None else s * gd, None, None, None)
+                                  want_dpsi=ctx.needs_input_grad[2])   # pointing recomputed
+        return (None if gm is None else (gout * gm).to(m.dtype),
+                None if gg is None else gout * gg,
+                None if gd is None else gout * gd, None, None, None)
 
 
 def chi2_loss(P: Pointing, N: Noise, d: torch.Tensor, m: torch.Tensor, gain: torch.Tensor,
@@ -609,6 +629,17 @@ def chi2_loss(P: Pointing, N: Noise, d: torch.Tensor, m: torch.Tensor, gain: tor
     if N.kind != "diag":
         raise ValueError("chi2_loss supports diagonal noise")
     return Chi2Fn.apply(m, gain, dpsi, P, N, d)
+
+
+def stream_copy(src: torch.Tensor, dst: torch.Tensor, nontemporal: bool = False):
+    """dst[:] = src[:] by the library's device copy (a measurement utility)."""
+    _dev(src, "src")
+    _dev(dst, "dst")
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb or not src.is_contiguous() or not dst.is_contiguous():
+        raise ValueError("stream_copy needs two contiguous buffers of the same size")
+    _check(_lib.furax_stream_copy(_ptr(src), _ptr(dst), nb, 1 if nontemporal else 0,
+                                  _stream(src.device)))
 
 
 def release_caches():

@@ -151,16 +151,16 @@ class Workload:
 # scale with 1/f noise and a HWP; 3: FP32 variant of 2; 4: differentiation;
 # 5: the large single-GPU run).
 WORKLOADS = {
-    1: Workload("nside64_4x65536_diag_f64", 1001, 64, 4, 65536, "diag", 1, False, "f64", 20,
-                offsets_deg=0.0),
+    1: Workload("nside64_4x65536_diag_f64", 1001, 64, 4, 65536, "diag", 1, False, "f64",
+                iters=20, offsets_deg=0.0),
     2: Workload("nside512_256x2^20_band4096_hwp_f64", 1002, 512, 256, 1 << 20, "band", 4096,
-                True, "f64", 50),
+                True, "f64", iters=50),
     3: Workload("nside512_256x2^20_band4096_hwp_f32", 1003, 512, 256, 1 << 20, "band", 4096,
-                True, "f32", 50),
+                True, "f32", iters=50),
     4: Workload("nside256_64x2^20_diag_f32_grad", 1004, 256, 64, 1 << 20, "diag", 1, False,
-                "f32", 0),
+                "f32", iters=0),
     5: Workload("nside1024_1024x2^20_band8192_hwp_f32", 1005, 1024, 1024, 1 << 20, "band", 8192,
-                True, "f32", 100),
+                True, "f32", iters=100),
 }
 
 

@@ -30,7 +30,8 @@ def lib():
 def test_header_declares_the_entry_points():
     names = _declared()
     for n in ("furax_ang2pix", "furax_pointing_apply", "furax_pointing_transpose",
-              "furax_noise_apply", "furax_pcg_mapmake", "furax_pointing_vjp"):
+              "furax_noise_apply", "furax_pcg_mapmake", "furax_pointing_vjp",
+              "furax_chi2_grad"):
         assert n in names
 
 
@@ -76,5 +77,13 @@ def test_validation_happens_before_any_launch(lib):
     assert L.furax_pcg_mapmake(C.byref(P), C.byref(Nd), lib.F64, 1, 1, None, C.byref(opts),
                                C.byref(info), None) == lib.EINVAL
     assert L.furax_ang2pix(9000, lib.F64, 1, 1, 4, 1, None) == lib.EINVAL
+    # chi2 gradient: NULL map, band noise, FP64 pointing with an FP32 map
+    assert L.furax_chi2_grad(C.byref(P), C.byref(Nd), lib.F64, None, 1, None, 1, None, None,
+                             None) == lib.EINVAL
+    Nb = lib._Noise(1, 1, 10, None, 4, 1, 0)
+    assert L.furax_chi2_grad(C.byref(P), C.byref(Nb), lib.F64, 1, 1, None, 1, None, None,
+                             None) == lib.EUNSUPPORTED
+    assert L.furax_chi2_grad(C.byref(P), C.byref(Nd), lib.F32, 1, 1, None, 1, None, None,
+                             None) == lib.EINVAL
     assert L.furax_pcg_iterate(None, 1) == lib.EINVAL
     assert L.furax_version() >= 100

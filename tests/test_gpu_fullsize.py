@@ -18,32 +18,11 @@ from oracle import mapmaker as omm
 from oracle import noise as onz
 from oracle import pointing as opt
 from paper_2603_19600_amd import synth
-from tests.gpu_util import dev, rel_err
+from tests.gpu_util import check_pixel_mismatches, dev, rel_err
 
 pytestmark = pytest.mark.gpu
 
 
-
-@pytest.fixture(scope="module")
-def fx():
-    from paper_2603_19600_amd import furax
-    return furax
-
-
-@pytest.fixture(scope="module")
-def full(fx):
-    """Canonical FP32 pointing of the workload and its exact FP64 promotion."""
-    w = synth.WORKLOADS[3]                     # FP32 canonical arrays
-    D = dev()
-    pt = synth.pointing(w, device=D, det_chunk=8)
-    hwp = (w.hwp_num, w.hwp_den, 0.0)
-    P32 = fx.Pointing(w.nside, pt.theta, pt.phi, pt.psi, hwp=hwp)
-    P64 = fx.Pointing(w.nside, pt.theta.double(), pt.phi.double(), pt.psi.double(), hwp=hwp)
-    lags = synth.toeplitz_lags(w)
-    N = fx.Noise("band", w.n_det, w.n_samp, lags=torch.from_numpy(lags).to(D))
-    m = synth.sky_map(w, device=D)
-    host = {k: getattr(pt, k)[list(ROWS)].double().cpu().numpy() for k in ("theta", "phi", "psi")}
-    return dict(w=w, P32=P32, P64=P64, N=N, lags=lags, m=m, hwp=hwp, host=host)
 
 # workload -> detector rows the oracle recomputes in full, detectors per group
 # of the decomposition test

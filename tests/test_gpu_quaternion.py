@@ -141,8 +141,12 @@ def test_quaternion_pcg_matches_oracle(fx, kind, dpsi):
     n = synth.noise(w.with_(noise="diag")).numpy()
     pix, c, s = prob.geometry()
     d = opt.apply_pix(pix, c, s, m, prob.gain) + n
-    ref = omm.pcg_mapmake(prob, d, max_iter=15, rtol=0.0)
-    x, valid, info, _ = fx.pcg_mapmake(P, N, torch.from_numpy(d).to(dev()), max_iter=15,
+    # diagonal N is solved exactly at the first iteration; the iterations after
+    # it act on rounding-level residuals that shrink until they underflow, so
+    # where each side stops there is noise: compare the first three
+    iters = 3 if kind == "diag" else 15
+    ref = omm.pcg_mapmake(prob, d, max_iter=iters, rtol=0.0)
+    x, valid, info, _ = fx.pcg_mapmake(P, N, torch.from_numpy(d).to(dev()), max_iter=iters,
                                        rtol=0.0, valid_in=torch.from_numpy(
                                            ref.valid.astype(np.uint8)).to(dev()))
     assert info.iters == ref.iters
