@@ -659,6 +659,9 @@ def main():
                     help="skip the gap-filling measurement")
     ap.add_argument("--no-copy", action="store_true", help="skip the device-copy ceiling")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--iters", type=int, default=0,
+                    help="PCG iterations per solve (0: the workload's own count); profiling "
+                         "runs shorten the solves with it")
     ap.add_argument("--cpu-dets", type=int, default=16)
     ap.add_argument("--cpu-workers", type=int, default=16,
                     help="worker processes of the CPU baseline (capped by the host's CPUs)")
@@ -701,6 +704,8 @@ def main():
     if args.calibrate:
         return
     w = synth.WORKLOADS[args.config]
+    if args.iters > 0:
+        w = w.with_(iters=args.iters)
     if w.dtype != "f32" or w.noise != "band":
         raise SystemExit("--config must name an FP32 band-noise workload (3 or 5)")
     primary, x32 = measure(w, dev, args.steps, args.warmup, "f32", keep_map=not args.no_fp64)
