@@ -351,6 +351,23 @@ furax_status furax_gap_fill(const furax_noise *C, int32_t dt, const uint8_t *gap
                             const furax_gapfill_opts *opt, furax_gapfill_info *info,
                             hipStream_t stream);
 
+/* furax_chi2_grad for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments and results as furax_chi2_grad; it calls no hipMalloc,
+ * hipFree or allocating library routine.  Its FP64 partial sums live in a
+ * static device array of 2^21 values (16 MiB) that every GPU the library runs
+ * on holds until the process ends (its address is looked up on the first call
+ * on each device).  A problem needing more partial sums than that -- one per
+ * sample tile plus two per detector and time block, e.g. 64 detectors x 2^20
+ * samples needs 5.3e5 -- returns FURAX_EUNSUPPORTED with nothing launched.
+ * Calls that overlap on one GPU (concurrent streams or threads) share the
+ * array and race; serialise them.  Every partial sum is written before it is
+ * read, so consecutive calls need no clearing. */
+furax_status furax_chi2_grad_noalloc(const furax_pointing *P, const furax_noise *N,
+                                     int32_t map_dt, const void *map, const void *tod,
+                                     double *chi2_out, double *grad_map, double *grad_gain,
+                                     double *grad_dpsi, hipStream_t stream);
+
 /* Measurement utility, not a step of the method: dst[0 .. bytes) =
  * src[0 .. bytes) on the device (bytes a multiple of 16, both buffers 16-byte
  * aligned and not overlapping).  nontemporal = 1 moves the data with

@@ -134,6 +134,11 @@ furax_status chi2_grad_impl(const furax_pointing *P, const furax_noise *N, int32
                             const void *map, const T *tod, double *chi2_out, double *grad_map,
                             double *grad_gain, double *grad_dpsi, hipStream_t s);
 template <typename T>
+furax_status chi2_grad_noalloc_impl(const furax_pointing *P, const furax_noise *N,
+                                    int32_t map_dt, const void *map, const T *tod,
+                                    double *chi2_out, double *grad_map, double *grad_gain,
+                                    double *grad_dpsi, hipStream_t s);
+template <typename T>
 furax_status vjp_impl(const furax_pointing *P, int32_t map_dt, const void *map, const T *cot,
                       double *grad_map, double *grad_gain, double *grad_dpsi, hipStream_t s);
 void release_twiddles();
@@ -398,6 +403,24 @@ furax_status furax_chi2_grad(const furax_pointing *P, const furax_noise *N, int3
                                  grad_gain, grad_dpsi, stream);
   return chi2_grad_impl<double>(P, N, map_dt, map, (const double *)tod, chi2_out, grad_map,
                                 grad_gain, grad_dpsi, stream);
+}
+
+furax_status furax_chi2_grad_noalloc(const furax_pointing *P, const furax_noise *N,
+                                     int32_t map_dt, const void *map, const void *tod,
+                                     double *chi2_out, double *grad_map, double *grad_gain,
+                                     double *grad_dpsi, hipStream_t stream) {
+  FX_TRY(check_pointing(P));
+  FX_TRY(check_noise(N, P->n_det, P->n_samp, P->dtype));
+  if (N->kind != 0) return set_error(FURAX_EUNSUPPORTED, "chi2 supports diagonal noise only");
+  if (!dtype_ok(map_dt)) return set_error(FURAX_EINVAL, "bad map dtype");
+  if (P->dtype == FURAX_F64 && map_dt != FURAX_F64)
+    return set_error(FURAX_EINVAL, "FP64 pointing needs an FP64 map");
+  if (!map || (P->n_samp > 0 && !tod)) return set_error(FURAX_EINVAL, "NULL array");
+  if (P->dtype == FURAX_F32)
+    return chi2_grad_noalloc_impl<float>(P, N, map_dt, map, (const float *)tod, chi2_out,
+                                         grad_map, grad_gain, grad_dpsi, stream);
+  return chi2_grad_noalloc_impl<double>(P, N, map_dt, map, (const double *)tod, chi2_out,
+                                        grad_map, grad_gain, grad_dpsi, stream);
 }
 
 furax_status furax_pointing_vjp(const furax_pointing *P, int32_t map_dt, const void *map,

@@ -23,6 +23,9 @@
 // Per-detector and chi-square partials are then summed in a fixed order, so
 // those results are reproducible bit for bit; the map gradient's atomics make
 // its last bits depend on scheduling.
+#include <mutex>
+#include <string>
+
 #include "common.h"
 #include "reduce.h"
 #include "tiles.h"
@@ -317,7 +320,8 @@ template furax_status chi2_impl<double>(const furax_pointing *, const furax_nois
 template <typename T, int MODE>
 static furax_status grad_pass(const furax_pointing *P, const furax_noise *N, int32_t map_dt,
                               const void *map, const T *tod, double *chi2_out, double *grad_map,
-                              double *grad_gain, double *grad_dpsi, hipStream_t s) {
+                              double *grad_gain, double *grad_dpsi, hipStream_t s,
+                              double *ext_scratch = nullptr, size_t ext_doubles = 0) {
   const double scale = MODE == kModeGrad ? -2.0 : 1.0;
   const bool det = grad_gain || grad_dpsi;
   if (P->n_samp == 0) {
@@ -329,9 +333,19 @@ static furax_status grad_pass(const furax_pointing *P, const furax_noise *N, int
   const int64_t npix = npix_of(P->nside);
   const PtArgs<T> a = pt_args<T>(P, nullptr);
   const Tiling tl = grad_tiling(a);
+  const size_t need = grad_scratch_doubles(a, det);
   DevBuf part;
-  FX_TRY(part.alloc(sizeof(double) * grad_scratch_doubles(a, det), s));
-  double *chi_part = static_cast<double *>(part.ptr);
+  double *chi_part = ext_scratch;
+  if (ext_scratch) {
+    if (need > ext_doubles)
+      return set_error(FURAX_EUNSUPPORTED,
+                       "this problem needs " + std::to_string(need) +
+                           " FP64 partial sums, more than the " + std::to_string(ext_doubles) +
+                           " of the library's static scratch; use furax_chi2_grad");
+  } else {
+    FX_TRY(part.alloc(sizeof(double) * need, s));
+    chi_part = static_cast<double *>(part.ptr);
+  }
   double *det_part = det ? chi_part + tl.blocks() : nullptr;
   launch_grad_any<T, MODE>(map_dt, a, map, npix, tl, tod,
                            MODE == kModeGrad ? N->inv_var : nullptr, scale, grad_map, det_part,
@@ -373,5 +387,56 @@ template furax_status chi2_grad_impl<float>(const furax_pointing *, const furax_
 template furax_status chi2_grad_impl<double>(const furax_pointing *, const furax_noise *, int32_t,
                                              const void *, const double *, double *, double *,
                                              double *, double *, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// The chi-square gradient without any allocation, for callers that cannot
+// allocate (HIP graph capture, serving loops).  Its partial sums live in a
+// file-scope device array: every GPU the library runs on holds its own copy
+// (kNoAllocScratchDoubles FP64 values, 16 MiB) until the process ends.  Host
+// code never passes the array's name to a kernel: its device address is looked
+// up once per device with hipGetSymbolAddress, with that device current, and
+// that address is what the kernels receive.  Every partial sum is written
+// before it is read, so nothing needs clearing between calls; calls that
+// overlap on one GPU share the array and race.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchDoubles = (size_t)1 << 21;
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices] = {};
+
+static furax_status scratch_of_current_device(double **out) {
+  int dev = 0;
+  FX_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return set_error(FURAX_EUNSUPPORTED, "device ordinal beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    FX_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return FURAX_OK;
+}
+
+template <typename T>
+furax_status chi2_grad_noalloc_impl(const furax_pointing *P, const furax_noise *N,
+                                    int32_t map_dt, const void *map, const T *tod,
+                                    double *chi2_out, double *grad_map, double *grad_gain,
+                                    double *grad_dpsi, hipStream_t s) {
+  double *ws = nullptr;
+  FX_TRY(scratch_of_current_device(&ws));
+  return grad_pass<T, kModeGrad>(P, N, map_dt, map, tod, chi2_out, grad_map, grad_gain,
+                                 grad_dpsi, s, ws, kNoAllocScratchDoubles);
+}
+template furax_status chi2_grad_noalloc_impl<float>(const furax_pointing *, const furax_noise *,
+                                                    int32_t, const void *, const float *, double *,
+                                                    double *, double *, double *, hipStream_t);
+template furax_status chi2_grad_noalloc_impl<double>(const furax_pointing *, const furax_noise *,
+                                                     int32_t, const void *, const double *,
+                                                     double *, double *, double *, double *,
+                                                     hipStream_t);
 
 }  // namespace fx

@@ -97,6 +97,7 @@ def _load() -> C.CDLL:
         "furax_chi2": [P, N, i32, vp, vp, vp, vp, vp],
         "furax_pointing_vjp": [P, i32, vp, vp, vp, vp, vp, vp],
         "furax_chi2_grad": [P, N, i32, vp, vp, vp, vp, vp, vp, vp],
+        "furax_chi2_grad_noalloc": [P, N, i32, vp, vp, vp, vp, vp, vp, vp],
         "furax_stream_copy": [vp, vp, i64, i32, vp],
         "furax_last_error": [],
         "furax_release_caches": [],
@@ -121,7 +122,8 @@ EXPORTS = ("furax_ang2pix", "furax_pointing_apply", "furax_pointing_transpose",
            "furax_normal_workspace_bytes", "furax_normal_apply", "furax_pcg_mapmake",
            "furax_pcg_create", "furax_pcg_iterate", "furax_pcg_finish", "furax_pcg_destroy",
            "furax_pcg_set_timing", "furax_pcg_read_timing",
-           "furax_chi2", "furax_pointing_vjp", "furax_chi2_grad", "furax_stream_copy",
+           "furax_chi2", "furax_pointing_vjp", "furax_chi2_grad", "furax_chi2_grad_noalloc",
+           "furax_stream_copy",
            "furax_last_error", "furax_release_caches", "furax_version")
 
 
