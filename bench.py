@@ -99,10 +99,10 @@ def kernel_bytes(w):
     """Algorithmic HBM bytes per launch of each phase of one PCG iteration.
 
     P: the pointing stream once and the map read once (what the operator
-    needs; its TOD output and the per-sample label it hands to P^T are the
-    decomposition's intermediates, not counted).  N^-1: its TOD in and out.
-    P^T: what it reads (the angle plane psi, the 2-byte pixel label, the
-    weighted TOD) and the FP64 map written once."""
+    needs; its TOD output is the decomposition's intermediate, not counted).
+    N^-1: its TOD in and out.  P^T: what it reads (the angle psi and the
+    2-byte pixel offset of every sample, from the plan's run-sorted copies,
+    and the weighted TOD) and the FP64 map written once."""
     e = 8 if w.dtype == "f64" else 4
     S = w.n_det * w.n_samp
     if w.pointing == "quat":

@@ -200,8 +200,9 @@ furax_status furax_bj_invert(int64_t npix, const double *M6, const int32_t *hits
  * With band N and a power-of-two nside the call also builds, stream-ordered,
  * the per-sample schedule of its P^T (samples sorted by nested superpixel of
  * 1024 pixels) and frees it before returning; a PCG session builds that
- * schedule once and reuses it for every iteration.  Its P^T sums in a fixed
- * order, so q is reproducible bit for bit from run to run. */
+ * schedule once and reuses it for every iteration.  Its P^T adds each
+ * superpixel's samples into FP64 sums with several waves at once, so the
+ * summation order, hence the last bits of q, may vary from run to run. */
 int64_t furax_normal_workspace_bytes(const furax_pointing *P, const furax_noise *N,
                                      int32_t precision);
 furax_status furax_normal_apply(const furax_pointing *P, const furax_noise *N, int32_t precision,

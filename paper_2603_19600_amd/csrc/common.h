@@ -179,14 +179,37 @@ __device__ __forceinline__ double two_psi_eff(const PtArgs<T> &a, int64_t k, int
 }
 
 // Polariser weights cos / sin of an angle given in FP64.  The FP64 variant
-// evaluates them in FP64; the FP32 variant first reduces the angle to
-// [-pi, pi] in FP64, then evaluates in FP32.
+// evaluates them in FP64 (the library's sincos).  The FP32 variant reduces
+// the angle in FP64 to r = ang - k pi/2 with k = rint(ang 2/pi), |r| <= pi/4
+// (the FP64 error of k pi/2 is ~k 1e-16, far below an FP32 ulp for the
+// angles of the method: |ang| < ~100), rounds r to FP32 and evaluates the
+// Taylor series of sin r to r^9 / 9! and of cos r to r^10 / 10! by Horner's
+// rule (truncation below 3e-9 on |r| <= pi/4), then places the quadrant:
+//   k mod 4 = 0: ( cos r,  sin r)    1: (-sin r,  cos r)
+//             2: (-cos r, -sin r)    3: ( sin r, -cos r).
 __device__ __forceinline__ void weights(double ang, double &c, double &s) {
   sincos(ang, &s, &c);
 }
 __device__ __forceinline__ void weights(double ang, float &c, float &s) {
-  const double r = ang - (2.0 * kPi) * rint(ang * (1.0 / (2.0 * kPi)));
-  sincosf((float)r, &s, &c);
+  constexpr double kHalfPi = 0.5 * kPi;
+  constexpr double kTwoOverPi = 2.0 / kPi;
+  const double k = rint(ang * kTwoOverPi);
+  const float r = (float)fma(-k, kHalfPi, ang);
+  const float r2 = r * r;
+  float ps = fmaf(r2, 1.0f / 362880.0f, -1.0f / 5040.0f);
+  ps = fmaf(r2, ps, 1.0f / 120.0f);
+  ps = fmaf(r2, ps, -1.0f / 6.0f);
+  const float sr = fmaf(r * r2, ps, r);
+  float pc = fmaf(r2, -1.0f / 3628800.0f, 1.0f / 40320.0f);
+  pc = fmaf(r2, pc, -1.0f / 720.0f);
+  pc = fmaf(r2, pc, 1.0f / 24.0f);
+  pc = fmaf(r2, pc, -0.5f);
+  const float cr = fmaf(r2, pc, 1.0f);
+  const int q = (int)k;
+  const bool swap = (q & 1) != 0;
+  const float c0 = swap ? sr : cr, s0 = swap ? cr : sr;
+  c = ((q + 1) & 2) ? -c0 : c0;
+  s = (q & 2) ? -s0 : s0;
 }
 
 // cos / sin of 2 (psi + beta) where psi = atan2(west, north): cos 2 psi and
@@ -385,7 +408,7 @@ struct SpChunk {
   int32_t nr;   // number of runs
   int32_t sp;   // superpixel
   int32_t w;    // samples in the chunk (sum of its run lengths)
-  int32_t pad;
+  int32_t s0;   // the chunk's first sample in the run-sorted sample order
 };
 
 // Everything the superpixel accumulation needs, built once per pointing.
@@ -398,6 +421,13 @@ struct SpPlan {
   SpChunk *chunks = nullptr;                // [n_chunks], ordered by superpixel
   int32_t *sp_chunk = nullptr;              // [n_sp + 1]: first chunk of each superpixel
   double *partial = nullptr;                // [n_chunks][n_values][P]
+  // every scheduled sample in run-sorted order (chunk by chunk, run by run):
+  // its pixel's offset inside the superpixel and, with angle pointing, its
+  // angle psi (a reordered copy of the input plane), so that P^T reads both
+  // contiguously instead of in run-sized pieces of the time-ordered planes
+  int64_t n_sorted = 0;
+  uint16_t *lab = nullptr;                  // [n_sorted]
+  void *psi = nullptr;                      // [n_sorted] of the pointing dtype, or null
   void release(hipStream_t s);
 };
 
@@ -410,16 +440,14 @@ furax_status sp_nest_plane(const SpPlan &sp, const PtArgs<T> &a, int32_t *plane,
 template <typename T>
 furax_status sp_build_runs(SpPlan &sp, const PtArgs<T> &a, const int32_t *nest_plane,
                            int32_t n_values, hipStream_t s);
-// q = P^T (w tod) in ring order (every pixel written).  The per-sample pixel
-// comes from `local` (offset inside its superpixel, as written by
-// launch_pointing_apply) or, when local is null, from the nested plane.
+// q = P^T (w tod) in ring order (every pixel written); the per-sample pixel
+// offsets (and psi) come from the plan's run-sorted copies.
 template <typename T>
 furax_status sp_transpose(const SpPlan &sp, const PtArgs<T> &a, const T *tod,
-                          const double *w_det, const uint16_t *local, const int32_t *nest_plane,
-                          double *q, MapLayout ql, hipStream_t s);
+                          const double *w_det, double *q, MapLayout ql, hipStream_t s);
 template <typename T>
-furax_status sp_bj_build(const SpPlan &sp, const PtArgs<T> &a, const double *w_det,
-                         const int32_t *nest_plane, double *M6, int32_t *hits, hipStream_t s);
+furax_status sp_bj_build(const SpPlan &sp, const PtArgs<T> &a, const double *w_det, double *M6,
+                         int32_t *hits, hipStream_t s);
 
 template <typename T>
 furax_status launch_noise(const furax_noise *N, const T *in, T *out, void *work,

@@ -222,16 +222,16 @@ static int64_t map_blocks(int64_t n) {
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct NormalLayout {
-  size_t spec = 0, y = 0, z = 0, pg = 0, qi = 0, wdet = 0, gpix = 0, local = 0, total = 0;
+  size_t spec = 0, y = 0, z = 0, pg = 0, qi = 0, wdet = 0, gpix = 0, total = 0;
+  bool sp = false;   // band noise with the superpixel-major P^T
 };
 
 // Workspace of the normal operator: per-detector diagonal weights, the band
 // kernel's spectrum and two TOD buffers (band noise), and the interleaved
-// gather copy of p and the interleaved FP64 accumulator of q; with band noise
-// also the per-sample label that P writes and P^T reads back, so the pointing
-// is pixelised once per application: the sample's offset inside its
-// superpixel (uint16) on the superpixel path, its ring pixel (int32) on the
-// tiled path.
+// gather copy of p and the interleaved FP64 accumulator of q.  With band
+// noise and no superpixel plan (nside not a power of two) also the ring pixel
+// of every sample (int32), which P writes and the tiled P^T reads back; with
+// the plan, P^T reads each sample's pixel offset from the plan.
 template <typename T>
 static NormalLayout normal_layout(const furax_pointing *P, const furax_noise *N) {
   NormalLayout L;
@@ -245,7 +245,7 @@ static NormalLayout normal_layout(const furax_pointing *P, const furax_noise *N)
     L.z = off; off += align256(tod);
     const size_t S = (size_t)P->n_det * P->n_samp;
     if (sp_supported(P->nside, (int64_t)S)) {
-      L.local = off; off += align256(sizeof(uint16_t) * S);
+      L.sp = true;
     } else {
       L.gpix = off; off += align256(sizeof(int32_t) * S);
     }
@@ -281,21 +281,20 @@ static furax_status normal_prepare(NormalPlan<T> &pl, hipStream_t s) {
   return FURAX_OK;
 }
 
-// Superpixel tables, runs and chunk partials of the plan's pointing (power-of-
-// two nside).  With M6/hits, the block-Jacobi blocks are accumulated on the
-// way; with nest_keep, the nested plane is handed to the caller (who frees it).
+// Superpixel tables, runs, run-sorted sample copies and chunk partials of the
+// plan's pointing (power-of-two nside).  With M6/hits, the block-Jacobi
+// blocks are accumulated on the way.
 template <typename T>
 static furax_status sp_prepare(NormalPlan<T> &pl, const double *w, double *M6, int32_t *hits,
-                               DevBuf *nest_keep, hipStream_t s) {
+                               hipStream_t s) {
   const int64_t S = pl.P->n_det * pl.P->n_samp;
   FX_TRY(sp_nest_tables(pl.sp, pl.P->nside, s));
-  DevBuf own;
-  DevBuf &plane = nest_keep ? *nest_keep : own;
+  DevBuf plane;
   FX_TRY(plane.alloc(sizeof(int32_t) * S, s));
   int32_t *np = static_cast<int32_t *>(plane.ptr);
   FX_TRY(sp_nest_plane<T>(pl.sp, pl.a, np, s));
   FX_TRY(sp_build_runs<T>(pl.sp, pl.a, np, M6 ? 7 : 3, s));
-  if (M6) FX_TRY(sp_bj_build<T>(pl.sp, pl.a, w, np, M6, hits, s));
+  if (M6) FX_TRY(sp_bj_build<T>(pl.sp, pl.a, w, M6, hits, s));
   return FURAX_OK;
 }
 
@@ -331,13 +330,11 @@ static furax_status normal_run(const NormalPlan<T> &pl, const T *pg, double *q, 
   T *y = reinterpret_cast<T *>(pl.work + pl.L.y);
   T *z = reinterpret_cast<T *>(pl.work + pl.L.z);
   if (pl.use_sp) {
-    uint16_t *local = reinterpret_cast<uint16_t *>(pl.work + pl.L.local);
-    FX_TRY(launch_pointing_apply<T>(pl.a, pg, f64, kInterleaved, y, s, nullptr, local,
-                                    (1 << pl.sp.log2P) - 1));
+    FX_TRY(launch_pointing_apply<T>(pl.a, pg, f64, kInterleaved, y, s));
     FX_TRY(mark(ev, 1, s));
     FX_TRY(noise_run<T>(pl.N, y, z, pl.work + pl.L.spec, s));
     FX_TRY(mark(ev, 2, s));
-    FX_TRY(sp_transpose<T>(pl.sp, pl.a, z, nullptr, local, nullptr, q, kInterleaved, s));
+    FX_TRY(sp_transpose<T>(pl.sp, pl.a, z, nullptr, q, kInterleaved, s));
     return mark(ev, 3, s);
   }
   int32_t *pix = reinterpret_cast<int32_t *>(pl.work + pl.L.gpix);
@@ -394,7 +391,7 @@ furax_status normal_apply_impl(const furax_pointing *P, const furax_noise *N, co
   pl.a = pt_args<T>(P, nullptr);
   pl.L = normal_layout<T>(P, N);
   pl.npix = npix_of(P->nside);
-  pl.use_sp = N->kind != 0 && pl.L.local != 0;
+  pl.use_sp = N->kind != 0 && pl.L.sp;
   DevBuf own;
   if (!work) {
     FX_TRY(own.alloc(pl.L.total, s));
@@ -403,7 +400,7 @@ furax_status normal_apply_impl(const furax_pointing *P, const furax_noise *N, co
   pl.work = static_cast<char *>(work);
   FX_TRY(normal_prepare<T>(pl, s));
   furax_status st = FURAX_OK;
-  if (pl.use_sp) st = sp_prepare<T>(pl, nullptr, nullptr, nullptr, nullptr, s);
+  if (pl.use_sp) st = sp_prepare<T>(pl, nullptr, nullptr, nullptr, s);
   if (st == FURAX_OK) {
     T *pg = reinterpret_cast<T *>(pl.work + pl.L.pg);
     double *qi = reinterpret_cast<double *>(pl.work + pl.L.qi);
@@ -532,11 +529,10 @@ static furax_status pcg_setup(furax_pcg_state *h, const void *tod) {
   const double *w = reinterpret_cast<const double *>(pl.work + pl.L.wdet);
   const int64_t S = h->P.n_det * h->P.n_samp;
   pl.use_sp = sp_supported(h->P.nside, S);
-  DevBuf nest_plane;
   if (pl.use_sp) {
     // superpixel plan (kept for the iterations) and the blocks on the way
-    FX_TRY(sp_prepare<T>(pl, w, M6, hits, &nest_plane, s));
-    pl.use_sp = h->N.kind != 0 && pl.L.local != 0;
+    FX_TRY(sp_prepare<T>(pl, w, M6, hits, s));
+    pl.use_sp = h->N.kind != 0 && pl.L.sp;
   } else {
     FX_TRY(zero_async(M6, sizeof(double) * 6 * npix, s));
     FX_TRY(zero_async(hits, sizeof(int32_t) * npix, s));
@@ -559,9 +555,8 @@ static furax_status pcg_setup(furax_pcg_state *h, const void *tod) {
     zt = zbuf;
     wd = nullptr;
   }
-  if (nest_plane.ptr) {
-    FX_TRY(sp_transpose<T>(pl.sp, pl.a, zt, wd, nullptr, static_cast<const int32_t *>(nest_plane.ptr),
-                           b, planar_layout(npix), s));
+  if (pl.sp.lab) {
+    FX_TRY(sp_transpose<T>(pl.sp, pl.a, zt, wd, b, planar_layout(npix), s));
   } else {
     FX_TRY(zero_async(b, sizeof(double) * 3 * npix, s));
     FX_TRY(launch_scatter<T>(pl.a, zt, wd, nullptr, false, planar_layout(npix), b,

@@ -103,9 +103,10 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *
   __shared__ TileConsts tc;
   __shared__ Quat tq[QUAT ? kMaxTileDets : 1];
   __shared__ double2 turn4a[QUAT ? kMaxTileSamples : 1];
-  const int64_t tile = tile_of_block(blockIdx.x, tl.blocks());
-  const int64_t d0 = (tile / tl.n_tb) * tl.dets;
-  const int64_t t0 = (tile % tl.n_tb) << tl.log2ts;
+  int64_t dg, tb;
+  tile_coords(tl, tile_of_block(blockIdx.x, tl.blocks()), dg, tb);
+  const int64_t d0 = dg * tl.dets;
+  const int64_t t0 = tb << tl.log2ts;
   const int32_t nsamp = tl.dets << tl.log2ts;
   load_tile_consts(a, nullptr, tl, d0, t0, tc);
   if constexpr (QUAT) load_tile_quats(a.qd, a.n_det, tl, d0, tq);
@@ -234,9 +235,10 @@ k_scatter(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_d
     acc[1][h] = 0.0;
     acc[2][h] = 0.0;
   }
-  const int64_t tile = tile_of_block(blockIdx.x, tl.blocks());
-  const int64_t d0 = (tile / tl.n_tb) * tl.dets;
-  const int64_t t0 = (tile % tl.n_tb) << tl.log2ts;
+  int64_t dg, tb;
+  tile_coords(tl, tile_of_block(blockIdx.x, tl.blocks()), dg, tb);
+  const int64_t d0 = dg * tl.dets;
+  const int64_t t0 = tb << tl.log2ts;
   const int32_t nsamp = tl.dets << tl.log2ts;
   load_tile_consts(a, w_det, tl, d0, t0, tc);
   if constexpr (QUAT) load_tile_quats(a.qd, a.n_det, tl, d0, tq);

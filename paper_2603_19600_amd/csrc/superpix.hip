@@ -18,12 +18,17 @@
 //    LDS sums indexed directly by the pixel's offset inside the superpixel:
 //    no hashing, and nothing atomic outside LDS;
 //  * a second kernel sums each superpixel's chunk partials in chunk order
-//    and writes every pixel of the output exactly once, in ring order, so the
-//    result is also bitwise reproducible.
+//    and writes every pixel of the output exactly once, in ring order.  The
+//    LDS sums of a chunk are added by several waves at once, so their order,
+//    hence the last bits of the result, may differ from run to run.
 //
-// The pointing is still expanded on the fly at every application: the runs
-// are a schedule derived from it once, and the per-sample pixel offset that
-// the accumulation reads is written by the P of the same application.
+// The plan also keeps, in the run-sorted order, each scheduled sample's pixel
+// offset inside its superpixel and (angle pointing) its angle psi, so that
+// the accumulation reads them contiguously rather than in run-sized pieces
+// of the time-ordered planes, whose partly used cache lines would triple its
+// traffic.  P still expands the pointing at every application for its own
+// gathers; P^T recomputes the polariser weights from psi (or the
+// quaternions) at every application.
 #include <algorithm>
 #include <vector>
 
@@ -189,13 +194,38 @@ __global__ void __launch_bounds__(kFinalizeThreads) k_run_finalize(uint64_t *__r
   if (r == ch.nr - 1) ch.w = incl;
 }
 
+// One workgroup per chunk, one thread per run: copy the run's samples' pixel
+// offsets (nested index minus the superpixel's first) and, with angle
+// pointing, their angles psi into the run-sorted order.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sp_sort(const uint64_t *__restrict__ runs,
+                                                    const SpChunk *__restrict__ chunks,
+                                                    const int32_t *__restrict__ nest_plane,
+                                                    const T *__restrict__ psi, int32_t log2P,
+                                                    uint16_t *__restrict__ lab,
+                                                    T *__restrict__ psi_out) {
+  const SpChunk ch = chunks[blockIdx.x];
+  const int32_t base = ch.sp << log2P;
+  for (int r = threadIdx.x; r < ch.nr; r += kBlock) {
+    const uint64_t w = runs[ch.r0 + r];
+    const int64_t off = (int64_t)(w >> 24);
+    const int32_t pre = (int32_t)(w & 0xffffff);
+    const int32_t end = r + 1 < ch.nr ? (int32_t)(runs[ch.r0 + r + 1] & 0xffffff) : ch.w;
+    const int64_t dst = (int64_t)ch.s0 + pre;
+    for (int32_t t = 0; t < end - pre; ++t) {
+      lab[dst + t] = (uint16_t)(nest_plane[off + t] - base);
+      if (psi_out) psi_out[dst + t] = psi[off + t];
+    }
+  }
+}
+
 static unsigned grid_for(int64_t n, int64_t cap = 65536) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, cap));
 }
 
 void SpPlan::release(hipStream_t s) {
   for (void *p : {(void *)n2r, (void *)r2n, (void *)runs, (void *)chunks, (void *)sp_chunk,
-                  (void *)partial}) {
+                  (void *)partial, (void *)lab, psi}) {
     if (p) (void)hipFreeAsync(p, s);
   }
   *this = SpPlan();
@@ -298,7 +328,7 @@ furax_status sp_build_runs(SpPlan &sp, const PtArgs<T> &a, const int32_t *plane,
       k.nr = (int32_t)std::min<int64_t>(cr, hc[p] - c);
       k.sp = (int32_t)p;
       k.w = 0;
-      k.pad = 0;
+      k.s0 = 0;
       ch.push_back(k);
     }
     r += hc[p];
@@ -324,6 +354,28 @@ furax_status sp_build_runs(SpPlan &sp, const PtArgs<T> &a, const int32_t *plane,
     hipLaunchKernelGGL(k_run_finalize, dim3((unsigned)sp.n_chunks), dim3(kFinalizeThreads), 0, s,
                        sp.runs, sp.chunks);
     FX_HIP(hipGetLastError());
+    // each chunk's first position in the run-sorted sample order
+    FX_HIP(hipMemcpyAsync(ch.data(), sp.chunks, sizeof(SpChunk) * sp.n_chunks,
+                          hipMemcpyDeviceToHost, s));
+    FX_HIP(hipStreamSynchronize(s));
+    int64_t pos = 0;
+    for (auto &c : ch) {
+      c.s0 = (int32_t)pos;
+      pos += c.w;
+    }
+    sp.n_sorted = pos;
+    FX_HIP(hipMemcpyAsync(sp.chunks, ch.data(), sizeof(SpChunk) * sp.n_chunks,
+                          hipMemcpyHostToDevice, s));
+  }
+  if (hipMallocAsync((void **)&sp.lab, sizeof(uint16_t) * std::max<int64_t>(sp.n_sorted, 1), s) !=
+          hipSuccess ||
+      (!a.qb && hipMallocAsync(&sp.psi, sizeof(T) * std::max<int64_t>(sp.n_sorted, 1), s) !=
+                    hipSuccess))
+    return set_error(FURAX_ENOMEM, "superpixel sample order: allocation failed");
+  if (sp.n_chunks) {
+    hipLaunchKernelGGL(k_sp_sort<T>, dim3((unsigned)sp.n_chunks), dim3(kBlock), 0, s, sp.runs,
+                       sp.chunks, plane, a.psi, sp.log2P, sp.lab, static_cast<T *>(sp.psi));
+    FX_HIP(hipGetLastError());
   }
   FX_HIP(hipStreamSynchronize(s));   // the host vectors die here
   return FURAX_OK;
@@ -345,9 +397,10 @@ template furax_status sp_build_runs<double>(SpPlan &, const PtArgs<double> &, co
 // of run lengths, stored with each run by the plan builder).  Lanes take
 // consecutive slots, so every lane is busy whatever the run lengths, and the
 // loads stay coalesced along each run.  Each run's offset, detector constants
-// and HWP phase are staged in LDS once per chunk.  `local` is the per-sample
-// pixel offset inside its superpixel (written by P in the same application),
-// or, when null, the nested plane gives it.
+// and HWP phase are staged in LDS once per chunk.  The pixel offset inside the
+// superpixel and the angle psi of each slot come from the plan's run-sorted
+// copies (lab, psi_s), read contiguously; the TOD is read in place, along
+// each run.
 // ---------------------------------------------------------------------------
 constexpr int kSpThreads = 512;
 // Occupancy of the accumulation: with 512 runs per chunk the LDS below (the
@@ -406,7 +459,7 @@ __device__ __forceinline__ int32_t run_of(const int32_t *pre, int32_t lo, int32_
 template <typename T, int KIND, bool QUAT, int NR>
 __global__ void __launch_bounds__(kSpThreads)
 k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_det,
-           const uint16_t *__restrict__ local, const int32_t *__restrict__ nest_plane,
+           const uint16_t *__restrict__ lab, const T *__restrict__ psi_s,
            const uint64_t *__restrict__ runs, const SpChunk *__restrict__ chunks, int32_t log2P,
            double *__restrict__ partial) {
   __shared__ SpLds<KIND, NR> L;
@@ -462,7 +515,6 @@ k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_
   constexpr int kSlotBatch = slot_batch<T, QUAT, NR>();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int kWaves = kSpThreads / 64;
-  const int32_t base = ch.sp << log2P;
   // Each wave owns a contiguous range of 64-slot blocks and walks it with a
   // run cursor rb (the run holding the block's first slot); lane l looks at
   // the start of run rb + 1 + l, so a block's lanes see every run that can
@@ -498,13 +550,14 @@ k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_
       run[b] = r;
       tt[b] = jj - L.run.pre[r];                        // offset inside the run
       sidx[b] = (int64_t)L.run.det[r] * a.n_samp + (L.run.i0[r] + tt[b]);
-      lo[b] = local ? (int32_t)local[sidx[b]] : nest_plane[sidx[b]] - base;
+      const int64_t sj = (int64_t)ch.s0 + jj;           // run-sorted position
+      lo[b] = (int32_t)lab[sj];
       if constexpr (KIND == 0) z[b] = tod[sidx[b]];
       if constexpr (QUAT) {
         qb[b] = load_quat(a.qb, L.run.i0[r] + tt[b]);
         qd[b] = load_quat(a.qd, L.run.det[r]);
       } else {
-        ps[b] = a.psi[sidx[b]];
+        ps[b] = psi_s[sj];
       }
     }
 #pragma unroll
@@ -601,23 +654,27 @@ __global__ void __launch_bounds__(kBlock) k_sp_reduce(int64_t npix, int32_t log2
   }
 }
 
+template <typename T, int KIND>
+static void launch_sp_accum(const SpPlan &sp, const PtArgs<T> &a, const T *tod,
+                            const double *w_det, hipStream_t s) {
+  const dim3 grid((unsigned)sp.n_chunks), blk(kSpThreads);
+  const T *psi = static_cast<const T *>(sp.psi);
+  if (a.qb)
+    hipLaunchKernelGGL((k_sp_accum<T, KIND, true, kChunkRunsMax>), grid, blk, 0, s, a, tod, w_det,
+                       sp.lab, psi, sp.runs, sp.chunks, sp.log2P, sp.partial);
+  else if (sp.chunk_runs == kChunkRunsSmall)
+    hipLaunchKernelGGL((k_sp_accum<T, KIND, false, kChunkRunsSmall>), grid, blk, 0, s, a, tod,
+                       w_det, sp.lab, psi, sp.runs, sp.chunks, sp.log2P, sp.partial);
+  else
+    hipLaunchKernelGGL((k_sp_accum<T, KIND, false, kChunkRunsMax>), grid, blk, 0, s, a, tod,
+                       w_det, sp.lab, psi, sp.runs, sp.chunks, sp.log2P, sp.partial);
+}
+
 template <typename T>
 furax_status sp_transpose(const SpPlan &sp, const PtArgs<T> &a, const T *tod,
-                          const double *w_det, const uint16_t *local, const int32_t *nest_plane,
-                          double *q, MapLayout ql, hipStream_t s) {
+                          const double *w_det, double *q, MapLayout ql, hipStream_t s) {
   if (sp.n_chunks > 0) {
-    if (a.qb)
-      hipLaunchKernelGGL((k_sp_accum<T, 0, true, kChunkRunsMax>), dim3((unsigned)sp.n_chunks),
-                         dim3(kSpThreads), 0, s, a, tod, w_det, local, nest_plane, sp.runs,
-                         sp.chunks, sp.log2P, sp.partial);
-    else if (sp.chunk_runs == kChunkRunsSmall)
-      hipLaunchKernelGGL((k_sp_accum<T, 0, false, kChunkRunsSmall>), dim3((unsigned)sp.n_chunks),
-                         dim3(kSpThreads), 0, s, a, tod, w_det, local, nest_plane, sp.runs,
-                         sp.chunks, sp.log2P, sp.partial);
-    else
-      hipLaunchKernelGGL((k_sp_accum<T, 0, false, kChunkRunsMax>), dim3((unsigned)sp.n_chunks),
-                         dim3(kSpThreads), 0, s, a, tod, w_det, local, nest_plane, sp.runs,
-                         sp.chunks, sp.log2P, sp.partial);
+    launch_sp_accum<T, 0>(sp, a, tod, w_det, s);
     FX_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_sp_reduce, dim3(grid_for(sp.npix, 16384)), dim3(kBlock), 0, s, sp.npix,
@@ -627,33 +684,18 @@ furax_status sp_transpose(const SpPlan &sp, const PtArgs<T> &a, const T *tod,
   return FURAX_OK;
 }
 template furax_status sp_transpose<float>(const SpPlan &, const PtArgs<float> &, const float *,
-                                          const double *, const uint16_t *, const int32_t *,
-                                          double *, MapLayout, hipStream_t);
+                                          const double *, double *, MapLayout, hipStream_t);
 template furax_status sp_transpose<double>(const SpPlan &, const PtArgs<double> &,
-                                           const double *, const double *, const uint16_t *,
-                                           const int32_t *, double *, MapLayout, hipStream_t);
+                                           const double *, const double *, double *, MapLayout,
+                                           hipStream_t);
 
 // Block-Jacobi blocks M6 [6][npix] and hits [npix]; needs a plan built with
-// n_values = 7 and the nested plane of the pointing.
+// n_values = 7.
 template <typename T>
-furax_status sp_bj_build(const SpPlan &sp, const PtArgs<T> &a, const double *w_det,
-                         const int32_t *nest_plane, double *M6, int32_t *hits, hipStream_t s) {
+furax_status sp_bj_build(const SpPlan &sp, const PtArgs<T> &a, const double *w_det, double *M6,
+                         int32_t *hits, hipStream_t s) {
   if (sp.n_chunks > 0) {
-    if (a.qb)
-      hipLaunchKernelGGL((k_sp_accum<T, 1, true, kChunkRunsMax>), dim3((unsigned)sp.n_chunks),
-                         dim3(kSpThreads), 0, s, a, (const T *)nullptr, w_det,
-                         (const uint16_t *)nullptr, nest_plane, sp.runs, sp.chunks, sp.log2P,
-                         sp.partial);
-    else if (sp.chunk_runs == kChunkRunsSmall)
-      hipLaunchKernelGGL((k_sp_accum<T, 1, false, kChunkRunsSmall>), dim3((unsigned)sp.n_chunks),
-                         dim3(kSpThreads), 0, s, a, (const T *)nullptr, w_det,
-                         (const uint16_t *)nullptr, nest_plane, sp.runs, sp.chunks, sp.log2P,
-                         sp.partial);
-    else
-      hipLaunchKernelGGL((k_sp_accum<T, 1, false, kChunkRunsMax>), dim3((unsigned)sp.n_chunks),
-                         dim3(kSpThreads), 0, s, a, (const T *)nullptr, w_det,
-                         (const uint16_t *)nullptr, nest_plane, sp.runs, sp.chunks, sp.log2P,
-                         sp.partial);
+    launch_sp_accum<T, 1>(sp, a, (const T *)nullptr, w_det, s);
     FX_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_sp_reduce, dim3(grid_for(sp.npix, 16384)), dim3(kBlock), 0, s, sp.npix,
@@ -662,9 +704,9 @@ furax_status sp_bj_build(const SpPlan &sp, const PtArgs<T> &a, const double *w_d
   return FURAX_OK;
 }
 template furax_status sp_bj_build<float>(const SpPlan &, const PtArgs<float> &, const double *,
-                                         const int32_t *, double *, int32_t *, hipStream_t);
+                                         double *, int32_t *, hipStream_t);
 template furax_status sp_bj_build<double>(const SpPlan &, const PtArgs<double> &, const double *,
-                                          const int32_t *, double *, int32_t *, hipStream_t);
+                                          double *, int32_t *, hipStream_t);
 
 template <typename T>
 furax_status sp_nest_plane(const SpPlan &sp, const PtArgs<T> &a, int32_t *plane, hipStream_t s) {

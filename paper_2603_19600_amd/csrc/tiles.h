@@ -8,13 +8,25 @@
 
 namespace fx {
 
-// Block index -> logical tile, keeping consecutive time blocks of one detector
-// group on the same XCD (workgroups are dealt round-robin over the 8 XCDs), so
-// the map lines a tile touches are likely already in that XCD's L2.
+// Block index -> logical tile, keeping consecutive logical tiles on the same
+// XCD (workgroups are dealt round-robin over the 8 XCDs), so the map lines a
+// tile touches are likely already in that XCD's L2.
 __device__ __forceinline__ int64_t tile_of_block(int64_t bid, int64_t nblocks) {
   const int64_t per = nblocks / 8;
   if (per == 0 || bid >= per * 8) return bid;
   return (bid % 8) * per + bid / 8;
+}
+
+// Logical tile -> (detector group, time block).  Time blocks are the outer
+// index and detector groups the inner one: the groups of one time block look
+// at the same patch of sky (every group spans the whole focal plane), so they
+// run next to each other on one XCD and share its L2 copy of the map lines,
+// instead of each XCD walking one group along the scan and fetching the same
+// lines again.
+__device__ __forceinline__ void tile_coords(const Tiling &tl, int64_t tile, int64_t &dg,
+                                            int64_t &tb) {
+  tb = tile / tl.n_dg;
+  dg = tile - tb * tl.n_dg;
 }
 
 

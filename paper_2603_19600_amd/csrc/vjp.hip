@@ -76,8 +76,8 @@ k_grad_tile(PtArgs<T> a, const MT *__restrict__ m, int64_t npix, Tiling tl,
       acc[2][h] = 0.0;
     }
   }
-  const int64_t tile = tile_of_block(blockIdx.x, tl.blocks());
-  const int64_t dg = tile / tl.n_tb, tb = tile % tl.n_tb;
+  int64_t dg, tb;
+  tile_coords(tl, tile_of_block(blockIdx.x, tl.blocks()), dg, tb);
   const int64_t d0 = dg * tl.dets;
   const int64_t t0 = tb << tl.log2ts;
   const int32_t nsamp = tl.dets << tl.log2ts;
