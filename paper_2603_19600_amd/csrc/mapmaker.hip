@@ -295,6 +295,7 @@ static furax_status sp_prepare(NormalPlan<T> &pl, const double *w, double *M6, i
   FX_TRY(sp_nest_plane<T>(pl.sp, pl.a, np, s));
   FX_TRY(sp_build_runs<T>(pl.sp, pl.a, np, M6 ? 7 : 3, s));
   if (M6) FX_TRY(sp_bj_build<T>(pl.sp, pl.a, w, M6, hits, s));
+  pl.a.det_perm = pl.sp.det_perm;   // P's tiles take the detectors in sky order
   return FURAX_OK;
 }
 
@@ -562,7 +563,10 @@ static furax_status pcg_setup(furax_pcg_state *h, const void *tod) {
     FX_TRY(launch_scatter<T>(pl.a, zt, wd, nullptr, false, planar_layout(npix), b,
                               planar_layout(npix), s));
   }
-  if (!pl.use_sp && pl.sp.n2r) pl.sp.release(s);   // diagonal noise: tables no longer needed
+  if (!pl.use_sp && pl.sp.n2r) {   // diagonal noise: tables no longer needed
+    pl.sp.release(s);
+    pl.a.det_perm = nullptr;
+  }
   // r = b (copied into r), x = 0, z = Minv r, p = z.  b lives in z; k_init_vectors
   // reads b[i] before writing z[i] for the same i, element by element.
   hipLaunchKernelGGL(k_init_vectors<T>, dim3((unsigned)kRedBlocks), dim3(kBlock), 0, s, npix, b,

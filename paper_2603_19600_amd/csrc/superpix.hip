@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(kBlock) k_nest_plane(PtArgs<T> a, const int32_
       const QuatDir d = quat_dir(qmul(load_quat(a.qb, i), load_quat(a.qd, k)));
       p = zphi2pix_ring(a.nside, d.z, d.phi);
     } else {
-      p = ang2pix_ring(a.nside, (double)a.theta[s], (double)a.phi[s]);
+      p = ang2pix_any(a.nside, a.theta[s], a.phi[s]);
     }
     plane[s] = p >= 0 ? r2n[p] : -1;
   }
@@ -219,13 +219,24 @@ __global__ void __launch_bounds__(kBlock) k_sp_sort(const uint64_t *__restrict__
   }
 }
 
+// The nested index of each detector's first sample (the largest int32 when
+// that sample's pointing is invalid): the key that orders the detectors.
+__global__ void __launch_bounds__(kBlock) k_det_keys(int64_t n_det, int64_t n_samp,
+                                                     const int32_t *__restrict__ plane,
+                                                     int32_t *__restrict__ key) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n_det) return;
+  const int32_t v = plane[k * n_samp];
+  key[k] = v >= 0 ? v : 0x7fffffff;
+}
+
 static unsigned grid_for(int64_t n, int64_t cap = 65536) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, cap));
 }
 
 void SpPlan::release(hipStream_t s) {
   for (void *p : {(void *)n2r, (void *)r2n, (void *)runs, (void *)chunks, (void *)sp_chunk,
-                  (void *)partial, (void *)lab, psi}) {
+                  (void *)partial, (void *)lab, psi, (void *)det_perm}) {
     if (p) (void)hipFreeAsync(p, s);
   }
   *this = SpPlan();
@@ -372,6 +383,28 @@ furax_status sp_build_runs(SpPlan &sp, const PtArgs<T> &a, const int32_t *plane,
       (!a.qb && hipMallocAsync(&sp.psi, sizeof(T) * std::max<int64_t>(sp.n_sorted, 1), s) !=
                     hipSuccess))
     return set_error(FURAX_ENOMEM, "superpixel sample order: allocation failed");
+  // detector order for the sample tiles of P: by the nested index of the
+  // first sample, a walk along a space-filling curve, so that detectors a
+  // tile takes together look at neighbouring pixels
+  {
+    DevBuf b_dkey;
+    FX_TRY(b_dkey.alloc(sizeof(int32_t) * a.n_det, s));
+    hipLaunchKernelGGL(k_det_keys, dim3((unsigned)((a.n_det + kBlock - 1) / kBlock)), dim3(kBlock),
+                       0, s, a.n_det, a.n_samp, plane, static_cast<int32_t *>(b_dkey.ptr));
+    FX_HIP(hipGetLastError());
+    std::vector<int32_t> dkey(a.n_det), perm(a.n_det);
+    FX_HIP(hipMemcpyAsync(dkey.data(), b_dkey.ptr, sizeof(int32_t) * a.n_det,
+                          hipMemcpyDeviceToHost, s));
+    FX_HIP(hipStreamSynchronize(s));
+    for (int64_t k = 0; k < a.n_det; ++k) perm[k] = (int32_t)k;
+    std::stable_sort(perm.begin(), perm.end(),
+                     [&dkey](int32_t x, int32_t y) { return dkey[x] < dkey[y]; });
+    if (hipMallocAsync((void **)&sp.det_perm, sizeof(int32_t) * a.n_det, s) != hipSuccess)
+      return set_error(FURAX_ENOMEM, "detector order: allocation failed");
+    FX_HIP(hipMemcpyAsync(sp.det_perm, perm.data(), sizeof(int32_t) * a.n_det,
+                          hipMemcpyHostToDevice, s));
+    FX_HIP(hipStreamSynchronize(s));   // perm dies here
+  }
   if (sp.n_chunks) {
     hipLaunchKernelGGL(k_sp_sort<T>, dim3((unsigned)sp.n_chunks), dim3(kBlock), 0, s, sp.runs,
                        sp.chunks, plane, a.psi, sp.log2P, sp.lab, static_cast<T *>(sp.psi));

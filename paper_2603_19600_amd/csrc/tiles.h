@@ -47,16 +47,22 @@ struct Slot {
 };
 
 __device__ __forceinline__ Slot slot_of(const Tiling &tl, int64_t d0, int64_t t0, int32_t s,
-                                        int64_t n_det, int64_t n_samp) {
+                                        int64_t n_det, int64_t n_samp,
+                                        const int32_t *tile_det) {
   Slot r;
   r.kl = s >> tl.log2ts;
-  r.k = d0 + r.kl;
   r.il = s & ((1 << tl.log2ts) - 1);
   const int64_t i = t0 + r.il;
-  r.in = s < (tl.dets << tl.log2ts) && r.k < n_det && i < n_samp;
+  r.in = s < (tl.dets << tl.log2ts) && d0 + r.kl < n_det && i < n_samp;
+  r.k = r.in ? (int64_t)tile_det[r.kl] : 0;
   r.off = r.in ? r.k * n_samp + i : 0;
-  if (!r.in) r.k = 0;
   return r;
+}
+
+// The detector taking tile position d0 + j (within n_det).
+template <typename T>
+__device__ __forceinline__ int64_t tile_detector(const PtArgs<T> &a, int64_t idx) {
+  return a.det_perm ? (int64_t)a.det_perm[idx] : idx;
 }
 
 // Per-tile constants staged in LDS once per workgroup: the HWP term
@@ -67,6 +73,7 @@ constexpr int kMaxTileSamples = 1024;   // longest tile (2^10 samples per detect
 struct TileConsts {
   double two_alpha[kMaxTileSamples];
   double gain[kMaxTileDets], dpsi[kMaxTileDets], w[kMaxTileDets];
+  int32_t det[kMaxTileDets];   // the detector at each tile position
 };
 
 template <typename T>
@@ -78,7 +85,8 @@ __device__ __forceinline__ void load_tile_consts(const PtArgs<T> &a, const doubl
       tc.two_alpha[t] = 2.0 * hwp_alpha(t0 + t, a.hwp_num_mod, a.hwp_den, a.hwp_phase0);
   }
   for (int j = threadIdx.x; j < tl.dets; j += blockDim.x) {
-    const int64_t k = d0 + j < a.n_det ? d0 + j : 0;
+    const int64_t k = d0 + j < a.n_det ? tile_detector(a, d0 + j) : 0;
+    tc.det[j] = (int32_t)k;
     tc.gain[j] = a.gain ? a.gain[k] : 1.0;
     tc.dpsi[j] = a.dpsi ? a.dpsi[k] : 0.0;
     tc.w[j] = w_det ? w_det[k] : 1.0;
@@ -99,7 +107,7 @@ __device__ __forceinline__ void pol_weights(const PtArgs<T> &a, const TileConsts
 
 template <typename T>
 __device__ __forceinline__ int32_t pixel_of(const PtArgs<T> &a, T theta, T phi) {
-  int32_t p = ang2pix_ring(a.nside, (double)theta, (double)phi);
+  int32_t p = ang2pix_any(a.nside, theta, phi);
   if (p >= 0 && a.valid && !a.valid[p]) p = -1;
   return p;
 }
@@ -108,10 +116,11 @@ __device__ __forceinline__ int32_t pixel_of(const PtArgs<T> &a, T theta, T phi) 
 // the other per-detector constants; a slot's geometry then needs its boresight
 // attitude (shared by all detectors of the time block, so cache-resident) and
 // one Hamilton product.
-__device__ __forceinline__ void load_tile_quats(const double *qd, int64_t n_det,
-                                                const Tiling &tl, int64_t d0, Quat *tq) {
+template <typename T>
+__device__ __forceinline__ void load_tile_quats(const PtArgs<T> &a, const Tiling &tl, int64_t d0,
+                                                Quat *tq) {
   for (int j = threadIdx.x; j < tl.dets; j += blockDim.x)
-    tq[j] = load_quat(qd, d0 + j < n_det ? d0 + j : 0);
+    tq[j] = load_quat(a.qd, d0 + j < a.n_det ? tile_detector(a, d0 + j) : 0);
 }
 
 // With a HWP and no angle offsets the turn of the polariser weights is by

@@ -84,7 +84,7 @@ k_grad_tile(PtArgs<T> a, const MT *__restrict__ m, int64_t npix, Tiling tl,
   const int32_t log2G = tl.log2ts < 6 ? tl.log2ts : 6;   // group: min(64, tile length) slots
   const int32_t G = 1 << log2G;
   load_tile_consts(a, w_det, tl, d0, t0, tc);
-  if constexpr (QUAT) load_tile_quats(a.qd, a.n_det, tl, d0, tq);
+  if constexpr (QUAT) load_tile_quats(a, tl, d0, tq);
   __syncthreads();
   if constexpr (QUAT) {
     if (a.hwp && !a.dpsi) {
@@ -102,7 +102,7 @@ k_grad_tile(PtArgs<T> a, const MT *__restrict__ m, int64_t npix, Tiling tl,
       Quat qb[KB];
 #pragma unroll
       for (int b = 0; b < KB; ++b) {
-        sl[b] = slot_of(tl, d0, t0, s0 + b * kGradThreads, a.n_det, a.n_samp);
+        sl[b] = slot_of(tl, d0, t0, s0 + b * kGradThreads, a.n_det, a.n_samp, tc.det);
         qb[b] = load_quat(a.qb, t0 + sl[b].il < a.n_samp ? t0 + sl[b].il : 0);
         dv[b] = ld_stream(tod + sl[b].off);
       }
@@ -113,7 +113,7 @@ k_grad_tile(PtArgs<T> a, const MT *__restrict__ m, int64_t npix, Tiling tl,
       T th[KB], ph[KB], ps[KB];
 #pragma unroll
       for (int b = 0; b < KB; ++b) {
-        sl[b] = slot_of(tl, d0, t0, s0 + b * kGradThreads, a.n_det, a.n_samp);
+        sl[b] = slot_of(tl, d0, t0, s0 + b * kGradThreads, a.n_det, a.n_samp, tc.det);
         th[b] = ld_stream(a.theta + sl[b].off);
         ph[b] = ld_stream(a.phi + sl[b].off);
         ps[b] = ld_stream(a.psi + sl[b].off);
@@ -188,8 +188,8 @@ k_grad_tile(PtArgs<T> a, const MT *__restrict__ m, int64_t npix, Tiling tl,
     // detector kl's groups kl * gpd .. (kl + 1) * gpd - 1, summed in order
     const int32_t gpd = 1 << (tl.log2ts - log2G);
     for (int kl = threadIdx.x; kl < tl.dets; kl += kGradThreads) {
-      const int64_t k = d0 + kl;
-      if (k >= a.n_det) continue;
+      if (d0 + kl >= a.n_det) continue;
+      const int64_t k = tc.det[kl];
       double t0s = 0.0, t1s = 0.0;
       for (int j = 0; j < gpd; ++j) {
         t0s += grp[0][kl * gpd + j];

@@ -82,6 +82,28 @@ def test_ang2pix_f32_inputs_and_invalid(fx):
     assert np.all(got[:5] == -1)
 
 
+@pytest.mark.parametrize("nside", [1, 4, 64, 1024, 8192])
+def test_ang2pix_every_fp32_theta_matches_the_fp64_path(fx, nside):
+    """Every FP32 theta in [0, pi] (all 1.08e9 of them, plus the FP32 value just
+    above pi), each with a random FP32 phi: the FP32 path's pixel (a polynomial
+    cosine whose error is guarded against every floor and branch of the ring
+    scheme, with the library cosine as fallback) equals the FP64 path's pixel
+    of the same, exactly promoted, inputs bit for bit.  The FP64 path itself is
+    pinned to the oracle by the tests above."""
+    D = dev()
+    hi = int(np.array([np.pi], dtype=np.float32).view(np.int32)[0])
+    g = torch.Generator(device=D).manual_seed(nside)
+    step = 1 << 27
+    for a in range(0, hi + 1, step):
+        b = min(a + step, hi + 1)
+        th = torch.arange(a, b, dtype=torch.int32, device=D).view(torch.float32)
+        ph = torch.rand(b - a, generator=g, device=D, dtype=torch.float32) * float(2 * np.pi)
+        p32 = fx.ang2pix(nside, th, ph)
+        p64 = fx.ang2pix(nside, th.double(), ph.double())
+        bad = torch.nonzero(p32 != p64).flatten()
+        assert bad.numel() == 0, (nside, th[bad[:4]].tolist(), ph[bad[:4]].tolist())
+
+
 def test_ang2pix_empty(fx):
     e = torch.empty(0, dtype=torch.float64, device=dev())
     assert fx.ang2pix(8, e, e).numel() == 0
