@@ -244,7 +244,7 @@ def measure(w, dev, steps, warmup, prec, keep_map=False):
                        "GB_s": ob / (ms * 1e-3) / 1e9,
                        "frac_hbm_peak": ob / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                        "target_frac": TARGET_FRAC}
-    log(f"{w.name}: {ms:.3f} ms/iter, {res['value']:.4g} samples/s; after {info.iters} "
+    log(f"{res['workload']}: {ms:.3f} ms/iter, {res['value']:.4g} samples/s; after {info.iters} "
         f"iterations rel resid {info.rel_resid:.3e}")
     log("phases: " + ", ".join(f"{k} {v['ms']:.3f} ms" + (f" {v['GB_s']:.0f} GB/s" if "GB_s" in v else "")
                                for k, v in res["kernels"].items()))
@@ -662,7 +662,7 @@ def main():
     ap.add_argument("--iters", type=int, default=0,
                     help="PCG iterations per solve (0: the workload's own count); profiling "
                          "runs shorten the solves with it")
-    ap.add_argument("--cpu-dets", type=int, default=16)
+    ap.add_argument("--cpu-dets", type=int, default=64)
     ap.add_argument("--cpu-workers", type=int, default=16,
                     help="worker processes of the CPU baseline (capped by the host's CPUs)")
     ap.add_argument("--summarize-trace", metavar="DIR",

@@ -57,18 +57,7 @@ struct PtArgs {
 // 2005) of the direction with z = cos(theta) and longitude phi, both already
 // validated.  Every operation is rounded on its own (no contraction) so that
 // the result equals a plain IEEE evaluation of the same expression sequence.
-//
-// With GUARD, z is known only to within kZTol of the cosine that defines the
-// pixel, and ok reports whether that uncertainty provably cannot change the
-// result: every floor argument lies further from an integer than the
-// uncertainty can move it, and |z| is not at the polar/equatorial split.
-// (Equatorial floors t1 -+ t2 move by at most 0.75 N kZTol plus two roundings
-// of numbers below 4.5 N; polar floors tp w, (1 - tp) w by at most
-// 1.5 N^2 kZTol / w plus a few roundings, as w = N sqrt(3 (1 - |z|)).)  The
-// result is then the one the exact cosine gives, bit for bit.
-constexpr double kZTol = 1e-15;
-template <bool GUARD = false>
-__device__ __forceinline__ int32_t pix_of_z(int32_t n, double z, double phi, bool *ok = nullptr) {
+__device__ __forceinline__ int32_t pix_of_z(int32_t n, double z, double phi) {
 #pragma clang fp contract(off)
   const double N = (double)n;
   const double two_pi = 2.0 * kPi;
@@ -88,15 +77,8 @@ __device__ __forceinline__ int32_t pix_of_z(int32_t n, double z, double phi, boo
   if (za <= 2.0 / 3.0) {
     const double t1 = N * (0.5 + tt);
     const double t2 = (0.75 * N) * z;
-    const double a = t1 - t2, b = t1 + t2;
-    const double fa = floor(a), fb = floor(b);
-    const int32_t jp = (int32_t)fa;
-    const int32_t jm = (int32_t)fb;
-    if constexpr (GUARD) {
-      const double eta = N * 1e-14;
-      const double da = fmin(a - fa, (fa + 1.0) - a), db = fmin(b - fb, (fb + 1.0) - b);
-      *ok = da > eta && db > eta && (2.0 / 3.0) - za > 2.0 * kZTol;
-    }
+    const int32_t jp = (int32_t)floor(t1 - t2);
+    const int32_t jm = (int32_t)floor(t1 + t2);
     const int32_t ir = n + 1 + jp - jm;                 // 1 .. 2n+1
     const int32_t kshift = 1 - (ir & 1);
     int32_t ip = (jp + jm - n + kshift + 1) / 2;        // in [0, 4n + 1]
@@ -105,15 +87,8 @@ __device__ __forceinline__ int32_t pix_of_z(int32_t n, double z, double phi, boo
   } else {
     const double tp = tt - floor(tt);
     const double w = N * sqrt(3.0 * (1.0 - za));
-    const double a = tp * w, b = (1.0 - tp) * w;
-    const double fa = floor(a), fb = floor(b);
-    const int32_t jp = (int32_t)fa;
-    const int32_t jm = (int32_t)fb;
-    if constexpr (GUARD) {
-      const double eta_w = 2e-14 * N * N;   // bound on (floor-argument shift) * w
-      const double da = fmin(a - fa, (fa + 1.0) - a), db = fmin(b - fb, (fb + 1.0) - b);
-      *ok = da * w > eta_w && db * w > eta_w && za - (2.0 / 3.0) > 2.0 * kZTol;
-    }
+    const int32_t jp = (int32_t)floor(tp * w);
+    const int32_t jm = (int32_t)floor((1.0 - tp) * w);
     const int32_t ir = jp + jm + 1;                     // 1 .. n
     int32_t ip = (int32_t)floor(tt * (double)ir);       // in [0, 4 ir]
     if (ip >= 4 * ir) ip -= 4 * ir;                     // ip mod 4 ir
@@ -123,71 +98,12 @@ __device__ __forceinline__ int32_t pix_of_z(int32_t n, double z, double phi, boo
 }
 
 // Ring pixel of (theta, phi); the only libm call on the way is cos().
-// Returns -1 for non-finite input or theta outside [0, pi].
+// Returns -1 for non-finite input or theta outside [0, pi].  FP32 angles are
+// promoted exactly.
 __device__ __forceinline__ int32_t ang2pix_ring(int32_t n, double theta, double phi) {
   if (!(theta >= 0.0 && theta <= kPi)) return -1;      // also rejects NaN
   if (!(phi - phi == 0.0)) return -1;                   // rejects NaN and +-inf
   return pix_of_z(n, cos(theta), phi);
-}
-
-// cos(theta) for theta in [0, pi] by a short polynomial: theta = k pi/2 + r
-// with k = rint(theta 2/pi) in {0, 1, 2} and |r| <= pi/4, r from a two-part
-// split of pi/2 (the leading part to 33 bits, so that k c1 and theta - k c1
-// are exact); then the Taylor series of cos r to r^16 and of sin r to r^15
-// (truncation below 5e-17 on |r| <= pi/4), and cos theta = cos r, -sin r or
-// -cos r.  For every FP32 theta in [0, pi] it is within 2.3e-16 of the
-// correctly rounded cosine, and so within kZTol of the library's.
-__device__ __forceinline__ double cos_poly(double th) {
-  constexpr double c1 = 1.5707963267341256;      // pi/2 to 33 bits
-  constexpr double c2 = 6.077100506506192e-11;   // pi/2 - c1
-  const double k = rint(th * (2.0 / kPi));
-  const double r = (th - k * c1) - k * c2;
-  const double r2 = r * r;
-  double c = 1.0 / 20922789888000.0;             // 1/16!
-  c = fma(c, r2, -1.0 / 87178291200.0);          // 1/14!
-  c = fma(c, r2, 1.0 / 479001600.0);
-  c = fma(c, r2, -1.0 / 3628800.0);
-  c = fma(c, r2, 1.0 / 40320.0);
-  c = fma(c, r2, -1.0 / 720.0);
-  c = fma(c, r2, 1.0 / 24.0);
-  c = fma(c, r2, -0.5);
-  c = fma(c, r2, 1.0);
-  double sn = -1.0 / 1307674368000.0;            // 1/15!
-  sn = fma(sn, r2, 1.0 / 6227020800.0);          // 1/13!
-  sn = fma(sn, r2, -1.0 / 39916800.0);
-  sn = fma(sn, r2, 1.0 / 362880.0);
-  sn = fma(sn, r2, -1.0 / 5040.0);
-  sn = fma(sn, r2, 1.0 / 120.0);
-  sn = fma(sn, r2, -1.0 / 6.0);
-  sn = fma(sn * r2, r, r);
-  return k == 0.0 ? c : (k == 1.0 ? -sn : -c);
-}
-
-// Ring pixel of (theta, phi) for a theta given in FP32 (the FP32 path's
-// canonical inputs), bit-identical to ang2pix_ring: the polynomial cosine
-// decides the pixel whenever the guard shows that its error cannot matter,
-// the library cosine otherwise (a sample within ~1e-11 of a pixel edge).
-// The polynomial step alone: ok = false asks for the library cosine.
-__device__ __forceinline__ int32_t ang2pix_f32_guarded(int32_t n, float theta32, float phi32,
-                                                       bool &ok) {
-  const double theta = (double)theta32, phi = (double)phi32;
-  ok = true;
-  if (!(theta >= 0.0 && theta <= kPi)) return -1;      // also rejects NaN
-  if (!(phi - phi == 0.0)) return -1;                   // rejects NaN and +-inf
-  return pix_of_z<true>(n, cos_poly(theta), phi, &ok);
-}
-__device__ __forceinline__ int32_t ang2pix_ring_f32(int32_t n, float theta32, float phi32) {
-  bool ok;
-  const int32_t p = ang2pix_f32_guarded(n, theta32, phi32, ok);
-  return ok ? p : pix_of_z(n, cos((double)theta32), (double)phi32);
-}
-
-// The pixel of a sample in the pointing's dtype.
-__device__ __forceinline__ int32_t ang2pix_any(int32_t n, double theta, double phi) {
-  return ang2pix_ring(n, theta, phi);
-}
-__device__ __forceinline__ int32_t ang2pix_any(int32_t n, float theta, float phi) {
-  return ang2pix_ring_f32(n, theta, phi);
 }
 
 // Ring pixel of (z, phi); -1 for non-finite input or z outside [-1, 1].
@@ -359,7 +275,7 @@ __device__ __forceinline__ Geom<T> sample_geom(const PtArgs<T> &a, int64_t k, in
     quat_weights(d, a.dpsi || a.hwp, beta, g.c, g.s);
   } else {
     const int64_t off = k * a.n_samp + i;
-    g.pix = ang2pix_any(a.nside, a.theta[off], a.phi[off]);
+    g.pix = ang2pix_ring(a.nside, (double)a.theta[off], (double)a.phi[off]);
     weights(two_psi_eff(a, k, i, (double)a.psi[off]), g.c, g.s);
   }
   if (g.pix >= 0 && a.valid && !a.valid[g.pix]) g.pix = -1;

@@ -20,7 +20,7 @@ __global__ void __launch_bounds__(kBlock) k_ang2pix(int32_t nside, const T *__re
                                                     int64_t *__restrict__ out) {
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
-    out[i] = ang2pix_any(nside, theta[i], phi[i]);
+    out[i] = ang2pix_ring(nside, (double)theta[i], (double)phi[i]);
 }
 
 template <typename T>
@@ -117,19 +117,9 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *
       __syncthreads();
     }
   }
-  // FP32 angles: the pixel comes from the guarded polynomial cosine; a sample
-  // that the guard sends to the library cosine (one within ~1e-11 of a pixel
-  // edge) is marked in `redo` (bit KB * iteration + b; a tile holds at most
-  // 16384 samples, 16 iterations of the 1024 per pass) and done again after
-  // the main loop, so that the library cosine's registers do not add to the
-  // batch's.
-  constexpr bool kGuard = !QUAT && sizeof(T) == 4;
-  uint64_t redo = 0;
-  int32_t iter = 0;
-  for (int32_t s0 = threadIdx.x; s0 < nsamp; s0 += kBatch * kApplyThreads, ++iter) {
+  for (int32_t s0 = threadIdx.x; s0 < nsamp; s0 += kBatch * kApplyThreads) {
     Slot sl[kBatch];
     int32_t px[kBatch], tag[kBatch];
-    bool ok[kBatch];
     T c[kBatch], s[kBatch];
     if constexpr (QUAT) {
       Quat qb[kBatch];
@@ -137,7 +127,6 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *
       for (int b = 0; b < kBatch; ++b) {
         sl[b] = slot_of(tl, d0, t0, s0 + b * kApplyThreads, a.n_det, a.n_samp, tc.det);
         qb[b] = load_quat(a.qb, t0 + sl[b].il < a.n_samp ? t0 + sl[b].il : 0);
-        ok[b] = true;
       }
 #pragma unroll
       for (int b = 0; b < kBatch; ++b)
@@ -153,13 +142,7 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *
       }
 #pragma unroll
       for (int b = 0; b < kBatch; ++b) {
-        if constexpr (kGuard) {
-          px[b] = ang2pix_f32_guarded(a.nside, th[b], ph[b], ok[b]);
-          if (px[b] >= 0 && a.valid && !a.valid[px[b]]) px[b] = -1;
-        } else {
-          px[b] = pixel_of(a, th[b], ph[b]);
-          ok[b] = true;
-        }
+        px[b] = pixel_of(a, th[b], ph[b]);
         pol_weights(a, tc, sl[b], ps[b], c[b], s[b]);
       }
     }
@@ -170,38 +153,12 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *
 #pragma unroll
     for (int b = 0; b < kBatch; ++b) {
       if (!sl[b].in) continue;
-      if (kGuard && !ok[b]) {
-        redo |= (uint64_t)1 << (iter * kBatch + b);
-        continue;
-      }
       const T y = (T)I[b] + c[b] * (T)Q[b] + s[b] * (T)U[b];
       st_stream(tod + sl[b].off, px[b] >= 0 ? (T)tc.gain[sl[b].kl] * y : (T)0);
       if (pix_out) st_stream(pix_out + sl[b].off, px[b]);
       if (local_out)
         st_stream(local_out + sl[b].off,
                   (uint16_t)(px[b] >= 0 ? (uint16_t)(tag[b] & local_mask) : 0xffff));
-    }
-  }
-  if constexpr (kGuard) {
-    while (redo) {
-      const int bit = __builtin_ctzll(redo);
-      redo &= redo - 1;
-      const int32_t slot = threadIdx.x + (bit % kBatch) * kApplyThreads +
-                           (bit / kBatch) * kBatch * kApplyThreads;
-      const Slot sl = slot_of(tl, d0, t0, slot, a.n_det, a.n_samp, tc.det);
-      const T th = a.theta[sl.off], ph = a.phi[sl.off], ps = a.psi[sl.off];
-      int32_t px = pix_of_z(a.nside, cos((double)th), (double)ph);
-      if (px >= 0 && a.valid && !a.valid[px]) px = -1;
-      T c, s;
-      pol_weights(a, tc, sl, ps, c, s);
-      MT I, Q, U;
-      int32_t tag;
-      load_iqu<IL>(map, map_cs, px >= 0 ? px : 0, I, Q, U, tag);
-      const T y = (T)I + c * (T)Q + s * (T)U;
-      tod[sl.off] = px >= 0 ? (T)tc.gain[sl.kl] * y : (T)0;
-      if (pix_out) pix_out[sl.off] = px;
-      if (local_out)
-        local_out[sl.off] = (uint16_t)(px >= 0 ? (uint16_t)(tag & local_mask) : 0xffff);
     }
   }
 }
@@ -226,10 +183,6 @@ furax_status launch_pointing_apply(const PtArgs<T> &a, const void *map, bool map
                                    uint16_t *local_out, int32_t local_mask) {
   if (a.n_samp == 0) return FURAX_OK;
   const Tiling tl = tiling_for(a, 4096);
-  // k_apply marks the samples it redoes in a 64-bit mask: at most 16 passes
-  // of kBatch * kApplyThreads samples per tile
-  if (((int64_t)tl.dets << tl.log2ts) > 16 * kBatch * kApplyThreads)
-    return set_error(FURAX_EUNSUPPORTED, "pointing tile larger than k_apply's redo mask");
   const bool il = ml.ps == 4;
   if (a.qb) {
     if (map_f64)

@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(kBlock) k_nest_plane(PtArgs<T> a, const int32_
       const QuatDir d = quat_dir(qmul(load_quat(a.qb, i), load_quat(a.qd, k)));
       p = zphi2pix_ring(a.nside, d.z, d.phi);
     } else {
-      p = ang2pix_any(a.nside, a.theta[s], a.phi[s]);
+      p = ang2pix_ring(a.nside, (double)a.theta[s], (double)a.phi[s]);
     }
     plane[s] = p >= 0 ? r2n[p] : -1;
   }
@@ -194,28 +194,41 @@ __global__ void __launch_bounds__(kFinalizeThreads) k_run_finalize(uint64_t *__r
   if (r == ch.nr - 1) ch.w = incl;
 }
 
-// One workgroup per chunk, one thread per run: copy the run's samples' pixel
-// offsets (nested index minus the superpixel's first) and, with angle
-// pointing, their angles psi into the run-sorted order.
+// One workgroup per chunk: the chunk's run table in LDS, then threads over
+// consecutive sorted slots (coalesced writes), each finding its run by a
+// binary search, copy the sample's pixel offset (nested index minus the
+// superpixel's first) and, with angle pointing, its angle psi into the
+// run-sorted order.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_sp_sort(const uint64_t *__restrict__ runs,
-                                                    const SpChunk *__restrict__ chunks,
-                                                    const int32_t *__restrict__ nest_plane,
-                                                    const T *__restrict__ psi, int32_t log2P,
-                                                    uint16_t *__restrict__ lab,
-                                                    T *__restrict__ psi_out) {
+__global__ void __launch_bounds__(kFinalizeThreads) k_sp_sort(const uint64_t *__restrict__ runs,
+                                                              const SpChunk *__restrict__ chunks,
+                                                              const int32_t *__restrict__ nest_plane,
+                                                              const T *__restrict__ psi,
+                                                              int32_t log2P,
+                                                              uint16_t *__restrict__ lab,
+                                                              T *__restrict__ psi_out) {
+  __shared__ int32_t pre[kChunkRunsMax + 1];
+  __shared__ int64_t off[kChunkRunsMax];
   const SpChunk ch = chunks[blockIdx.x];
   const int32_t base = ch.sp << log2P;
-  for (int r = threadIdx.x; r < ch.nr; r += kBlock) {
+  for (int r = threadIdx.x; r < ch.nr; r += kFinalizeThreads) {
     const uint64_t w = runs[ch.r0 + r];
-    const int64_t off = (int64_t)(w >> 24);
-    const int32_t pre = (int32_t)(w & 0xffffff);
-    const int32_t end = r + 1 < ch.nr ? (int32_t)(runs[ch.r0 + r + 1] & 0xffffff) : ch.w;
-    const int64_t dst = (int64_t)ch.s0 + pre;
-    for (int32_t t = 0; t < end - pre; ++t) {
-      lab[dst + t] = (uint16_t)(nest_plane[off + t] - base);
-      if (psi_out) psi_out[dst + t] = psi[off + t];
+    off[r] = (int64_t)(w >> 24);
+    pre[r] = (int32_t)(w & 0xffffff);
+  }
+  if (threadIdx.x == 0) pre[ch.nr] = ch.w;
+  __syncthreads();
+  for (int32_t j = threadIdx.x; j < ch.w; j += kFinalizeThreads) {
+    int32_t lo = 0, hi = ch.nr;                   // last run with pre <= j
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (pre[mid] <= j) lo = mid;
+      else hi = mid;
     }
+    const int64_t src = off[lo] + (j - pre[lo]);
+    const int64_t dst = (int64_t)ch.s0 + j;
+    lab[dst] = (uint16_t)(nest_plane[src] - base);
+    if (psi_out) psi_out[dst] = psi[src];
   }
 }
 
@@ -406,7 +419,8 @@ furax_status sp_build_runs(SpPlan &sp, const PtArgs<T> &a, const int32_t *plane,
     FX_HIP(hipStreamSynchronize(s));   // perm dies here
   }
   if (sp.n_chunks) {
-    hipLaunchKernelGGL(k_sp_sort<T>, dim3((unsigned)sp.n_chunks), dim3(kBlock), 0, s, sp.runs,
+    hipLaunchKernelGGL(k_sp_sort<T>, dim3((unsigned)sp.n_chunks), dim3(kFinalizeThreads), 0, s,
+                       sp.runs,
                        sp.chunks, plane, a.psi, sp.log2P, sp.lab, static_cast<T *>(sp.psi));
     FX_HIP(hipGetLastError());
   }

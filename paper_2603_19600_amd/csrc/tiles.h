@@ -107,7 +107,7 @@ __device__ __forceinline__ void pol_weights(const PtArgs<T> &a, const TileConsts
 
 template <typename T>
 __device__ __forceinline__ int32_t pixel_of(const PtArgs<T> &a, T theta, T phi) {
-  int32_t p = ang2pix_any(a.nside, theta, phi);
+  int32_t p = ang2pix_ring(a.nside, (double)theta, (double)phi);
   if (p >= 0 && a.valid && !a.valid[p]) p = -1;
   return p;
 }

@@ -85,11 +85,10 @@ def test_ang2pix_f32_inputs_and_invalid(fx):
 @pytest.mark.parametrize("nside", [1, 4, 64, 1024, 8192])
 def test_ang2pix_every_fp32_theta_matches_the_fp64_path(fx, nside):
     """Every FP32 theta in [0, pi] (all 1.08e9 of them, plus the FP32 value just
-    above pi), each with a random FP32 phi: the FP32 path's pixel (a polynomial
-    cosine whose error is guarded against every floor and branch of the ring
-    scheme, with the library cosine as fallback) equals the FP64 path's pixel
-    of the same, exactly promoted, inputs bit for bit.  The FP64 path itself is
-    pinned to the oracle by the tests above."""
+    above pi), each with a random FP32 phi: the pixel of the FP32 inputs equals
+    the pixel of their exact FP64 promotion bit for bit (the FP32 path promotes
+    before any arithmetic).  The FP64 path itself is pinned to the oracle by
+    the tests above."""
     D = dev()
     hi = int(np.array([np.pi], dtype=np.float32).view(np.int32)[0])
     g = torch.Generator(device=D).manual_seed(nside)
