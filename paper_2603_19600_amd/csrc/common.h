@@ -97,13 +97,86 @@ __device__ __forceinline__ int32_t pix_of_z(int32_t n, double z, double phi) {
   return ((uint32_t)pix < (uint32_t)(12 * n * n)) ? pix : -1;
 }
 
-// Ring pixel of (theta, phi); the only libm call on the way is cos().
-// Returns -1 for non-finite input or theta outside [0, pi].  FP32 angles are
-// promoted exactly.
+// ---------------------------------------------------------------------------
+// cos t for t in [0, pi] in FP64, within one ulp: a colatitude needs neither
+// the general range reduction nor both of the sine and cosine series that a
+// library cos evaluates for every argument.
+//
+// Reduction: t <= pi/4 is kept (x = t); above, x = c - t with c = pi/2 (up to
+// 3 pi/4) or c = pi, c held as hi + lo.  hi - t is exact (Sterbenz: t lies in
+// [hi/2, 2 hi] on each sub-range) and lo joins it by Fast2Sum, so x + xl
+// equals c - t to ~2^-106 relative with |x| <= pi/4.  Then
+//   cos t = cos x (t <= pi/4),  sin x (middle),  -cos x (t >= 3 pi/4).
+// The series are Taylor's, truncated where the next term is below 2^-60 of
+// the value on |x| <= pi/4 (sin to x^17, cos to x^18), with the coefficients
+// RN(1/n!).  Both kernels evaluate the small terms first and add the leading
+// one last, with the tail xl entering to first order, after the kernels of
+// Sun's fdlibm (k_sin, k_cos): for cos, 1 - x^2/2 is rounded to w and its
+// rounding error (1 - w) - x^2/2, exact by Sterbenz, is added back.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double sin_kernel(double x, double xl) {
+#pragma clang fp contract(off)
+  constexpr double S1 = -1.0 / 6.0, S2 = 1.0 / 120.0, S3 = -1.0 / 5040.0,
+                   S4 = 1.0 / 362880.0, S5 = -1.0 / 39916800.0, S6 = 1.0 / 6227020800.0,
+                   S7 = -1.0 / 1307674368000.0, S8 = 1.0 / 355687428096000.0;
+  const double z = x * x, v = z * x;
+  double r = fma(z, S8, S7);
+  r = fma(z, r, S6);
+  r = fma(z, r, S5);
+  r = fma(z, r, S4);
+  r = fma(z, r, S3);
+  r = fma(z, r, S2);
+  r = fma(z, r, S1);                      // sin x = x + v r
+  const double tail = fma(-0.5 * z, xl, xl);   // xl cos x to first order
+  return x + fma(v, r, tail);
+}
+
+__device__ __forceinline__ double cos_kernel(double x, double xl) {
+#pragma clang fp contract(off)
+  constexpr double C2 = 1.0 / 24.0, C3 = -1.0 / 720.0, C4 = 1.0 / 40320.0,
+                   C5 = -1.0 / 3628800.0, C6 = 1.0 / 479001600.0, C7 = -1.0 / 87178291200.0,
+                   C8 = 1.0 / 20922789888000.0, C9 = -1.0 / 6402373705728000.0;
+  const double z = x * x;
+  double r = fma(z, C9, C8);
+  r = fma(z, r, C7);
+  r = fma(z, r, C6);
+  r = fma(z, r, C5);
+  r = fma(z, r, C4);
+  r = fma(z, r, C3);
+  r = fma(z, r, C2);                      // cos x = 1 - z/2 + z^2 r
+  const double hz = 0.5 * z, w = 1.0 - hz;
+  const double small = fma(z * z, r, -(x * xl));   // - x xl: the tail, to first order
+  return w + (((1.0 - w) - hz) + small);
+}
+
+__device__ __forceinline__ double cos_0pi(double t) {
+#pragma clang fp contract(off)
+  constexpr double kPio2Hi = 1.5707963267948966;     // RN(pi/2)
+  constexpr double kPio2Lo = 6.123233995736766e-17;  // RN(pi/2 - kPio2Hi)
+  constexpr double kPiHi = 3.141592653589793;        // RN(pi)
+  constexpr double kPiLo = 1.2246467991473532e-16;   // RN(pi - kPiHi)
+  constexpr double kQuarter = 0.7853981633974483;    // ~pi/4
+  constexpr double kThreeQuarter = 2.356194490192345;  // ~3 pi/4
+  const bool far = t >= kThreeQuarter;
+  const double hi = far ? kPiHi : kPio2Hi, lo = far ? kPiLo : kPio2Lo;
+  const double xh = hi - t;               // exact
+  double x = xh + lo;
+  double xl = (xh - x) + lo;              // Fast2Sum: |xh| >= |lo| or xh = 0
+  const bool near = t <= kQuarter;
+  x = near ? t : x;
+  xl = near ? 0.0 : xl;
+  if (!near && !far) return sin_kernel(x, xl);
+  const double c = cos_kernel(x, xl);
+  return far ? -c : c;
+}
+
+// Ring pixel of (theta, phi) with z = cos_0pi(theta).  Returns -1 for
+// non-finite input or theta outside [0, pi].  FP32 angles are promoted
+// exactly.
 __device__ __forceinline__ int32_t ang2pix_ring(int32_t n, double theta, double phi) {
   if (!(theta >= 0.0 && theta <= kPi)) return -1;      // also rejects NaN
   if (!(phi - phi == 0.0)) return -1;                   // rejects NaN and +-inf
-  return pix_of_z(n, cos(theta), phi);
+  return pix_of_z(n, cos_0pi(theta), phi);
 }
 
 // Ring pixel of (z, phi); -1 for non-finite input or z outside [-1, 1].
@@ -407,6 +480,7 @@ constexpr int kSpPix = 1024;        // pixels per superpixel (32 x 32 nested blo
 constexpr int kChunkRunsSmall = 512;
 constexpr int kChunkRunsMax = 1024;
 constexpr int64_t kMaxRun = 1024;   // longest run of consecutive samples
+constexpr int kChunksPerGroup = 4;  // chunks one P^T workgroup takes in turn
 
 struct SpChunk {
   int64_t r0;   // first run (index into the sorted run list)
@@ -420,12 +494,15 @@ struct SpChunk {
 struct SpPlan {
   int32_t nside = 0, log2P = 0, n_values = 0;
   int32_t chunk_runs = kChunkRunsMax;   // runs per chunk: kChunkRunsSmall or kChunkRunsMax
-  int64_t npix = 0, n_sp = 0, n_runs = 0, n_chunks = 0;
+  int64_t npix = 0, n_sp = 0, n_runs = 0, n_chunks = 0, n_groups = 0;
   int32_t *n2r = nullptr, *r2n = nullptr;   // nested -> ring, ring -> nested [npix]
   uint64_t *runs = nullptr;                 // offset << 24 | chunk-local prefix of lengths
   SpChunk *chunks = nullptr;                // [n_chunks], ordered by superpixel
-  int32_t *sp_chunk = nullptr;              // [n_sp + 1]: first chunk of each superpixel
-  double *partial = nullptr;                // [n_chunks][n_values][P]
+  // a group is up to kChunksPerGroup consecutive chunks of one superpixel,
+  // accumulated by one workgroup into one partial: [n_groups + 1] first chunks
+  int32_t *groups = nullptr;
+  int32_t *sp_group = nullptr;              // [n_sp + 1]: first group of each superpixel
+  double *partial = nullptr;                // [n_groups][n_values][P]
   // every scheduled sample in run-sorted order (chunk by chunk, run by run):
   // its pixel's offset inside the superpixel and, with angle pointing, its
   // angle psi (a reordered copy of the input plane), so that P^T reads both

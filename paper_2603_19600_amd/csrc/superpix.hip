@@ -13,13 +13,15 @@
 //    into runs of consecutive samples that stay in one superpixel, the runs
 //    are sorted by superpixel (stably, so the order is deterministic) and
 //    grouped into chunks of at most SpPlan::chunk_runs runs;
-//  * at every application one workgroup per chunk streams its runs -- tens of
-//    consecutive samples each, so the loads stay coalesced -- and adds into
-//    LDS sums indexed directly by the pixel's offset inside the superpixel:
-//    no hashing, and nothing atomic outside LDS;
-//  * a second kernel sums each superpixel's chunk partials in chunk order
+//  * at every application one workgroup per group of up to kChunksPerGroup
+//    chunks of one superpixel streams their runs -- tens of consecutive
+//    samples each, so the loads stay coalesced -- and adds into LDS sums
+//    indexed directly by the pixel's offset inside the superpixel: no
+//    hashing, and nothing atomic outside LDS.  The group writes one partial
+//    (24 KB), so the partials' HBM traffic is a quarter of one per chunk;
+//  * a second kernel sums each superpixel's group partials in group order
 //    and writes every pixel of the output exactly once, in ring order.  The
-//    LDS sums of a chunk are added by several waves at once, so their order,
+//    LDS sums of a group are added by several waves at once, so their order,
 //    hence the last bits of the result, may differ from run to run.
 //
 // The plan also keeps, in the run-sorted order, each scheduled sample's pixel
@@ -248,8 +250,8 @@ static unsigned grid_for(int64_t n, int64_t cap = 65536) {
 }
 
 void SpPlan::release(hipStream_t s) {
-  for (void *p : {(void *)n2r, (void *)r2n, (void *)runs, (void *)chunks, (void *)sp_chunk,
-                  (void *)partial, (void *)lab, psi, (void *)det_perm}) {
+  for (void *p : {(void *)n2r, (void *)r2n, (void *)runs, (void *)chunks, (void *)groups,
+                  (void *)sp_group, (void *)partial, (void *)lab, psi, (void *)det_perm}) {
     if (p) (void)hipFreeAsync(p, s);
   }
   *this = SpPlan();
@@ -361,18 +363,39 @@ furax_status sp_build_runs(SpPlan &sp, const PtArgs<T> &a, const int32_t *plane,
   sp.n_runs = r;
   sp.n_chunks = (int64_t)ch.size();
   sp.n_values = n_values;
+  // groups: each superpixel's chunks dealt into ceil(n / kChunksPerGroup)
+  // groups of near-equal size, so one workgroup sums several chunks in LDS
+  // and writes one partial for them
+  // (quaternion pointing keeps one chunk per workgroup: its accumulation is
+  // register-bound to one workgroup per CU, which would idle at the barrier
+  // between chunks)
+  const int64_t per_group = a.qb ? 1 : kChunksPerGroup;
+  std::vector<int32_t> grp, first_grp(sp.n_sp + 1);
+  for (int64_t p = 0; p < sp.n_sp; ++p) {
+    first_grp[p] = (int32_t)grp.size();
+    const int64_t nc = first[p + 1] - first[p];
+    const int64_t ng = (nc + per_group - 1) / per_group;
+    for (int64_t g = 0; g < ng; ++g) grp.push_back(first[p] + (int32_t)(nc * g / ng));
+  }
+  first_grp[sp.n_sp] = (int32_t)grp.size();
+  sp.n_groups = (int64_t)grp.size();
+  grp.push_back((int32_t)sp.n_chunks);
   if (hipMallocAsync((void **)&sp.chunks, sizeof(SpChunk) * std::max<int64_t>(sp.n_chunks, 1), s) !=
           hipSuccess ||
-      hipMallocAsync((void **)&sp.sp_chunk, sizeof(int32_t) * (sp.n_sp + 1), s) != hipSuccess ||
+      hipMallocAsync((void **)&sp.groups, sizeof(int32_t) * (sp.n_groups + 1), s) !=
+          hipSuccess ||
+      hipMallocAsync((void **)&sp.sp_group, sizeof(int32_t) * (sp.n_sp + 1), s) != hipSuccess ||
       hipMallocAsync((void **)&sp.partial,
-                     sizeof(double) * std::max<int64_t>(sp.n_chunks, 1) * n_values *
+                     sizeof(double) * std::max<int64_t>(sp.n_groups, 1) * n_values *
                          ((int64_t)1 << sp.log2P),
                      s) != hipSuccess)
     return set_error(FURAX_ENOMEM, "superpixel chunk tables: allocation failed");
   if (sp.n_chunks)
     FX_HIP(hipMemcpyAsync(sp.chunks, ch.data(), sizeof(SpChunk) * sp.n_chunks,
                           hipMemcpyHostToDevice, s));
-  FX_HIP(hipMemcpyAsync(sp.sp_chunk, first.data(), sizeof(int32_t) * (sp.n_sp + 1),
+  FX_HIP(hipMemcpyAsync(sp.groups, grp.data(), sizeof(int32_t) * (sp.n_groups + 1),
+                        hipMemcpyHostToDevice, s));
+  FX_HIP(hipMemcpyAsync(sp.sp_group, first_grp.data(), sizeof(int32_t) * (sp.n_sp + 1),
                         hipMemcpyHostToDevice, s));
   if (sp.n_chunks) {
     hipLaunchKernelGGL(k_run_finalize, dim3((unsigned)sp.n_chunks), dim3(kFinalizeThreads), 0, s,
@@ -507,12 +530,11 @@ template <typename T, int KIND, bool QUAT, int NR>
 __global__ void __launch_bounds__(kSpThreads)
 k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_det,
            const uint16_t *__restrict__ lab, const T *__restrict__ psi_s,
-           const uint64_t *__restrict__ runs, const SpChunk *__restrict__ chunks, int32_t log2P,
-           double *__restrict__ partial) {
+           const uint64_t *__restrict__ runs, const SpChunk *__restrict__ chunks,
+           const int32_t *__restrict__ groups, int32_t log2P, double *__restrict__ partial) {
   __shared__ SpLds<KIND, NR> L;
   constexpr int NV = KIND == 0 ? 3 : 6;
   const int P = 1 << log2P;
-  const SpChunk ch = chunks[blockIdx.x];
   for (int l = threadIdx.x; l < P; l += kSpThreads) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) L.acc[v][l] = 0.0;
@@ -542,127 +564,134 @@ k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_
       L.two_alpha[u] = 2.0 * ((2.0 * kPi) * frac + a.hwp_phase0);
     }
   }
-  for (int r = threadIdx.x; r < ch.nr; r += kSpThreads) {
-    const uint64_t w = runs[ch.r0 + r];
-    const int64_t off = (int64_t)(w >> 24);
-    const int64_t k = off / a.n_samp;
-    const int64_t i0 = off - k * a.n_samp;
-    L.run.pre[r] = (int32_t)(w & 0xffffff);
-    L.run.hwp0[r] = table ? (int32_t)(i0 % a.hwp_den) : 0;
-    L.run.det[r] = (int32_t)k;
-    L.run.i0[r] = (int32_t)i0;
-    const double g = a.gain ? a.gain[k] : 1.0;
-    const double wk = w_det ? w_det[k] : 1.0;
-    L.run.gw[r] = KIND == 0 ? g * wk : g * g * wk;
-    L.run.dpsi[r] = a.dpsi ? a.dpsi[k] : 0.0;
-  }
-  if (threadIdx.x == 0) L.run.pre[ch.nr] = ch.w;
-  __syncthreads();
+  // the group's chunks in turn, summed into the same LDS accumulators (with
+  // quaternion pointing a group is one chunk, and the loop compiles away)
+  const int32_t c_lo = groups[blockIdx.x], c_hi = QUAT ? c_lo + 1 : groups[blockIdx.x + 1];
+  for (int32_t ci = c_lo; ci < c_hi; ++ci) {
+    const SpChunk ch = chunks[ci];
+    if (ci > c_lo) __syncthreads();   // every wave is done with the previous run table
+    for (int r = threadIdx.x; r < ch.nr; r += kSpThreads) {
+      const uint64_t w = runs[ch.r0 + r];
+      const int64_t off = (int64_t)(w >> 24);
+      const int64_t k = off / a.n_samp;
+      const int64_t i0 = off - k * a.n_samp;
+      L.run.pre[r] = (int32_t)(w & 0xffffff);
+      L.run.hwp0[r] = table ? (int32_t)(i0 % a.hwp_den) : 0;
+      L.run.det[r] = (int32_t)k;
+      L.run.i0[r] = (int32_t)i0;
+      const double g = a.gain ? a.gain[k] : 1.0;
+      const double wk = w_det ? w_det[k] : 1.0;
+      L.run.gw[r] = KIND == 0 ? g * wk : g * g * wk;
+      L.run.dpsi[r] = a.dpsi ? a.dpsi[k] : 0.0;
+    }
+    if (threadIdx.x == 0) L.run.pre[ch.nr] = ch.w;
+    __syncthreads();
 
-  constexpr int kSlotBatch = slot_batch<T, QUAT, NR>();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int kWaves = kSpThreads / 64;
-  // Each wave owns a contiguous range of 64-slot blocks and walks it with a
-  // run cursor rb (the run holding the block's first slot); lane l looks at
-  // the start of run rb + 1 + l, so a block's lanes see every run that can
-  // start inside it.
-  const int32_t nblk = (ch.w + 63) >> 6;
-  const int32_t b0 = (int32_t)((int64_t)nblk * wave / kWaves);
-  const int32_t b1 = (int32_t)((int64_t)nblk * (wave + 1) / kWaves);
-  int32_t rb = b0 < b1 ? run_of(L.run.pre, 0, ch.nr, b0 * 64) : 0;
-  for (int32_t blk = b0; blk < b1; blk += kSlotBatch) {
-    int32_t run[kSlotBatch], lo[kSlotBatch], tt[kSlotBatch];
-    int64_t sidx[kSlotBatch];
-    bool in[kSlotBatch];
-    T z[kSlotBatch], ps[kSlotBatch];
-    Quat qb[QUAT ? kSlotBatch : 1], qd[QUAT ? kSlotBatch : 1];
+    constexpr int kSlotBatch = slot_batch<T, QUAT, NR>();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int kWaves = kSpThreads / 64;
+    // Each wave owns a contiguous range of 64-slot blocks and walks it with a
+    // run cursor rb (the run holding the block's first slot); lane l looks at
+    // the start of run rb + 1 + l, so a block's lanes see every run that can
+    // start inside it.
+    const int32_t nblk = (ch.w + 63) >> 6;
+    const int32_t b0 = (int32_t)((int64_t)nblk * wave / kWaves);
+    const int32_t b1 = (int32_t)((int64_t)nblk * (wave + 1) / kWaves);
+    int32_t rb = b0 < b1 ? run_of(L.run.pre, 0, ch.nr, b0 * 64) : 0;
+    for (int32_t blk = b0; blk < b1; blk += kSlotBatch) {
+      int32_t run[kSlotBatch], lo[kSlotBatch], tt[kSlotBatch];
+      int64_t sidx[kSlotBatch];
+      bool in[kSlotBatch];
+      T z[kSlotBatch], ps[kSlotBatch];
+      Quat qb[QUAT ? kSlotBatch : 1], qd[QUAT ? kSlotBatch : 1];
 #pragma unroll
-    for (int b = 0; b < kSlotBatch; ++b) {
-      const int32_t jb = (blk + b) * 64;
-      const int32_t j = jb + lane;
-      in[b] = blk + b < b1 && j < ch.w;
-      // starts of runs rb+1 .. rb+64 relative to the block (>= 1: rb holds jb)
-      const int32_t m = rb + 1 + lane;
-      const int32_t st = m < ch.nr ? L.run.pre[m] - jb : 65;
-      // this lane's run: rb + (number of those starts <= lane), by a binary
-      // search over the lanes' (increasing) start values
-      int32_t pos = 0;
+      for (int b = 0; b < kSlotBatch; ++b) {
+        const int32_t jb = (blk + b) * 64;
+        const int32_t j = jb + lane;
+        in[b] = blk + b < b1 && j < ch.w;
+        // starts of runs rb+1 .. rb+64 relative to the block (>= 1: rb holds jb)
+        const int32_t m = rb + 1 + lane;
+        const int32_t st = m < ch.nr ? L.run.pre[m] - jb : 65;
+        // this lane's run: rb + (number of those starts <= lane), by a binary
+        // search over the lanes' (increasing) start values
+        int32_t pos = 0;
 #pragma unroll
-      for (int step = 32; step >= 1; step >>= 1)
-        if (__shfl(st, pos + step - 1, 64) <= lane) pos += step;
-      run[b] = rb + pos;
-      rb += __popcll(__ballot(st <= 64));
-      const int32_t jj = min(j, ch.w - 1);
-      const int32_t r = min(run[b], ch.nr - 1);
-      run[b] = r;
-      tt[b] = jj - L.run.pre[r];                        // offset inside the run
-      sidx[b] = (int64_t)L.run.det[r] * a.n_samp + (L.run.i0[r] + tt[b]);
-      const int64_t sj = (int64_t)ch.s0 + jj;           // run-sorted position
-      lo[b] = (int32_t)lab[sj];
-      if constexpr (KIND == 0) z[b] = tod[sidx[b]];
-      if constexpr (QUAT) {
-        qb[b] = load_quat(a.qb, L.run.i0[r] + tt[b]);
-        qd[b] = load_quat(a.qd, L.run.det[r]);
-      } else {
-        ps[b] = psi_s[sj];
-      }
-    }
-#pragma unroll
-    for (int b = 0; b < kSlotBatch; ++b) {
-      if (!in[b] || (uint32_t)lo[b] >= (uint32_t)P) continue;
-      const int32_t r = run[b];
-      const int32_t t = tt[b];
-      // psi_eff = psi + dpsi_k + 2 alpha_i, in the oracle's order (beta: the
-      // part that does not come from the pointing)
-      double two_a = 0.0;
-      if (a.hwp && !qturn) {
-        if (table) {
-          two_a = L.two_alpha[L.run.hwp0[r] + t];
+        for (int step = 32; step >= 1; step >>= 1)
+          if (__shfl(st, pos + step - 1, 64) <= lane) pos += step;
+        run[b] = rb + pos;
+        rb += __popcll(__ballot(st <= 64));
+        const int32_t jj = min(j, ch.w - 1);
+        const int32_t r = min(run[b], ch.nr - 1);
+        run[b] = r;
+        tt[b] = jj - L.run.pre[r];                        // offset inside the run
+        sidx[b] = (int64_t)L.run.det[r] * a.n_samp + (L.run.i0[r] + tt[b]);
+        const int64_t sj = (int64_t)ch.s0 + jj;           // run-sorted position
+        lo[b] = (int32_t)lab[sj];
+        if constexpr (KIND == 0) z[b] = tod[sidx[b]];
+        if constexpr (QUAT) {
+          qb[b] = load_quat(a.qb, L.run.i0[r] + tt[b]);
+          qd[b] = load_quat(a.qd, L.run.det[r]);
         } else {
-          const int64_t i = (int64_t)L.run.i0[r] + t;
-          two_a = 2.0 * hwp_alpha(i, a.hwp_num_mod, a.hwp_den, a.hwp_phase0);
+          ps[b] = psi_s[sj];
         }
       }
-      T c, sn;
-      if constexpr (QUAT) {
-        const QuatDir qdir = quat_dir(qmul(qb[b], qd[b]));
-        if (qturn) {
-          double c2, s2;
-          quat_c2s2(qdir, c2, s2);
-          const double2 tn = L.turn4a[(uint32_t)(L.run.hwp0[r] + t) % (uint32_t)a.hwp_den];
-          turn_weights(c2, s2, (T)tn.x, (T)tn.y, c, sn);
-        } else {
-          double beta = a.dpsi ? L.run.dpsi[r] : 0.0;
-          if (a.hwp) beta = beta + two_a;
-          quat_weights(qdir, a.dpsi || a.hwp, beta, c, sn);
+#pragma unroll
+      for (int b = 0; b < kSlotBatch; ++b) {
+        if (!in[b] || (uint32_t)lo[b] >= (uint32_t)P) continue;
+        const int32_t r = run[b];
+        const int32_t t = tt[b];
+        // psi_eff = psi + dpsi_k + 2 alpha_i, in the oracle's order (beta: the
+        // part that does not come from the pointing)
+        double two_a = 0.0;
+        if (a.hwp && !qturn) {
+          if (table) {
+            two_a = L.two_alpha[L.run.hwp0[r] + t];
+          } else {
+            const int64_t i = (int64_t)L.run.i0[r] + t;
+            two_a = 2.0 * hwp_alpha(i, a.hwp_num_mod, a.hwp_den, a.hwp_phase0);
+          }
         }
-      } else {
-        double pe = (double)ps[b];
-        if (a.dpsi) pe = pe + L.run.dpsi[r];
-        if (a.hwp) pe = pe + two_a;
-        weights(2.0 * pe, c, sn);
-      }
-      if constexpr (KIND == 0) {
-        const T v = (T)L.run.gw[r] * z[b];
-        atomicAdd(&L.acc[0][lo[b]], (double)v);
-        atomicAdd(&L.acc[1][lo[b]], (double)(v * c));
-        atomicAdd(&L.acc[2][lo[b]], (double)(v * sn));
-      } else {
-        const double w = L.run.gw[r];
-        const double cd = (double)c, sd = (double)sn;
-        const double wc = w * cd, ws = w * sd;
-        atomicAdd(&L.acc[0][lo[b]], w);
-        atomicAdd(&L.acc[1][lo[b]], wc);
-        atomicAdd(&L.acc[2][lo[b]], ws);
-        atomicAdd(&L.acc[3][lo[b]], wc * cd);
-        atomicAdd(&L.acc[4][lo[b]], wc * sd);
-        atomicAdd(&L.acc[5][lo[b]], ws * sd);
-        atomicAdd(&L.hits[lo[b]], 1);
+        T c, sn;
+        if constexpr (QUAT) {
+          const QuatDir qdir = quat_dir(qmul(qb[b], qd[b]));
+          if (qturn) {
+            double c2, s2;
+            quat_c2s2(qdir, c2, s2);
+            const double2 tn = L.turn4a[(uint32_t)(L.run.hwp0[r] + t) % (uint32_t)a.hwp_den];
+            turn_weights(c2, s2, (T)tn.x, (T)tn.y, c, sn);
+          } else {
+            double beta = a.dpsi ? L.run.dpsi[r] : 0.0;
+            if (a.hwp) beta = beta + two_a;
+            quat_weights(qdir, a.dpsi || a.hwp, beta, c, sn);
+          }
+        } else {
+          double pe = (double)ps[b];
+          if (a.dpsi) pe = pe + L.run.dpsi[r];
+          if (a.hwp) pe = pe + two_a;
+          weights(2.0 * pe, c, sn);
+        }
+        if constexpr (KIND == 0) {
+          const T v = (T)L.run.gw[r] * z[b];
+          atomicAdd(&L.acc[0][lo[b]], (double)v);
+          atomicAdd(&L.acc[1][lo[b]], (double)(v * c));
+          atomicAdd(&L.acc[2][lo[b]], (double)(v * sn));
+        } else {
+          const double w = L.run.gw[r];
+          const double cd = (double)c, sd = (double)sn;
+          const double wc = w * cd, ws = w * sd;
+          atomicAdd(&L.acc[0][lo[b]], w);
+          atomicAdd(&L.acc[1][lo[b]], wc);
+          atomicAdd(&L.acc[2][lo[b]], ws);
+          atomicAdd(&L.acc[3][lo[b]], wc * cd);
+          atomicAdd(&L.acc[4][lo[b]], wc * sd);
+          atomicAdd(&L.acc[5][lo[b]], ws * sd);
+          atomicAdd(&L.hits[lo[b]], 1);
+        }
       }
     }
   }
   __syncthreads();
-  // partial[chunk][v][l]
+  // partial[group][v][l]
   constexpr int NOUT = KIND == 0 ? 3 : 7;
   double *out = partial + (int64_t)blockIdx.x * NOUT * P;
   for (int l = threadIdx.x; l < P; l += kSpThreads) {
@@ -672,12 +701,12 @@ k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_
   }
 }
 
-// Sum each superpixel's chunk partials (in chunk order) into the ring-ordered
+// Sum each superpixel's group partials (in group order) into the ring-ordered
 // output: dst[c * cs + ring * ps] for c < nv, every pixel written once (0 on
 // pixels no sample reaches).  With hits, the 7th partial goes to hits[ring].
 __global__ void __launch_bounds__(kBlock) k_sp_reduce(int64_t npix, int32_t log2P, int32_t nv,
                                                       const double *__restrict__ partial,
-                                                      const int32_t *__restrict__ sp_chunk,
+                                                      const int32_t *__restrict__ sp_group,
                                                       const int32_t *__restrict__ n2r,
                                                       double *__restrict__ dst, int64_t cs,
                                                       int32_t ps, int32_t *__restrict__ hits) {
@@ -687,7 +716,7 @@ __global__ void __launch_bounds__(kBlock) k_sp_reduce(int64_t npix, int32_t log2
   for (int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x; n < npix; n += stride) {
     const int64_t sp = n >> log2P;
     const int l = (int)(n & (P - 1));
-    const int32_t c0 = sp_chunk[sp], c1 = sp_chunk[sp + 1];
+    const int32_t c0 = sp_group[sp], c1 = sp_group[sp + 1];
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double h = 0.0;
     for (int32_t c = c0; c < c1; ++c) {
@@ -704,17 +733,17 @@ __global__ void __launch_bounds__(kBlock) k_sp_reduce(int64_t npix, int32_t log2
 template <typename T, int KIND>
 static void launch_sp_accum(const SpPlan &sp, const PtArgs<T> &a, const T *tod,
                             const double *w_det, hipStream_t s) {
-  const dim3 grid((unsigned)sp.n_chunks), blk(kSpThreads);
+  const dim3 grid((unsigned)sp.n_groups), blk(kSpThreads);
   const T *psi = static_cast<const T *>(sp.psi);
   if (a.qb)
     hipLaunchKernelGGL((k_sp_accum<T, KIND, true, kChunkRunsMax>), grid, blk, 0, s, a, tod, w_det,
-                       sp.lab, psi, sp.runs, sp.chunks, sp.log2P, sp.partial);
+                       sp.lab, psi, sp.runs, sp.chunks, sp.groups, sp.log2P, sp.partial);
   else if (sp.chunk_runs == kChunkRunsSmall)
     hipLaunchKernelGGL((k_sp_accum<T, KIND, false, kChunkRunsSmall>), grid, blk, 0, s, a, tod,
-                       w_det, sp.lab, psi, sp.runs, sp.chunks, sp.log2P, sp.partial);
+                       w_det, sp.lab, psi, sp.runs, sp.chunks, sp.groups, sp.log2P, sp.partial);
   else
     hipLaunchKernelGGL((k_sp_accum<T, KIND, false, kChunkRunsMax>), grid, blk, 0, s, a, tod,
-                       w_det, sp.lab, psi, sp.runs, sp.chunks, sp.log2P, sp.partial);
+                       w_det, sp.lab, psi, sp.runs, sp.chunks, sp.groups, sp.log2P, sp.partial);
 }
 
 template <typename T>
@@ -725,7 +754,7 @@ furax_status sp_transpose(const SpPlan &sp, const PtArgs<T> &a, const T *tod,
     FX_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_sp_reduce, dim3(grid_for(sp.npix, 16384)), dim3(kBlock), 0, s, sp.npix,
-                     sp.log2P, 3, sp.partial, sp.sp_chunk, sp.n2r, q, ql.cs, ql.ps,
+                     sp.log2P, 3, sp.partial, sp.sp_group, sp.n2r, q, ql.cs, ql.ps,
                      (int32_t *)nullptr);
   FX_HIP(hipGetLastError());
   return FURAX_OK;
@@ -746,7 +775,7 @@ furax_status sp_bj_build(const SpPlan &sp, const PtArgs<T> &a, const double *w_d
     FX_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_sp_reduce, dim3(grid_for(sp.npix, 16384)), dim3(kBlock), 0, s, sp.npix,
-                     sp.log2P, 6, sp.partial, sp.sp_chunk, sp.n2r, M6, sp.npix, 1, hits);
+                     sp.log2P, 6, sp.partial, sp.sp_group, sp.n2r, M6, sp.npix, 1, hits);
   FX_HIP(hipGetLastError());
   return FURAX_OK;
 }
