@@ -33,13 +33,22 @@ struct PcgScalars {
 __device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v - v == 0.0; }
 
 // partial[block] = this block's share of <p, q>, p planar [3][npix], q interleaved [npix][4].
+//
+// The vector passes touch valid pixels only.  On the others x, r, z and p are
+// 0 from the initialisation on and stay 0 (p = 0 there gives <p, q> nothing),
+// and in ring order the unobserved pixels come in long stretches, so whole
+// waves skip their loads and stores: the passes move the observed part of the
+// sky instead of all of it.
 __global__ void __launch_bounds__(kBlock) k_dot_pq(int64_t npix, const double *__restrict__ p,
                                                    const double *__restrict__ q,
+                                                   const uint8_t *__restrict__ valid,
                                                    double *__restrict__ partial) {
   double v[1] = {0.0};
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npix; i += stride)
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npix; i += stride) {
+    if (!valid[i]) continue;
     v[0] += p[i] * q[4 * i] + p[npix + i] * q[4 * i + 1] + p[2 * npix + i] * q[4 * i + 2];
+  }
   block_sum<1>(v, partial + blockIdx.x, kRedBlocks);
 }
 
@@ -74,8 +83,9 @@ __global__ void __launch_bounds__(kBlock) k_pq_final(const double *__restrict__ 
 // x += alpha p; r -= alpha q (q interleaved); z = Minv r; partials of <r,z> and <r,r>.
 // The operator kernels do not flag samples of invalid pixels; q there holds
 // contributions that flagging would have dropped, so r is kept at 0 on invalid
-// pixels (p, z and Minv are 0 there, so the valid pixels see exactly the
-// flagged operator).
+// pixels -- they are skipped, and x, r, z keep the 0 of the initialisation
+// (p, z and Minv are 0 there, so the valid pixels see exactly the flagged
+// operator).
 __global__ void __launch_bounds__(kBlock) k_update1(int64_t npix, double *__restrict__ x,
                                                     double *__restrict__ r,
                                                     const double *__restrict__ p,
@@ -90,13 +100,13 @@ __global__ void __launch_bounds__(kBlock) k_update1(int64_t npix, double *__rest
   double v[2] = {0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npix; i += stride) {
+    if (!valid[i]) continue;
     double rr[3];
-    const bool ok = valid[i] != 0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int64_t j = c * npix + i;
       x[j] = x[j] + alpha * p[j];
-      rr[c] = ok ? r[j] - alpha * q[4 * i + c] : 0.0;
+      rr[c] = r[j] - alpha * q[4 * i + c];
       r[j] = rr[c];
     }
     const double a = Mi[i], b = Mi[npix + i], cc = Mi[2 * npix + i];
@@ -134,16 +144,19 @@ __global__ void __launch_bounds__(kBlock) k_rz_final(const double *__restrict__ 
   }
 }
 
-// p = z + beta p, and its interleaved gather copy pg in the path's precision.
+// p = z + beta p, and its interleaved gather copy pg in the path's precision
+// (valid pixels; p and pg stay 0 on the others).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_update2(int64_t npix, double *__restrict__ p,
                                                     const double *__restrict__ z,
                                                     T *__restrict__ pg,
+                                                    const uint8_t *__restrict__ valid,
                                                     const PcgScalars *__restrict__ sc) {
   if (sc->stop) return;
   const double beta = sc->beta;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npix; i += stride) {
+    if (!valid[i]) continue;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const double v = z[c * npix + i] + beta * p[c * npix + i];
@@ -597,14 +610,14 @@ static furax_status pcg_step(furax_pcg_state *h) {
   }
   FX_TRY(normal_run<T>(pl, static_cast<const T *>(h->pg), h->q, s, ev));
   hipLaunchKernelGGL(k_dot_pq, dim3((unsigned)kRedBlocks), dim3(kBlock), 0, s, h->npix, h->p, h->q,
-                     h->partial);
+                     h->valid, h->partial);
   hipLaunchKernelGGL(k_pq_final, dim3(1), dim3(kBlock), 0, s, h->partial, h->sc);
   hipLaunchKernelGGL(k_update1, dim3((unsigned)kRedBlocks), dim3(kBlock), 0, s, h->npix, h->x,
                      h->r, h->p, h->q, h->Minv, h->valid, h->z, h->sc, h->partial);
   hipLaunchKernelGGL(k_rz_final, dim3(1), dim3(kBlock), 0, s, h->partial, h->sc, h->hist,
                      h->nhist);
   hipLaunchKernelGGL(k_update2<T>, dim3((unsigned)map_blocks(h->npix)), dim3(kBlock), 0, s,
-                     h->npix, h->p, h->z, static_cast<T *>(h->pg), h->sc);
+                     h->npix, h->p, h->z, static_cast<T *>(h->pg), h->valid, h->sc);
   FX_HIP(hipGetLastError());
   return mark(ev, 4, s);
 }
