@@ -238,11 +238,11 @@ def test_band_noise_full_stream(fx, dtype, b, wl, tol):
     assert rel_err(got, ref) <= tol
 
 
-@pytest.mark.parametrize("b", [2500, 3000, 4096])
+@pytest.mark.parametrize("b", [2500, 3000, 4096, 6000, 8192])
 @pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-12), (np.float32, 2e-6)])
 def test_band_noise_per_detector_long_kernels(fx, dtype, tol, b):
     """Per-detector lags wide enough for the register-resident blocks (8192-
-    and 16384-point packed transforms)."""
+    and 16384-point packed transforms), up to the widest band."""
     rng = np.random.default_rng(3)
     y = rng.standard_normal((3, 30001)).astype(dtype)
     base = synth.toeplitz_lags(synth.WORKLOADS[2], b)
