@@ -545,8 +545,43 @@ def summarize_trace(db_dir, out, command, title):
         lines.append(f"| `{_short_kernel(r[0])}` | {r[1]} | {r[2] / 1000:.1f} | {r[3] / 1000:.1f} | "
                      f"{r[4] / 1000:.1f} | {r[5] / 1000:.1f} | {r[6]} | {r[7]} | {r[8]} | {r[9]} | "
                      f"{r[10]} | {r[11]} | {r[12]} |")
+    lines += _marker_summary(db_dir)
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
+
+
+def _marker_summary(db_dir):
+    """Host-side roctx ranges (P, N^-1, P^T, pcg_iteration, pcg_update) of a
+    run taken with --marker-trace: count and mean duration per name, from the
+    first table of the database whose name mentions regions or markers and
+    that has name and start/end columns."""
+    import sqlite3
+
+    agg = {}
+    for db in _rocpd_dbs(db_dir):
+        con = sqlite3.connect(db)
+        names = [r[0] for r in con.execute(
+            "select name from sqlite_master where type in ('table', 'view')")]
+        for t in names:
+            if "region" not in t.lower() and "marker" not in t.lower():
+                continue
+            cols = [r[1] for r in con.execute(f"pragma table_info('{t}')")]
+            if not {"name", "start", "end"} <= set(cols):
+                continue
+            for name, n, tot in con.execute(
+                    f"select name, count(*), sum(\"end\" - start) from '{t}' group by name"):
+                if name in ("P", "N^-1", "P^T", "pcg_iteration", "pcg_update"):
+                    a = agg.setdefault(name, [0, 0.0])
+                    a[0] += n
+                    a[1] += tot
+            break
+    if not agg:
+        return []
+    out = ["", "Host-side roctx ranges (enqueue time on the host thread, not GPU time):", "",
+           "| range | count | mean us |", "|---|---|---|"]
+    for name, (n, tot) in sorted(agg.items()):
+        out.append(f"| `{name}` | {n} | {tot / max(n, 1) / 1000:.1f} |")
+    return out
 
 
 def traffic_record(dirs, out, commands):

@@ -11,6 +11,8 @@
 #include <cstring>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "common.h"
 #include "reduce.h"
 
@@ -320,6 +322,16 @@ struct PhaseEvents {
   hipEvent_t e[5];
 };
 
+// A named range for the profiler's marker trace (rocprofv3 --marker-trace)
+// around the host code that enqueues one PCG iteration or one phase of the
+// operator; the calls do nothing unless a tool listens.
+struct Range {
+  explicit Range(const char *name) { roctxRangePush(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range &) = delete;
+  Range &operator=(const Range &) = delete;
+};
+
 static furax_status mark(const PhaseEvents *ev, int i, hipStream_t s) {
   if (ev) FX_HIP(hipEventRecord(ev->e[i], s));
   return FURAX_OK;
@@ -344,11 +356,20 @@ static furax_status normal_run(const NormalPlan<T> &pl, const T *pg, double *q, 
   T *y = reinterpret_cast<T *>(pl.work + pl.L.y);
   T *z = reinterpret_cast<T *>(pl.work + pl.L.z);
   if (pl.use_sp) {
-    FX_TRY(launch_pointing_apply<T>(pl.a, pg, f64, kInterleaved, y, s));
+    {
+      Range r("P");
+      FX_TRY(launch_pointing_apply<T>(pl.a, pg, f64, kInterleaved, y, s));
+    }
     FX_TRY(mark(ev, 1, s));
-    FX_TRY(noise_run<T>(pl.N, y, z, pl.work + pl.L.spec, s));
+    {
+      Range r("N^-1");
+      FX_TRY(noise_run<T>(pl.N, y, z, pl.work + pl.L.spec, s));
+    }
     FX_TRY(mark(ev, 2, s));
-    FX_TRY(sp_transpose<T>(pl.sp, pl.a, z, nullptr, q, kInterleaved, s));
+    {
+      Range r("P^T");
+      FX_TRY(sp_transpose<T>(pl.sp, pl.a, z, nullptr, q, kInterleaved, s));
+    }
     return mark(ev, 3, s);
   }
   int32_t *pix = reinterpret_cast<int32_t *>(pl.work + pl.L.gpix);
@@ -608,7 +629,9 @@ static furax_status pcg_step(furax_pcg_state *h) {
     }
     ev = &h->events[h->n_timed++];
   }
+  Range it("pcg_iteration");
   FX_TRY(normal_run<T>(pl, static_cast<const T *>(h->pg), h->q, s, ev));
+  Range up("pcg_update");
   hipLaunchKernelGGL(k_dot_pq, dim3((unsigned)kRedBlocks), dim3(kBlock), 0, s, h->npix, h->p, h->q,
                      h->valid, h->partial);
   hipLaunchKernelGGL(k_pq_final, dim3(1), dim3(kBlock), 0, s, h->partial, h->sc);
