@@ -552,35 +552,37 @@ def summarize_trace(db_dir, out, command, title):
 
 def _marker_summary(db_dir):
     """Host-side roctx ranges (P, N^-1, P^T, pcg_iteration, pcg_update) of a
-    run taken with --marker-trace: count and mean duration per name, from the
-    first table of the database whose name mentions regions or markers and
-    that has name and start/end columns."""
+    run taken with --marker-trace: count and mean duration per range.  The
+    database records each range as a region of the roctx API with its
+    message in the region's extdata (JSON)."""
     import sqlite3
 
+    wanted = ("pcg_iteration", "P", "N^-1", "P^T", "pcg_update")
     agg = {}
     for db in _rocpd_dbs(db_dir):
         con = sqlite3.connect(db)
-        names = [r[0] for r in con.execute(
-            "select name from sqlite_master where type in ('table', 'view')")]
-        for t in names:
-            if "region" not in t.lower() and "marker" not in t.lower():
+        try:
+            rows = list(con.execute(
+                "select extdata, \"end\" - start from regions where name like 'roctx%'"))
+        except sqlite3.Error:
+            continue
+        for ext, dur in rows:
+            try:
+                name = json.loads(ext or "{}").get("message")
+            except ValueError:
                 continue
-            cols = [r[1] for r in con.execute(f"pragma table_info('{t}')")]
-            if not {"name", "start", "end"} <= set(cols):
-                continue
-            for name, n, tot in con.execute(
-                    f"select name, count(*), sum(\"end\" - start) from '{t}' group by name"):
-                if name in ("P", "N^-1", "P^T", "pcg_iteration", "pcg_update"):
-                    a = agg.setdefault(name, [0, 0.0])
-                    a[0] += n
-                    a[1] += tot
-            break
+            if name in wanted:
+                a = agg.setdefault(name, [0, 0.0])
+                a[0] += 1
+                a[1] += dur
     if not agg:
         return []
-    out = ["", "Host-side roctx ranges (enqueue time on the host thread, not GPU time):", "",
-           "| range | count | mean us |", "|---|---|---|"]
-    for name, (n, tot) in sorted(agg.items()):
-        out.append(f"| `{name}` | {n} | {tot / max(n, 1) / 1000:.1f} |")
+    out = ["", "Host-side roctx ranges (time to enqueue each phase on the host thread, not GPU "
+           "time):", "", "| range | count | mean us |", "|---|---|---|"]
+    for name in wanted:
+        if name in agg:
+            n, tot = agg[name]
+            out.append(f"| `{name}` | {n} | {tot / max(n, 1) / 1000:.1f} |")
     return out
 
 
