@@ -212,3 +212,53 @@ def test_chi2_and_vjp_match_oracle(fx, dtype):
     assert rel_err(-2 * gmap.cpu().numpy(), gm) <= tol
     assert rel_err(-2 * ggain.cpu().numpy(), gg) <= tol
     assert rel_err(-2 * gdpsi.cpu().numpy(), gd) <= (tol if dtype == "f64" else 1e-5)
+
+
+def _patch_scan(n_det, n_samp, seed):
+    """A raster over a ~5 degree patch at nside 1024 (the 1.8 degree 32 x 32
+    superpixels crossed every ~30 samples): a dozen or so superpixels each
+    hold tens of thousands of short runs -- dozens of chunks, and several
+    chunk groups, per superpixel."""
+    rng = np.random.default_rng(seed)
+    t = np.arange(n_samp, dtype=np.float64)
+    th0, ph0 = 1.1, 2.3
+    dth = np.deg2rad(rng.uniform(-0.3, 0.3, n_det))[:, None]
+    dph = np.deg2rad(rng.uniform(-0.3, 0.3, n_det))[:, None]
+    theta = th0 + dth + np.deg2rad(2.5) * np.sin(2 * np.pi * t / 5003.0)[None, :]
+    phi = ph0 + dph + np.deg2rad(5.0) * ((t * 0.0113) % 1.0)[None, :]
+    psi = rng.uniform(-np.pi, np.pi, (n_det, n_samp))
+    return theta, phi, psi
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_normal_apply_with_many_chunk_groups_per_superpixel(fx, dtype):
+    """The superpixel P^T sums a superpixel's chunks in groups, one partial per
+    group, and the reduction adds the groups: a dense patch scan puts dozens of
+    chunks in each superpixel; A x must still equal the oracle's."""
+    nside, nd, ns, b = 1024, 64, 150_000, 33
+    theta, phi, psi = _patch_scan(nd, ns, 5)
+    if dtype == "f32":
+        theta, phi, psi = (a.astype(np.float32).astype(np.float64) for a in (theta, phi, psi))
+    w = synth.WORKLOADS[2].with_(nside=nside, n_det=nd, n_samp=ns)
+    lags = synth.toeplitz_lags(w, b)
+    hwp = (w.hwp_num, w.hwp_den, 0.3)
+    prob = omm.Problem(nside, theta, phi, psi, "band", lags=lags, hwp=hwp)
+    pix, c, s = prob.geometry()
+    npix = 12 * nside * nside
+    hit = np.unique(pix[pix >= 0])
+    # 9.6e6 samples on a patch of < 2e4 pixels (~20 superpixels' worth):
+    # every superpixel holds thousands of runs of a few tens of samples
+    assert hit.size < 20_000 and pix.min() >= 0
+    D = dev()
+    tt = torch.float32 if dtype == "f32" else torch.float64
+    P = fx.Pointing(nside, torch.from_numpy(theta).to(D, tt).contiguous(),
+                    torch.from_numpy(phi).to(D, tt).contiguous(),
+                    torch.from_numpy(psi).to(D, tt).contiguous(), hwp=hwp)
+    N = fx.Noise("band", nd, ns, lags=torch.from_numpy(lags).to(D))
+    rng = np.random.default_rng(11)
+    x = np.zeros((3, npix))
+    x[:, hit] = rng.standard_normal((3, hit.size))
+    got = fx.normal_apply(P, N, torch.from_numpy(x).to(D)).cpu().numpy()
+    ref = omm.normal_apply(prob, pix, c, s, x)
+    assert rel_err(got, ref) <= (1e-12 if dtype == "f64" else 2e-5)
+
