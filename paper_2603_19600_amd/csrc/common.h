@@ -552,6 +552,28 @@ furax_status noise_prepare(const furax_noise *N, void *spec, hipStream_t s);
 template <typename T>
 furax_status noise_run(const furax_noise *N, const T *in, T *out, const void *spec,
                        hipStream_t s);
+// Gap-fill CG work carried by the overlap-save kernel for 32768-sample FP64
+// blocks (noise_run_gap): the new direction p = r / c0_k + beta_k p_prev is
+// formed as each block loads its input -- the transform's input -- and
+// written to p_next on the block's valid outputs, and each block adds its
+// share of p . (mask N p) after its output.  Per-detector scalars are read
+// with a stride (in doubles) from the solver's per-detector records.
+struct GapFuse {
+  const double *r;        // [n_det][n]: residual, 0 on missing samples
+  double *p_next;         // [n_det][n]
+  const uint8_t *gaps;    // [n_det][n]: 1 on missing samples
+  const double *inv_c0;   // inv_c0[k * stride]
+  const double *beta;     // beta[k * stride]
+  int64_t stride;
+  double *partial;        // [n_det][blocks]: p . (mask N p) per block
+};
+// Blocks per detector of the fused path for covariance C, or 0 when C takes
+// another overlap-save kernel (then the solver runs its separate passes).
+int64_t noise_gap_blocks(const furax_noise *C);
+// q = N p_next with p_next formed from p_prev (see GapFuse).
+furax_status noise_run_gap(const furax_noise *C, const double *p_prev, double *q,
+                           const void *spec, const GapFuse &g, hipStream_t s);
+
 template <typename T>
 furax_status gap_fill_impl(const furax_noise *C, const uint8_t *gaps, const T *d, const T *nr,
                            T *out, const furax_gapfill_opts *opt, furax_gapfill_info *info,

@@ -14,7 +14,15 @@
 // no final product is needed.  Vectors are FP64 in both TOD precisions.
 // Per-detector sums are taken in two fixed-order stages (chunk partials, then
 // one pass over them), so results do not depend on scheduling.
+//
+// Where N is applied by the 32768-sample FP64 overlap-save kernel (bands
+// above 2560 lags), that kernel also forms the new direction as it loads its
+// input and adds each block's share of p . (mask q) after its output
+// (noise_run_gap): an iteration is then the transform and one vector pass
+// (the step) instead of the transform and three.
 #include <algorithm>
+#include <cstddef>
+#include <utility>
 
 #include "common.h"
 #include "reduce.h"
@@ -85,6 +93,7 @@ __global__ void __launch_bounds__(kBlock) k_gap_pq(const double *__restrict__ p,
 // 2: beta = rz_new / rz, rr.  With rel_out, the largest |r_k| / |b_k| goes there
 // (0 for a detector with b_k = 0, which then takes alpha = 0 throughout).
 __global__ void __launch_bounds__(kBlock) k_gap_scalars(int64_t n_det, int32_t stage,
+                                                        int64_t n_part,
                                                         const double *__restrict__ part,
                                                         GapDet *__restrict__ det,
                                                         double *__restrict__ rel_out) {
@@ -104,8 +113,10 @@ __global__ void __launch_bounds__(kBlock) k_gap_scalars(int64_t n_det, int32_t s
       g.bb = m > 0.0 ? b : 0.0;
       g.rr = g.bb;
     } else if (stage == 1) {
+      // n_part partials per detector: the vector pass's chunks, or the fused
+      // transform's blocks
       double a = 0.0;
-      for (int c = 0; c < kGapChunks; ++c) a += part[k * kGapChunks + c];
+      for (int64_t c = 0; c < n_part; ++c) a += part[k * n_part + c];
       g.pq = a;
       const bool ok = a > 0.0 && g.rz > 0.0 && (g.rz / a) - (g.rz / a) == 0.0;
       g.alpha = ok ? g.rz / a : 0.0;
@@ -213,19 +224,23 @@ furax_status gap_fill_impl(const furax_noise *C, const uint8_t *gaps, const T *d
     FX_HIP(hipGetLastError());
     return FURAX_OK;
   }
-  // y, r, p, q [S] FP64; spectrum; per-detector scalars and chunk partials
+  // y, r, p, q [S] FP64 (and with the fused transform a second direction
+  // buffer); spectrum; per-detector scalars and chunk / block partials
+  const int64_t nblk = noise_gap_blocks(C);
+  const int nvec = nblk > 0 ? 5 : 4;
   const size_t vb = sizeof(double) * (size_t)S;
   const size_t spec_b = noise_workspace_bytes<double>(C);
-  const size_t part_b = sizeof(double) * 3 * kGapChunks * nd;
+  const size_t part_b = sizeof(double) * std::max<int64_t>(3 * kGapChunks, nblk) * nd;
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   DevBuf mem;
-  FX_TRY(mem.alloc(4 * al(vb) + al(spec_b) + al(part_b) + al(sizeof(GapDet) * nd) + 256, s));
+  FX_TRY(mem.alloc(nvec * al(vb) + al(spec_b) + al(part_b) + al(sizeof(GapDet) * nd) + 256, s));
   char *base = static_cast<char *>(mem.ptr);
   double *y = reinterpret_cast<double *>(base);
   double *r = reinterpret_cast<double *>(base + al(vb));
   double *p = reinterpret_cast<double *>(base + 2 * al(vb));
   double *q = reinterpret_cast<double *>(base + 3 * al(vb));
-  char *spec = base + 4 * al(vb);
+  double *p_alt = nblk > 0 ? reinterpret_cast<double *>(base + 4 * al(vb)) : nullptr;
+  char *spec = base + nvec * al(vb);
   double *part = reinterpret_cast<double *>(spec + al(spec_b));
   GapDet *det = reinterpret_cast<GapDet *>(reinterpret_cast<char *>(part) + al(part_b));
   double *rel = reinterpret_cast<double *>(reinterpret_cast<char *>(det) + al(sizeof(GapDet) * nd));
@@ -234,19 +249,40 @@ furax_status gap_fill_impl(const furax_noise *C, const uint8_t *gaps, const T *d
                      s, nd, C->toeplitz, C->toeplitz_stride, det);
   const dim3 grid(kGapChunks, (unsigned)nd);
   hipLaunchKernelGGL(k_gap_init<T>, grid, dim3(kBlock), 0, s, d, nr, gaps, n, det, y, r, p, part);
-  hipLaunchKernelGGL(k_gap_scalars, dim3(1), dim3(kBlock), 0, s, nd, 0, part, det, rel);
+  hipLaunchKernelGGL(k_gap_scalars, dim3(1), dim3(kBlock), 0, s, nd, 0, (int64_t)kGapChunks, part,
+                     det, rel);
   FX_HIP(hipGetLastError());
   double worst = 0.0;
   FX_HIP(hipMemcpyAsync(&worst, rel, sizeof(double), hipMemcpyDeviceToHost, s));
   FX_HIP(hipStreamSynchronize(s));
   int32_t it = 0;
+  // per-detector beta and 1 / c0 inside the GapDet records, read with a stride
+  const double *det_words = reinterpret_cast<const double *>(det);
+  constexpr int64_t kDetStride = sizeof(GapDet) / sizeof(double);
+  static_assert(sizeof(GapDet) % sizeof(double) == 0, "GapDet holds doubles only");
+  double *p_cur = p;
   while (it < opt->max_iter && worst > opt->rtol) {
-    FX_TRY(noise_run<double>(C, p, q, spec, s));
-    hipLaunchKernelGGL(k_gap_pq, grid, dim3(kBlock), 0, s, p, q, gaps, n, part);
-    hipLaunchKernelGGL(k_gap_scalars, dim3(1), dim3(kBlock), 0, s, nd, 1, part, det, rel);
-    hipLaunchKernelGGL(k_gap_step, grid, dim3(kBlock), 0, s, y, r, q, gaps, n, det, part);
-    hipLaunchKernelGGL(k_gap_scalars, dim3(1), dim3(kBlock), 0, s, nd, 2, part, det, rel);
-    hipLaunchKernelGGL(k_gap_dir, grid, dim3(kBlock), 0, s, p, r, n, det);
+    if (nblk > 0) {
+      // p_alt = z + beta p_cur (beta = 0 at the first iteration: p_alt = z),
+      // q = N p_alt and the blocks' partials of p_alt . (mask q), in one kernel
+      const GapFuse g{r, p_alt, gaps, det_words + offsetof(GapDet, inv_c0) / sizeof(double),
+                      det_words + offsetof(GapDet, beta) / sizeof(double), kDetStride, part};
+      FX_TRY(noise_run_gap(C, p_cur, q, spec, g, s));
+      std::swap(p_cur, p_alt);
+      hipLaunchKernelGGL(k_gap_scalars, dim3(1), dim3(kBlock), 0, s, nd, 1, nblk, part, det, rel);
+      hipLaunchKernelGGL(k_gap_step, grid, dim3(kBlock), 0, s, y, r, q, gaps, n, det, part);
+      hipLaunchKernelGGL(k_gap_scalars, dim3(1), dim3(kBlock), 0, s, nd, 2, (int64_t)kGapChunks,
+                         part, det, rel);
+    } else {
+      FX_TRY(noise_run<double>(C, p, q, spec, s));
+      hipLaunchKernelGGL(k_gap_pq, grid, dim3(kBlock), 0, s, p, q, gaps, n, part);
+      hipLaunchKernelGGL(k_gap_scalars, dim3(1), dim3(kBlock), 0, s, nd, 1, (int64_t)kGapChunks,
+                         part, det, rel);
+      hipLaunchKernelGGL(k_gap_step, grid, dim3(kBlock), 0, s, y, r, q, gaps, n, det, part);
+      hipLaunchKernelGGL(k_gap_scalars, dim3(1), dim3(kBlock), 0, s, nd, 2, (int64_t)kGapChunks,
+                         part, det, rel);
+      hipLaunchKernelGGL(k_gap_dir, grid, dim3(kBlock), 0, s, p, r, n, det);
+    }
     FX_HIP(hipGetLastError());
     ++it;
     FX_HIP(hipMemcpyAsync(&worst, rel, sizeof(double), hipMemcpyDeviceToHost, s));

@@ -755,10 +755,14 @@ k_os_r32(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, in
 // exchanges move a whole radix-32 butterfly per thread in one round (its 32
 // outputs fall in one half, chosen per wave).
 // ---------------------------------------------------------------------------
-template <typename T, bool PAIR>
+// With GAP (FP64 only) the kernel also carries the gap-fill CG's direction
+// update and its p . (mask N p) partial (GapFuse); in is then p_prev.
+template <typename T, bool PAIR, bool GAP = false>
 __global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 2)
 k_os_r32x(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, int64_t nblk,
-          const T *__restrict__ spec, int64_t spec_stride, const C2<double> *__restrict__ tw) {
+          const T *__restrict__ spec, int64_t spec_stride, const C2<double> *__restrict__ tw,
+          GapFuse gf = GapFuse{}) {
+  static_assert(!GAP || sizeof(T) == 8, "the gap-fill fusion is FP64");
   constexpr int M = 16384, L = 2 * M, HALF = M / 2, NT = 512;
   constexpr int HP = HALF + HALF / 16;   // padded half: pad16(e - HALF) = pad16(e) - HP
   // FP32 (VALU-bound) takes each exchange's LDS slots as one per-thread base
@@ -776,10 +780,10 @@ k_os_r32x(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, i
 
   // ---- forward pass 0 (radix 32, span 1): inputs z[t + 512 r] from HBM
   {
-    const int tid = pinned_tid<T>(tid0);
+    const int tid = GAP ? fresh_tid(tid0) : pinned_tid<T>(tid0);
     const __amdgpu_buffer_rsrc_t xr = row_buffer(const_cast<T *>(in) + det * n, n);
 #pragma unroll
-    for (int r = 0; r < 32; ++r) {
+    for (int r = 0; r < (GAP ? 0 : 32); ++r) {
       const int32_t g = s0 + 2 * (tid + NT * r);   // even
       if constexpr (PAIR) {
         // n even: a pair is wholly before the row, inside it or past its end
@@ -787,6 +791,42 @@ k_os_r32x(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, i
       } else {
         v[r].x = buf_load<T>(xr, g >= 0 ? (uint32_t)g * (uint32_t)sizeof(T) : kDropOffset);
         v[r].y = buf_load<T>(xr, g + 1 >= 0 ? (uint32_t)(g + 1) * (uint32_t)sizeof(T) : kDropOffset);
+      }
+    }
+    if constexpr (GAP) {
+      // p = r / c0 + beta p_prev, element by element (p_prev and the residual
+      // loaded together, four elements at a time: the block's 32 values
+      // already take half the registers); the block's valid outputs keep p
+      // in p_next for the solver's next step
+      const __amdgpu_buffer_rsrc_t rr = row_buffer(const_cast<double *>(gf.r) + det * n, n);
+      const __amdgpu_buffer_rsrc_t pn = row_buffer(gf.p_next + det * n, n);
+      const double ic = gf.inv_c0[det * gf.stride], be = gf.beta[det * gf.stride];
+      const int hi = lo + V;
+#pragma unroll
+      for (int r = 0; r < 32; ++r) {
+        const int32_t g = s0 + 2 * (tid + NT * r);
+        const int e = 2 * (tid + NT * r);
+        C2<T> rv, pv;
+        if constexpr (PAIR) {
+          rv = buf_load2(rr, g >= 0 ? (uint32_t)g * (uint32_t)sizeof(T) : kDropOffset, T());
+          pv = buf_load2(xr, g >= 0 ? (uint32_t)g * (uint32_t)sizeof(T) : kDropOffset, T());
+        } else {
+          rv.x = buf_load<T>(rr, g >= 0 ? (uint32_t)g * (uint32_t)sizeof(T) : kDropOffset);
+          rv.y = buf_load<T>(rr, g + 1 >= 0 ? (uint32_t)(g + 1) * (uint32_t)sizeof(T) : kDropOffset);
+          pv.x = buf_load<T>(xr, g >= 0 ? (uint32_t)g * (uint32_t)sizeof(T) : kDropOffset);
+          pv.y = buf_load<T>(xr, g + 1 >= 0 ? (uint32_t)(g + 1) * (uint32_t)sizeof(T) : kDropOffset);
+        }
+        v[r] = C2<T>{rv.x * ic + be * pv.x, rv.y * ic + be * pv.y};
+        if constexpr (PAIR) {
+          buf_store2(pn, e >= lo && e < hi ? (uint32_t)(s0 + e) * (uint32_t)sizeof(T) : kDropOffset,
+                     v[r]);
+        } else {
+          buf_store(pn, e >= lo && e < hi ? (uint32_t)(s0 + e) * (uint32_t)sizeof(T) : kDropOffset,
+                    v[r].x);
+          buf_store(pn, e + 1 >= lo && e + 1 < hi ? (uint32_t)(s0 + e + 1) * (uint32_t)sizeof(T)
+                                                  : kDropOffset, v[r].y);
+        }
+        if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
       }
     }
     dft32<T, false>(v);
@@ -941,6 +981,7 @@ k_os_r32x(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, i
     dft32<T, true>(v);
     const __amdgpu_buffer_rsrc_t zr = row_buffer(out + det * n, n);
     const int hi = lo + V;
+    double acc = 0.0;   // GAP: this thread's share of p . (mask N p)
 #pragma unroll
     for (int r = 0; r < 32; ++r) {
       const C2<T> w = v[p32(r)];
@@ -951,6 +992,31 @@ k_os_r32x(const T *__restrict__ in, T *__restrict__ out, int64_t n, int32_t b, i
         buf_store(zr, e >= lo && e < hi ? (uint32_t)(s0 + e) * (uint32_t)sizeof(T) : kDropOffset, w.x);
         buf_store(zr, e + 1 >= lo && e + 1 < hi ? (uint32_t)(s0 + e + 1) * (uint32_t)sizeof(T)
                                                 : kDropOffset, w.y);
+      }
+      if constexpr (GAP) {
+        // the pair (s0 + e, s0 + e + 1) is this block's output: p there is
+        // what this thread wrote in the first pass
+        const int64_t i0 = (int64_t)s0 + e;
+        if (e >= lo && e < hi && i0 < n) {
+          const int64_t o = det * n + i0;
+          const bool two = i0 + 1 < n;
+          const double p0 = gf.p_next[o], p1 = two ? gf.p_next[o + 1] : 0.0;
+          const bool v0 = gf.gaps[o] == 0, v1 = two && gf.gaps[o + 1] == 0;
+          acc += (v0 ? p0 * w.x : 0.0) + (v1 ? p1 * w.y : 0.0);
+        }
+        if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    if constexpr (GAP) {
+      __shared__ double wsum[NT / 64];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) acc += __shfl_down(acc, off, 64);
+      if ((tid0 & 63) == 0) wsum[tid0 >> 6] = acc;
+      __syncthreads();
+      if (tid0 == 0) {
+        double t = 0.0;
+        for (int w = 0; w < NT / 64; ++w) t += wsum[w];   // fixed order
+        gf.partial[det * nblk + blk] = t;
       }
     }
   }
@@ -1531,5 +1597,34 @@ template furax_status launch_noise<float>(const furax_noise *, const float *, fl
                                           size_t, hipStream_t);
 template furax_status launch_noise<double>(const furax_noise *, const double *, double *, void *,
                                            size_t, hipStream_t);
+
+int64_t noise_gap_blocks(const furax_noise *C) {
+  constexpr int M = 16384;
+  if (C->kind != 1 || C->n_samp == 0) return 0;
+  if (os_half_length<double>(C) != M || !os_reg_fits<double>(C->n_samp, M)) return 0;
+  const int64_t V = 2 * M - 2 * (int64_t)os_pair_lo((int)C->bandwidth);
+  return (C->n_samp + V - 1) / V;
+}
+
+furax_status noise_run_gap(const furax_noise *C, const double *p_prev, double *q,
+                           const void *spec, const GapFuse &g, hipStream_t s) {
+  constexpr int M = 16384;
+  const int64_t nblk = noise_gap_blocks(C);
+  if (nblk == 0) return set_error(FURAX_EUNSUPPORTED, "no fused gap-fill kernel for this band");
+  TwTables tw;
+  FX_TRY(get_twiddles(2 * M, s, tw));
+  const int b = (int)C->bandwidth;
+  const int64_t ntask = C->n_det * nblk;
+  const int64_t spec_stride = C->toeplitz_stride ? spec_block(M) : 0;
+  const double *sp = static_cast<const double *>(spec);
+  if (C->n_samp % 2 == 0)
+    hipLaunchKernelGGL((k_os_r32x<double, true, true>), dim3((unsigned)ntask), dim3(512), 0, s,
+                       p_prev, q, C->n_samp, b, nblk, sp, spec_stride, tw.tw64, g);
+  else
+    hipLaunchKernelGGL((k_os_r32x<double, false, true>), dim3((unsigned)ntask), dim3(512), 0, s,
+                       p_prev, q, C->n_samp, b, nblk, sp, spec_stride, tw.tw64, g);
+  FX_HIP(hipGetLastError());
+  return FURAX_OK;
+}
 
 }  // namespace fx
