@@ -498,6 +498,7 @@ template <int KIND, int NR>
 struct SpLds;
 template <int NR>
 struct SpLds<0, NR> {
+  uint8_t run_start[kSpThreads / 64][64];   // per wave: a run starts at this slot of the block
   double acc[3][kSpPix];
   union {
     double two_alpha[kHwpTable];
@@ -507,6 +508,7 @@ struct SpLds<0, NR> {
 };
 template <int NR>
 struct SpLds<1, NR> {
+  uint8_t run_start[kSpThreads / 64][64];
   double acc[6][kSpPix];
   int32_t hits[kSpPix];
   union {
@@ -612,13 +614,18 @@ k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_
         // starts of runs rb+1 .. rb+64 relative to the block (>= 1: rb holds jb)
         const int32_t m = rb + 1 + lane;
         const int32_t st = m < ch.nr ? L.run.pre[m] - jb : 65;
-        // this lane's run: rb + (number of those starts <= lane), by a binary
-        // search over the lanes' (increasing) start values
-        int32_t pos = 0;
-#pragma unroll
-        for (int step = 32; step >= 1; step >>= 1)
-          if (__shfl(st, pos + step - 1, 64) <= lane) pos += step;
-        run[b] = rb + pos;
+        // this lane's run: rb + (number of those starts <= lane).  The lanes
+        // mark the block slots where a run starts in the wave's row of LDS
+        // flags, and one ballot of the flags gives every lane its count.  A
+        // wave's LDS accesses complete in issue order; the wave-scope fences
+        // keep the compiler from reordering or merging them.
+        uint8_t *fl = L.run_start[wave];
+        fl[lane] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (st < 64) fl[st] = 1;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const uint64_t starts = __ballot(fl[lane] != 0);
+        run[b] = rb + __popcll(starts & ((2ull << lane) - 1ull));
         rb += __popcll(__ballot(st <= 64));
         const int32_t jj = min(j, ch.w - 1);
         const int32_t r = min(run[b], ch.nr - 1);
