@@ -262,3 +262,27 @@ def test_normal_apply_with_many_chunk_groups_per_superpixel(fx, dtype):
     ref = omm.normal_apply(prob, pix, c, s, x)
     assert rel_err(got, ref) <= (1e-12 if dtype == "f64" else 2e-5)
 
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ns", [40000, 40001])
+def test_normal_apply_long_band_with_invalid_pointing(fx, dtype, ns):
+    """Above 3072 lags (2560 in FP64) N^-1 takes the transform of 32768-sample
+    blocks; with samples that no superpixel run holds (invalid pointing) and
+    on even and odd stream lengths (paired and single-value row accesses),
+    A x must equal the oracle's."""
+    nside, nd, b = 32, 3, 3500
+    w, h, t = case(nside, nd, ns, dtype=dtype, seed=5)
+    t["theta"][1, 100:150] = float("nan")
+    h["theta"][1, 100:150] = np.nan
+    P = to_pointing(nside, t)
+    lags = synth.toeplitz_lags(w, b)
+    N = fx.Noise("band", nd, ns, lags=torch.from_numpy(lags).to(dev()))
+    prob = omm.Problem(nside, h["theta"], h["phi"], h["psi"], "band", lags=lags,
+                       gain=h["gain"], dpsi=h["dpsi"], hwp=h["hwp"])
+    pix, c, s = prob.geometry()
+    assert (pix < 0).sum() == 50
+    x = np.random.default_rng(3).standard_normal((3, 12 * nside * nside))
+    got = fx.normal_apply(P, N, torch.from_numpy(x).to(dev())).cpu().numpy()
+    ref = omm.normal_apply(prob, pix, c, s, x)
+    assert rel_err(got, ref) <= (1e-12 if dtype == "f64" else 2e-5)
