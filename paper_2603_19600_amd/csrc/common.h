@@ -299,7 +299,11 @@ __device__ __forceinline__ void quat_c2s2(const QuatDir &g, double &c2, double &
   c2 = 1.0;
   s2 = 0.0;
   if (r2 > 0.0) {
-    const double inv = 1.0 / r2;
+    // 1 / r2 from the hardware reciprocal and two Newton steps (within an
+    // ulp or two; the correctly rounded quotient is not needed here)
+    double inv = __builtin_amdgcn_rcp(r2);
+    inv = fma(inv, fma(-r2, inv, 1.0), inv);
+    inv = fma(inv, fma(-r2, inv, 1.0), inv);
     c2 = (nn - ww) * inv;
     s2 = (2.0 * (g.west * g.north)) * inv;
   }

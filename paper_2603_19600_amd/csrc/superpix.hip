@@ -366,10 +366,7 @@ furax_status sp_build_runs(SpPlan &sp, const PtArgs<T> &a, const int32_t *plane,
   // groups: each superpixel's chunks dealt into ceil(n / kChunksPerGroup)
   // groups of near-equal size, so one workgroup sums several chunks in LDS
   // and writes one partial for them
-  // (quaternion pointing keeps one chunk per workgroup: its accumulation is
-  // register-bound to one workgroup per CU, which would idle at the barrier
-  // between chunks)
-  const int64_t per_group = a.qb ? 1 : kChunksPerGroup;
+  const int64_t per_group = kChunksPerGroup;
   std::vector<int32_t> grp, first_grp(sp.n_sp + 1);
   for (int64_t p = 0; p < sp.n_sp; ++p) {
     first_grp[p] = (int32_t)grp.size();
@@ -566,9 +563,8 @@ k_sp_accum(PtArgs<T> a, const T *__restrict__ tod, const double *__restrict__ w_
       L.two_alpha[u] = 2.0 * ((2.0 * kPi) * frac + a.hwp_phase0);
     }
   }
-  // the group's chunks in turn, summed into the same LDS accumulators (with
-  // quaternion pointing a group is one chunk, and the loop compiles away)
-  const int32_t c_lo = groups[blockIdx.x], c_hi = QUAT ? c_lo + 1 : groups[blockIdx.x + 1];
+  // the group's chunks in turn, summed into the same LDS accumulators
+  const int32_t c_lo = groups[blockIdx.x], c_hi = groups[blockIdx.x + 1];
   for (int32_t ci = c_lo; ci < c_hi; ++ci) {
     const SpChunk ch = chunks[ci];
     if (ci > c_lo) __syncthreads();   // every wave is done with the previous run table
