@@ -117,41 +117,45 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(PtArgs<T> a, const MT *
       __syncthreads();
     }
   }
-  for (int32_t s0 = threadIdx.x; s0 < nsamp; s0 += kBatch * kApplyThreads) {
-    Slot sl[kBatch];
-    int32_t px[kBatch], tag[kBatch];
-    T c[kBatch], s[kBatch];
+  // quaternion attitudes take more registers per sample in flight: two
+  // samples per thread there (four waves per SIMD instead of three) measured
+  // faster; the FP64 angle planes keep four (three waves)
+  constexpr int KB = QUAT ? 2 : kBatch;
+  for (int32_t s0 = threadIdx.x; s0 < nsamp; s0 += KB * kApplyThreads) {
+    Slot sl[KB];
+    int32_t px[KB], tag[KB];
+    T c[KB], s[KB];
     if constexpr (QUAT) {
-      Quat qb[kBatch];
+      Quat qb[KB];
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
+      for (int b = 0; b < KB; ++b) {
         sl[b] = slot_of(tl, d0, t0, s0 + b * kApplyThreads, a.n_det, a.n_samp, tc.det);
         qb[b] = load_quat(a.qb, t0 + sl[b].il < a.n_samp ? t0 + sl[b].il : 0);
       }
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b)
+      for (int b = 0; b < KB; ++b)
         quat_slot(a, tc, turn4a, sl[b], quat_dir(qmul(qb[b], tq[sl[b].kl])), px[b], c[b], s[b]);
     } else {
-      T th[kBatch], ph[kBatch], ps[kBatch];
+      T th[KB], ph[KB], ps[KB];
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
+      for (int b = 0; b < KB; ++b) {
         sl[b] = slot_of(tl, d0, t0, s0 + b * kApplyThreads, a.n_det, a.n_samp, tc.det);
         th[b] = ld_stream(a.theta + sl[b].off);
         ph[b] = ld_stream(a.phi + sl[b].off);
         ps[b] = ld_stream(a.psi + sl[b].off);
       }
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
+      for (int b = 0; b < KB; ++b) {
         px[b] = pixel_of(a, th[b], ph[b]);
         pol_weights(a, tc, sl[b], ps[b], c[b], s[b]);
       }
     }
-    MT I[kBatch], Q[kBatch], U[kBatch];
+    MT I[KB], Q[KB], U[KB];
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b)
+    for (int b = 0; b < KB; ++b)
       load_iqu<IL>(map, map_cs, px[b] >= 0 ? px[b] : 0, I[b], Q[b], U[b], tag[b]);
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b) {
+    for (int b = 0; b < KB; ++b) {
       if (!sl[b].in) continue;
       const T y = (T)I[b] + c[b] * (T)Q[b] + s[b] * (T)U[b];
       st_stream(tod + sl[b].off, px[b] >= 0 ? (T)tc.gain[sl[b].kl] * y : (T)0);
