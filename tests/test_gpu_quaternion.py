@@ -246,3 +246,46 @@ def test_full_quaternion_pcg_f32_within_1e6_of_f64(fx, full):
     print(f"quaternion full size: FP32 map vs FP64 map {err:.3e}; iterations "
           f"{i32.iters} / {i64.iters}")
     assert err <= 1e-6
+
+
+def _axis_quat(axis, ang):
+    """Rotation by ang about coordinate axis 0, 1 or 2, as (w, x, y, z) quaternions."""
+    ang = np.asarray(ang, dtype=np.float64)
+    q = np.zeros(ang.shape + (4,))
+    q[..., 0] = np.cos(0.5 * ang)
+    q[..., 1 + axis] = np.sin(0.5 * ang)
+    return q
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-5)])
+def test_quaternion_normal_operator_with_many_chunk_groups(fx, dtype, tol):
+    """Quaternion pointing on a raster over a ~5 degree patch at nside 1024: each
+    superpixel holds dozens of chunks, which the superpixel P^T takes in groups
+    (one partial per group); A x must still equal the oracle's."""
+    nside, nd, ns, b = 1024, 48, 150_000, 33
+    t = np.arange(ns, dtype=np.float64)
+    th = 1.1 + np.deg2rad(2.5) * np.sin(2 * np.pi * t / 5003.0)
+    ph = 2.3 + np.deg2rad(5.0) * ((t * 0.0113) % 1.0)
+    roll = 0.37 * t
+    # boresight R = Rz(phi) Ry(theta) Rz(roll): line of sight at (theta, phi)
+    qb = oq.quat_mul(oq.quat_mul(_axis_quat(2, ph), _axis_quat(1, th)), _axis_quat(2, roll))
+    rng = np.random.default_rng(5)
+    qd = oq.quat_mul(_axis_quat(0, np.deg2rad(rng.uniform(-0.3, 0.3, nd))),
+                     _axis_quat(1, np.deg2rad(rng.uniform(-0.3, 0.3, nd))))
+    w = synth.WORKLOADS[2].with_(nside=nside, n_det=nd, n_samp=ns)
+    lags = synth.toeplitz_lags(w, b)
+    hwp = (w.hwp_num, w.hwp_den, 0.3)
+    prob = omm.Problem(nside, None, None, None, "band", lags=lags, hwp=hwp,
+                       bore_quat=qb, det_quat=qd)
+    pix, c, s = prob.geometry()
+    hit = np.unique(pix[pix >= 0])
+    assert hit.size < 20_000 and pix.min() >= 0
+    D = dev()
+    P = fx.QuatPointing(nside, torch.from_numpy(qb).to(D), torch.from_numpy(qd).to(D), dtype,
+                        None, None, hwp)
+    N = fx.Noise("band", nd, ns, lags=torch.from_numpy(lags).to(D))
+    x = np.zeros((3, 12 * nside * nside))
+    x[:, hit] = np.random.default_rng(11).standard_normal((3, hit.size))
+    got = fx.normal_apply(P, N, torch.from_numpy(x).to(D)).cpu().numpy()
+    ref = omm.normal_apply(prob, pix, c, s, x)
+    assert rel_err(got, ref) <= tol
