@@ -727,8 +727,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the map-making path is built and measured on a single "
-              "MI355X (multi-GPU sharding by detector is a design note, not part of this build).",
+        print("bench.py measures one GPU: the map-making path runs on a single MI355X "
+              "(sharding the detectors over several GPUs is described, not implemented).",
               file=sys.stderr)
         sys.exit(2)
 
